@@ -1,0 +1,249 @@
+/*
+ * pt.h - C ABI of the MI355X (gfx950) predicate-transfer library, libpt_hip.so.
+ *
+ * Predicate transfer (Yang, Zhao, Yu, Koutris, "Predicate Transfer: Efficient
+ * Pre-Filtering on Multi-Join Queries", CIDR 2024) pre-filters every table of
+ * a multi-join query before any join runs:
+ *   - Sec. 3.1: the query is a join graph, one vertex per table and one edge
+ *     per equi-join; phase 1 transfers filters along it, phase 2 joins.
+ *   - Sec. 3.2: local predicates become filters; at each table a single scan
+ *     of its join-key columns probes every incoming filter and inserts the
+ *     surviving rows' keys into every outgoing filter ("filter
+ *     transformation"); edges point from the smaller table to the bigger one
+ *     ("predicate transfer graph"); a forward pass visits tables in
+ *     topological order, then a backward pass repeats it on the reversed
+ *     edges ("transfer schedule").
+ *   - Sec. 2.1: the filters are Bloom filters (no false negatives).
+ *
+ * Every table ends with a selection bitmap; the join phase reads the rows
+ * whose bits are set.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.   Pointers named d_* and every column's data are device pointers
+ *           (HIP device memory on the current device). Everything else is
+ *           host memory, read during the call only. The caller allocates and
+ *           owns every buffer and keeps device buffers alive until the work
+ *           queued on `stream` has finished. The library allocates no device
+ *           memory; scratch space is the caller's workspace argument.
+ * Streams.  Work is queued on `stream` (a hipStream_t; NULL is the null
+ *           stream) and the call returns without waiting for it.
+ * Errors.   Arguments are checked on the host first. A rejected call returns
+ *           PT_EINVAL and queues nothing. A failed launch returns
+ *           PT_EDEVICE. pt_last_error() gives the calling thread's message
+ *           for its last failed call. Nothing is thrown across this ABI.
+ * Rows.     A table has fewer than 2^32 rows. Row ids are uint32.
+ * Keys.     Columns hold int32 or int64 values. A key is compared as a
+ *           signed 64-bit integer, so an int32 column may join an int64 one.
+ * Bitmaps.  One bit per row, in uint64 words: row r is bit (r mod 64) of
+ *           word r / 64, ceil(n_rows / 64) words. Bits past the last row are
+ *           zero on output and must be zero on input.
+ *
+ * Filter specification (the paper fixes no hash, layout or size; the same
+ * rules are implemented independently by the CPU oracle in the tests)
+ * -----------------------------------------------------------------------
+ *   x   = the key as int64, reinterpreted as uint64
+ *   P   = x * 0x9E3779B97F4A7C15 mod 2^64        (multiply-shift hashing)
+ *   H1  = P >> 32
+ *   t   = (P mod 2^32) xor H1;  t = t xor (t >> 16)
+ *   H2  = t * 0x85EBCA6B mod 2^32
+ *   B   = block_bits (32..1024, a power of two; 512 = one 64-byte line),
+ *         b = log2(B), k = bits per key (1..16)
+ *   nb  = max(1, ceil(n_selected * bits_per_key / B)) blocks, nb < 2^32
+ *   blk = (H1 * nb) >> 32                        (multiply-high reduction)
+ *   g1  = H2 >> (32 - b);  g2 = ((H2 >> (32 - 2b)) mod B) | 1
+ *   bit i (i < k) of the key: pos_i = (g1 + i * g2) mod B in block blk,
+ *         i.e. bit (pos_i mod 32) of uint32 word blk * B/32 + pos_i / 32
+ *   A key is inserted by setting its k bits and passes when all k are set.
+ */
+#ifndef PT_H
+#define PT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pt_status {
+  PT_OK = 0,
+  PT_EINVAL = 1,       /* an argument was rejected; nothing was queued */
+  PT_ENOMEM = 2,       /* a caller-provided workspace is too small */
+  PT_EDEVICE = 3,      /* a HIP call or kernel launch failed */
+  PT_EUNSUPPORTED = 4  /* a valid request this build does not implement */
+} pt_status;
+
+typedef enum pt_dtype { PT_I32 = 0, PT_I64 = 1 } pt_dtype;
+
+/* A hipStream_t. */
+typedef void *pt_stream;
+
+/* One column: n_rows values of `dtype` at device address `data` (may be NULL
+ * when the table has no rows). */
+typedef struct pt_column {
+  const void *data;
+  uint32_t dtype;    /* pt_dtype */
+  uint32_t reserved; /* 0 */
+} pt_column;
+
+/* One base table (a vertex of the join graph; the same base table joined
+ * twice appears as two vertices). */
+typedef struct pt_table {
+  uint64_t n_rows;
+  uint32_t n_cols;
+  uint32_t reserved; /* 0 */
+  const pt_column *cols;
+} pt_table;
+
+/* One inner equi-join tables[u].cols[u_col] = tables[v].cols[v_col]
+ * (Sec. 3.1). A composite key is several edges between the same tables. */
+typedef struct pt_edge {
+  uint32_t u, u_col, v, v_col;
+} pt_edge;
+
+/* The join graph. `orient` is NULL for the paper's rule (Sec. 3.2: each edge
+ * points from the table with fewer rows to the one with more; equal sizes
+ * point from the lower table index), or one value per edge: +1 for u -> v,
+ * -1 for v -> u. The oriented graph must be acyclic. */
+typedef struct pt_graph {
+  uint32_t n_tables;
+  uint32_t n_edges;
+  const pt_edge *edges;
+  const int8_t *orient;
+} pt_graph;
+
+typedef enum pt_cmp {
+  PT_LT = 0, PT_LE = 1, PT_GT = 2, PT_GE = 3, PT_EQ = 4, PT_NE = 5,
+  PT_BETWEEN = 6 /* lo <= value <= hi */
+} pt_cmp;
+
+/* A local predicate "tables[table].cols[col] op lo" (Sec. 3.4: filters over
+ * base tables). The predicates of one table form a conjunction; values and
+ * bounds compare as int64. */
+typedef struct pt_pred {
+  uint32_t table, col;
+  uint32_t op;       /* pt_cmp */
+  uint32_t reserved; /* 0 */
+  int64_t lo, hi;
+} pt_pred;
+
+/* Filter parameters, one set for every filter of a call. */
+typedef struct pt_params {
+  uint32_t block_bits;   /* B: 32, 64, 128, 256, 512 or 1024 */
+  uint32_t k;            /* 1..16 */
+  uint32_t bits_per_key; /* 1..64 */
+  uint32_t flags;        /* 0 */
+} pt_params;
+
+/* A Bloom filter in device memory. `words` holds cap_words uint32 words; the
+ * filter in use is its first nb * B/32 words, where nb is the uint64 at
+ * device address `d_nb` (written by pt_bloom_build). */
+typedef struct pt_bloom {
+  uint32_t *words;
+  uint64_t cap_words;
+  uint64_t *d_nb;
+  pt_params params;
+} pt_bloom;
+
+/* Per-kernel timing record (see pt_profile_enable). */
+typedef struct pt_kernel_time {
+  char name[24];   /* "local", "probe", "size", "build", "count", "compact" */
+  uint32_t table;  /* table index inside pt_transfer, else 0 */
+  uint32_t pass;   /* 0 local, 1 forward, 2 backward; 0 outside pt_transfer */
+  uint64_t rows;   /* rows the kernel scanned */
+  uint64_t bytes;  /* algorithmic bytes: key and bitmap traffic the step must move */
+  float ms;        /* duration between events recorded around the launch */
+  uint32_t reserved;
+} pt_kernel_time;
+
+/* Library version string. */
+const char *pt_version(void);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *pt_last_error(void);
+
+/* Local filter (Sec. 3.2, inherent filters applied during the scan; Sec.
+ * 3.4). Writes into d_bitmap the rows of `table` that satisfy every one of
+ * the n_preds predicates (their `table` field is ignored; all rows if
+ * n_preds == 0), and if d_count is not NULL their number into *d_count.
+ * d_bitmap: ceil(n_rows/64) words, fully overwritten. */
+pt_status pt_local_filter(const pt_table *table, const pt_pred *preds, uint32_t n_preds,
+                          uint64_t *d_bitmap, uint64_t *d_count, pt_stream stream);
+
+/* Words a filter needs to hold up to max_keys keys (its cap_words). */
+pt_status pt_bloom_capacity(uint64_t max_keys, const pt_params *params, uint64_t *out_words);
+
+/* Bloom build (Sec. 2.1; Sec. 3.2, the outgoing half of the filter
+ * transformation). For each of the n_filters filters, sizes it from the
+ * number of selected rows (nb above), zeroes its nb blocks, writes nb to
+ * *filters[i].d_nb, and inserts keys[i] of every selected row.
+ *   keys[i]    key column of this table for filter i (n_rows values)
+ *   d_bitmap   selected rows; NULL selects all n_rows rows
+ *   d_count    device uint64 holding the number of selected rows (the
+ *              popcount of d_bitmap); required when d_bitmap is not NULL
+ *   filters[i] cap_words must hold a filter over n_rows keys
+ *              (pt_bloom_capacity); all filters share one pt_params value
+ * The filters' words must not overlap each other or the inputs. */
+pt_status pt_bloom_build(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
+                         uint64_t n_rows, const uint64_t *d_bitmap, const uint64_t *d_count,
+                         pt_stream stream);
+
+/* Bloom probe (Sec. 3.2, the incoming half of the filter transformation).
+ * Clears in d_bitmap the bit of every row whose keys[i] fails filters[i],
+ * for every i, in one scan of the table; rows already cleared stay cleared.
+ * If d_count is not NULL, writes the number of rows left. The order in
+ * which the filters are tested does not change the result. */
+pt_status pt_bloom_probe(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
+                         uint64_t n_rows, uint64_t *d_bitmap, uint64_t *d_count,
+                         pt_stream stream);
+
+/* Bytes of workspace pt_compact needs for n_rows rows. */
+pt_status pt_compact_workspace_size(uint64_t n_rows, size_t *bytes);
+
+/* Compaction: the ids of the set rows of d_bitmap in ascending order into
+ * d_idx (room for n_rows ids) and their number into *d_count: the
+ * pre-filtered row set handed to the join phase (Sec. 3.3). */
+pt_status pt_compact(const uint64_t *d_bitmap, uint64_t n_rows, uint32_t *d_idx,
+                     uint64_t *d_count, void *d_ws, size_t ws_bytes, pt_stream stream);
+
+/* Bytes of workspace pt_transfer needs for this graph, these tables' row
+ * counts and these parameters (every filter at its largest possible size,
+ * plus counters). */
+pt_status pt_transfer_workspace_size(const pt_graph *graph, const pt_table *tables,
+                                     const pt_params *params, size_t *bytes);
+
+/* The transfer phase (Sec. 3.2): local predicates, orientation, the forward
+ * pass in topological order, then the backward pass on the reversed edges
+ * starting from the forward survivors, with no pruning (every edge carries
+ * one filter in each pass). Every source of a pass builds filters whether or
+ * not it has a predicate. A filter is sized from the builder's row count
+ * after that pass's probes at the builder.
+ *   tables     graph->n_tables tables (at most 64)
+ *   preds      n_preds predicates, each naming its table
+ *   d_ws       workspace of at least pt_transfer_workspace_size bytes,
+ *              256-byte aligned; holds every filter after the call
+ *   d_bitmaps  d_bitmaps[t] receives table t's final bitmap
+ *   d_counts   NULL, or graph->n_tables device uint64: final row counts */
+pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pred *preds,
+                      uint32_t n_preds, const pt_params *params, void *d_ws, size_t ws_bytes,
+                      uint64_t *const *d_bitmaps, uint64_t *d_counts, pt_stream stream);
+
+/* Where pt_transfer left the filter that `edge` carried in `pass` (1 forward,
+ * 2 backward) inside d_ws, and which table built it (*builder). */
+pt_status pt_transfer_filter(const pt_graph *graph, const pt_table *tables,
+                             const pt_params *params, void *d_ws, uint32_t pass, uint32_t edge,
+                             pt_bloom *out, uint32_t *builder);
+
+/* Kernel timing. While enabled on the calling thread, every launch of the
+ * calls above is bracketed by HIP events recorded on the launch's own
+ * stream. pt_profile_read waits for those events, copies up to `max` records
+ * into `out`, sets *n to the number copied and clears the list. */
+pt_status pt_profile_enable(int on);
+pt_status pt_profile_read(pt_kernel_time *out, uint32_t max, uint32_t *n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PT_H */

@@ -1,0 +1,625 @@
+// pt_api.hip - the C ABI (include/pt.h): argument checks, the transfer
+// planner and the launch sequence of the transfer phase.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/pt.h"
+#include "pt_internal.hpp"
+
+namespace pt {
+
+// ------------------------------------------------------------- errors
+
+static thread_local std::string g_error;
+
+static pt_status fail(pt_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return st;
+}
+
+static pt_status check_hip(hipError_t e, const char *what) {
+  if (e == hipSuccess) return PT_OK;
+  return fail(PT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// -------------------------------------------------------- device info
+
+const DeviceInfo &device_info() {
+  static std::mutex mu;
+  static DeviceInfo infos[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  DeviceInfo &di = infos[dev];
+  if (di.device < 0) {
+    int n_cu = 0, lds = 0, lds_optin = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) n_cu = 256;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 65536;
+    if (hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) lds_optin = 0;
+    di.n_cu = n_cu > 0 ? n_cu : 256;
+    di.max_lds_block = std::max(lds, lds_optin);
+    if (di.max_lds_block <= 0) di.max_lds_block = 65536;
+    di.device = dev;
+  }
+  return di;
+}
+
+// ---------------------------------------------------------- profiling
+
+namespace {
+
+struct ProfRecord {
+  pt_kernel_time t;
+  hipEvent_t start, stop;
+};
+
+thread_local bool g_prof_on = false;
+thread_local std::vector<ProfRecord> g_prof;
+thread_local std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events on its stream when profiling is on.
+class Timed {
+ public:
+  Timed(const char *name, uint32_t table, uint32_t pass, uint64_t rows, uint64_t bytes,
+        hipStream_t s)
+      : s_(s) {
+    if (!g_prof_on) return;
+    rec_.t = pt_kernel_time{};
+    std::snprintf(rec_.t.name, sizeof rec_.t.name, "%s", name);
+    rec_.t.table = table;
+    rec_.t.pass = pass;
+    rec_.t.rows = rows;
+    rec_.t.bytes = bytes;
+    rec_.start = take_event();
+    rec_.stop = take_event();
+    if (rec_.start && rec_.stop) {
+      active_ = hipEventRecord(rec_.start, s_) == hipSuccess;
+    }
+  }
+  ~Timed() {
+    if (!active_) return;
+    if (hipEventRecord(rec_.stop, s_) == hipSuccess) g_prof.push_back(rec_);
+  }
+
+ private:
+  hipStream_t s_;
+  ProfRecord rec_{};
+  bool active_ = false;
+};
+
+// ---------------------------------------------------------- validation
+
+constexpr uint64_t kMaxRows = 0xFFFFFFFFull;  // row ids are uint32
+constexpr uint32_t kMaxTables = 64;
+
+pt_status check_params(const pt_params *p) {
+  if (!p) return fail(PT_EINVAL, "params is NULL");
+  const uint32_t B = p->block_bits;
+  if (B < 32 || B > 1024 || (B & (B - 1)) != 0)
+    return fail(PT_EINVAL, "block_bits %u is not a power of two in [32, 1024]", B);
+  if (p->k < 1 || p->k > 16) return fail(PT_EINVAL, "k %u outside [1, 16]", p->k);
+  if (p->bits_per_key < 1 || p->bits_per_key > 64)
+    return fail(PT_EINVAL, "bits_per_key %u outside [1, 64]", p->bits_per_key);
+  if (p->flags != 0) return fail(PT_EINVAL, "params.flags must be 0");
+  return PT_OK;
+}
+
+uint64_t blocks_for(uint64_t n_keys, const pt_params &p) {
+  uint64_t nb = (n_keys * p.bits_per_key + p.block_bits - 1) / p.block_bits;
+  return nb == 0 ? 1 : nb;
+}
+
+uint64_t capacity_words(uint64_t n_keys, const pt_params &p) {
+  return blocks_for(n_keys, p) * (p.block_bits / 32);
+}
+
+pt_status check_column(const pt_column *c, uint64_t n_rows, const char *what) {
+  if (!c) return fail(PT_EINVAL, "%s: column is NULL", what);
+  if (c->dtype != PT_I32 && c->dtype != PT_I64) return fail(PT_EINVAL, "%s: dtype %u", what, c->dtype);
+  if (n_rows > 0 && !c->data) return fail(PT_EINVAL, "%s: data is NULL", what);
+  return PT_OK;
+}
+
+pt_status check_table(const pt_table *t, uint32_t idx) {
+  if (t->n_rows > kMaxRows) return fail(PT_EINVAL, "table %u: %llu rows (limit 2^32 - 1)", idx,
+                                        (unsigned long long)t->n_rows);
+  if (t->n_cols > 0 && !t->cols) return fail(PT_EINVAL, "table %u: cols is NULL", idx);
+  for (uint32_t c = 0; c < t->n_cols; c++) {
+    char what[64];
+    std::snprintf(what, sizeof what, "table %u column %u", idx, c);
+    pt_status st = check_column(&t->cols[c], t->n_rows, what);
+    if (st != PT_OK) return st;
+  }
+  return PT_OK;
+}
+
+pt_status check_filter(const pt_bloom &f, const pt_params &p0, uint64_t n_rows, uint32_t i) {
+  if (!f.words || !f.d_nb) return fail(PT_EINVAL, "filter %u: words or d_nb is NULL", i);
+  pt_status st = check_params(&f.params);
+  if (st != PT_OK) return st;
+  if (std::memcmp(&f.params, &p0, sizeof p0) != 0)
+    return fail(PT_EINVAL, "filter %u: parameters differ from filter 0", i);
+  const uint64_t need = capacity_words(n_rows, f.params);
+  if (need / (f.params.block_bits / 32) > 0xFFFFFFFFull)
+    return fail(PT_EINVAL, "filter %u: %llu blocks exceed 2^32 - 1", i,
+                (unsigned long long)(need / (f.params.block_bits / 32)));
+  if (f.cap_words < need)
+    return fail(PT_EINVAL, "filter %u: cap_words %llu < %llu needed for %llu rows", i,
+                (unsigned long long)f.cap_words, (unsigned long long)need,
+                (unsigned long long)n_rows);
+  return PT_OK;
+}
+
+FilterRef make_ref(const pt_column &keys, const pt_bloom &f) {
+  FilterRef r{};
+  r.keys = keys.data;
+  r.words = f.words;
+  r.nb = f.d_nb;
+  r.cap_words = f.cap_words;
+  r.key64 = keys.dtype == PT_I64;
+  return r;
+}
+
+uint64_t key_bytes(const pt_column &c) { return c.dtype == PT_I64 ? 8 : 4; }
+
+// ------------------------------------------------------------- planner
+
+struct Plan {
+  uint32_t n_t = 0, n_e = 0;
+  std::vector<uint32_t> src, dst;  // forward orientation of every edge
+  std::vector<uint32_t> order;     // forward topological order
+  uint64_t off_counts = 0;         // 3 * n_t uint64: local, forward, backward
+  uint64_t off_nb = 0;             // 2 * n_e uint64: forward, backward filters
+  std::vector<uint64_t> off_filter, cap_words;  // [pass * n_e + e]
+  uint64_t total = 0;
+};
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *params, Plan &pl) {
+  if (!g) return fail(PT_EINVAL, "graph is NULL");
+  pt_status st = check_params(params);
+  if (st != PT_OK) return st;
+  if (g->n_tables > kMaxTables) return fail(PT_EINVAL, "%u tables (limit %u)", g->n_tables, kMaxTables);
+  if (g->n_tables > 0 && !tables) return fail(PT_EINVAL, "tables is NULL");
+  if (g->n_edges > 0 && !g->edges) return fail(PT_EINVAL, "edges is NULL");
+  for (uint32_t t = 0; t < g->n_tables; t++) {
+    st = check_table(&tables[t], t);
+    if (st != PT_OK) return st;
+    const uint64_t nb = blocks_for(tables[t].n_rows, *params);
+    if (nb > 0xFFFFFFFFull) return fail(PT_EINVAL, "table %u: filter of %llu blocks exceeds 2^32 - 1", t,
+                                        (unsigned long long)nb);
+  }
+  pl.n_t = g->n_tables;
+  pl.n_e = g->n_edges;
+  pl.src.assign(pl.n_e, 0);
+  pl.dst.assign(pl.n_e, 0);
+  for (uint32_t e = 0; e < pl.n_e; e++) {
+    const pt_edge &ed = g->edges[e];
+    if (ed.u >= pl.n_t || ed.v >= pl.n_t) return fail(PT_EINVAL, "edge %u: table out of range", e);
+    if (ed.u == ed.v) return fail(PT_EINVAL, "edge %u joins table %u with itself", e, ed.u);
+    if (ed.u_col >= tables[ed.u].n_cols || ed.v_col >= tables[ed.v].n_cols)
+      return fail(PT_EINVAL, "edge %u: column out of range", e);
+    bool u_first;
+    if (g->orient) {
+      if (g->orient[e] != 1 && g->orient[e] != -1)
+        return fail(PT_EINVAL, "edge %u: orientation must be +1 or -1", e);
+      u_first = g->orient[e] == 1;
+    } else {
+      // Sec. 3.2: from the smaller table to the bigger one; ties by index.
+      const uint64_t nu = tables[ed.u].n_rows, nv = tables[ed.v].n_rows;
+      u_first = nu < nv || (nu == nv && ed.u < ed.v);
+    }
+    pl.src[e] = u_first ? ed.u : ed.v;
+    pl.dst[e] = u_first ? ed.v : ed.u;
+  }
+  // Kahn's algorithm; the lowest ready index first.
+  std::vector<uint32_t> indeg(pl.n_t, 0);
+  std::vector<char> done(pl.n_t, 0);
+  for (uint32_t e = 0; e < pl.n_e; e++) indeg[pl.dst[e]]++;
+  pl.order.clear();
+  for (uint32_t i = 0; i < pl.n_t; i++) {
+    uint32_t pick = pl.n_t;
+    for (uint32_t v = 0; v < pl.n_t; v++)
+      if (!done[v] && indeg[v] == 0) {
+        pick = v;
+        break;
+      }
+    if (pick == pl.n_t) return fail(PT_EINVAL, "the oriented join graph has a cycle");
+    done[pick] = 1;
+    pl.order.push_back(pick);
+    for (uint32_t e = 0; e < pl.n_e; e++)
+      if (pl.src[e] == pick) indeg[pl.dst[e]]--;
+  }
+  // Workspace layout.
+  uint64_t off = 256;
+  pl.off_counts = off;
+  off = align256(off + 3ull * pl.n_t * 8);
+  pl.off_nb = off;
+  off = align256(off + 2ull * pl.n_e * 8);
+  pl.off_filter.assign(2ull * pl.n_e, 0);
+  pl.cap_words.assign(2ull * pl.n_e, 0);
+  for (uint32_t pass = 0; pass < 2; pass++) {
+    for (uint32_t e = 0; e < pl.n_e; e++) {
+      const uint32_t builder = pass == 0 ? pl.src[e] : pl.dst[e];
+      const uint64_t cap = capacity_words(tables[builder].n_rows, *params);
+      pl.off_filter[pass * pl.n_e + e] = off;
+      pl.cap_words[pass * pl.n_e + e] = cap;
+      off = align256(off + cap * 4);
+    }
+  }
+  pl.total = off;
+  return PT_OK;
+}
+
+uint32_t col_at(const pt_graph *g, uint32_t e, uint32_t table) {
+  return g->edges[e].u == table ? g->edges[e].u_col : g->edges[e].v_col;
+}
+
+}  // namespace
+}  // namespace pt
+
+using namespace pt;
+
+extern "C" {
+
+const char *pt_version(void) { return "pt-mi355x 0.1 (gfx950)"; }
+
+const char *pt_last_error(void) { return g_error.c_str(); }
+
+pt_status pt_profile_enable(int on) {
+  g_prof_on = on != 0;
+  return PT_OK;
+}
+
+pt_status pt_profile_read(pt_kernel_time *out, uint32_t max, uint32_t *n) {
+  if (!n || (max > 0 && !out)) return fail(PT_EINVAL, "pt_profile_read: NULL output");
+  uint32_t k = 0;
+  pt_status st = PT_OK;
+  for (ProfRecord &r : g_prof) {
+    if (hipEventSynchronize(r.stop) != hipSuccess) st = fail(PT_EDEVICE, "event synchronize failed");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) ms = -1.f;
+    r.t.ms = ms;
+    if (k < max) out[k++] = r.t;
+    g_event_pool.push_back(r.start);
+    g_event_pool.push_back(r.stop);
+  }
+  g_prof.clear();
+  *n = k;
+  return st;
+}
+
+pt_status pt_local_filter(const pt_table *table, const pt_pred *preds, uint32_t n_preds,
+                          uint64_t *d_bitmap, uint64_t *d_count, pt_stream stream) {
+  if (!table) return fail(PT_EINVAL, "table is NULL");
+  pt_status st = check_table(table, 0);
+  if (st != PT_OK) return st;
+  if (n_preds > 0 && !preds) return fail(PT_EINVAL, "preds is NULL");
+  if (table->n_rows > 0 && !d_bitmap) return fail(PT_EINVAL, "d_bitmap is NULL");
+  for (uint32_t i = 0; i < n_preds; i++) {
+    if (preds[i].col >= table->n_cols) return fail(PT_EINVAL, "predicate %u: column out of range", i);
+    if (preds[i].op > PT_BETWEEN) return fail(PT_EINVAL, "predicate %u: op %u", i, preds[i].op);
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (d_count) {
+    Timed tm("zero", 0, 0, 0, 8, s);
+    st = check_hip(launch_zero_u64(d_count, 1, s), "zero count");
+    if (st != PT_OK) return st;
+  }
+  uint32_t done = 0;
+  do {
+    PredSet ps{};
+    ps.and_into = done > 0;
+    uint64_t bytes = 0;
+    for (; done < n_preds && ps.n < kMaxPreds; done++, ps.n++) {
+      const pt_column &c = table->cols[preds[done].col];
+      ps.p[ps.n] = PredRef{c.data, c.dtype == PT_I64 ? 1u : 0u, preds[done].op, preds[done].lo,
+                           preds[done].hi};
+      bytes += table->n_rows * key_bytes(c);
+    }
+    const bool last = done >= n_preds;
+    Timed tm("local", 0, 0, table->n_rows, bytes + (table->n_rows + 63) / 64 * 8, s);
+    st = check_hip(launch_local_filter(ps, table->n_rows, d_bitmap, last ? d_count : nullptr, s),
+                   "local filter launch");
+    if (st != PT_OK) return st;
+  } while (done < n_preds);
+  return PT_OK;
+}
+
+pt_status pt_bloom_capacity(uint64_t max_keys, const pt_params *params, uint64_t *out_words) {
+  pt_status st = check_params(params);
+  if (st != PT_OK) return st;
+  if (!out_words) return fail(PT_EINVAL, "out_words is NULL");
+  *out_words = capacity_words(max_keys, *params);
+  return PT_OK;
+}
+
+static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
+                               uint64_t n_rows, const uint64_t *d_bitmap, const uint64_t *d_count,
+                               hipStream_t s, uint32_t table, uint32_t pass) {
+  const pt_params &p = filters[0].params;
+  for (uint32_t done = 0; done < n_filters;) {
+    FilterSet fs{};
+    uint64_t bytes = (n_rows + 63) / 64 * 8;
+    for (; done < n_filters && fs.n < kMaxFilters; done++, fs.n++) {
+      fs.f[fs.n] = make_ref(keys[done], filters[done]);
+      bytes += n_rows * key_bytes(keys[done]);
+    }
+    {
+      Timed tm("size", table, pass, 0, 0, s);
+      pt_status st = check_hip(launch_size_zero(p.block_bits, p.bits_per_key, fs, d_count, n_rows, s),
+                               "size launch");
+      if (st != PT_OK) return st;
+    }
+    Timed tm("build", table, pass, n_rows, bytes, s);
+    pt_status st = check_hip(launch_build(p.block_bits, p.k, fs, n_rows, d_bitmap, s), "build launch");
+    if (st != PT_OK) return st;
+  }
+  return PT_OK;
+}
+
+static pt_status probe_filters(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
+                               uint64_t n_rows, uint64_t *d_bitmap, uint64_t *d_count,
+                               hipStream_t s, uint32_t table, uint32_t pass) {
+  const pt_params &p = filters[0].params;
+  if (d_count) {
+    pt_status st = check_hip(launch_zero_u64(d_count, 1, s), "zero count");
+    if (st != PT_OK) return st;
+  }
+  for (uint32_t done = 0; done < n_filters;) {
+    FilterSet fs{};
+    uint64_t bytes = 2 * ((n_rows + 63) / 64 * 8);
+    for (; done < n_filters && fs.n < kMaxProbe; done++, fs.n++) {
+      fs.f[fs.n] = make_ref(keys[done], filters[done]);
+      bytes += n_rows * key_bytes(keys[done]);
+    }
+    const bool last = done >= n_filters;
+    Timed tm("probe", table, pass, n_rows, bytes, s);
+    pt_status st = check_hip(launch_probe(p.block_bits, p.k, fs, n_rows, d_bitmap,
+                                          last ? d_count : nullptr, s),
+                             "probe launch");
+    if (st != PT_OK) return st;
+  }
+  return PT_OK;
+}
+
+pt_status pt_bloom_build(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
+                         uint64_t n_rows, const uint64_t *d_bitmap, const uint64_t *d_count,
+                         pt_stream stream) {
+  if (n_filters == 0) return PT_OK;
+  if (!keys || !filters) return fail(PT_EINVAL, "keys or filters is NULL");
+  if (n_rows > kMaxRows) return fail(PT_EINVAL, "%llu rows (limit 2^32 - 1)", (unsigned long long)n_rows);
+  if (d_bitmap && !d_count) return fail(PT_EINVAL, "d_count is required with d_bitmap");
+  for (uint32_t i = 0; i < n_filters; i++) {
+    pt_status st = check_column(&keys[i], n_rows, "build key");
+    if (st != PT_OK) return st;
+    st = check_filter(filters[i], filters[0].params, n_rows, i);
+    if (st != PT_OK) return st;
+  }
+  return build_filters(n_filters, keys, filters, n_rows, d_bitmap, d_bitmap ? d_count : nullptr,
+                       reinterpret_cast<hipStream_t>(stream), 0, 0);
+}
+
+pt_status pt_bloom_probe(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
+                         uint64_t n_rows, uint64_t *d_bitmap, uint64_t *d_count, pt_stream stream) {
+  if (!keys && n_filters > 0) return fail(PT_EINVAL, "keys is NULL");
+  if (!filters && n_filters > 0) return fail(PT_EINVAL, "filters is NULL");
+  if (n_rows > kMaxRows) return fail(PT_EINVAL, "%llu rows (limit 2^32 - 1)", (unsigned long long)n_rows);
+  if (n_rows > 0 && !d_bitmap) return fail(PT_EINVAL, "d_bitmap is NULL");
+  for (uint32_t i = 0; i < n_filters; i++) {
+    pt_status st = check_column(&keys[i], n_rows, "probe key");
+    if (st != PT_OK) return st;
+    if (!filters[i].words || !filters[i].d_nb) return fail(PT_EINVAL, "filter %u: NULL pointer", i);
+    st = check_params(&filters[i].params);
+    if (st != PT_OK) return st;
+    if (filters[i].cap_words < filters[i].params.block_bits / 32)
+      return fail(PT_EINVAL, "filter %u: cap_words below one block", i);
+    if (std::memcmp(&filters[i].params, &filters[0].params, sizeof(pt_params)) != 0)
+      return fail(PT_EINVAL, "filter %u: parameters differ from filter 0", i);
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (n_filters == 0) {
+    if (!d_count) return PT_OK;
+    PredSet ps{};
+    ps.and_into = 1;  // no filter: the count of the bitmap as it is
+    pt_status st = check_hip(launch_zero_u64(d_count, 1, s), "zero count");
+    if (st != PT_OK) return st;
+    return check_hip(launch_local_filter(ps, n_rows, d_bitmap, d_count, s), "count launch");
+  }
+  return probe_filters(n_filters, keys, filters, n_rows, d_bitmap, d_count, s, 0, 0);
+}
+
+pt_status pt_compact_workspace_size(uint64_t n_rows, size_t *bytes) {
+  if (!bytes) return fail(PT_EINVAL, "bytes is NULL");
+  if (n_rows > kMaxRows) return fail(PT_EINVAL, "%llu rows (limit 2^32 - 1)", (unsigned long long)n_rows);
+  *bytes = (compact_partials(n_rows) + 1) * 8;
+  return PT_OK;
+}
+
+pt_status pt_compact(const uint64_t *d_bitmap, uint64_t n_rows, uint32_t *d_idx, uint64_t *d_count,
+                     void *d_ws, size_t ws_bytes, pt_stream stream) {
+  if (n_rows > kMaxRows) return fail(PT_EINVAL, "%llu rows (limit 2^32 - 1)", (unsigned long long)n_rows);
+  if (!d_count) return fail(PT_EINVAL, "d_count is NULL");
+  if (n_rows > 0 && (!d_bitmap || !d_idx)) return fail(PT_EINVAL, "d_bitmap or d_idx is NULL");
+  size_t need = 0;
+  pt_compact_workspace_size(n_rows, &need);
+  if (n_rows > 0 && (!d_ws || ws_bytes < need))
+    return fail(PT_ENOMEM, "compact workspace %zu < %zu bytes", ws_bytes, need);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Timed tm("compact", 0, 0, n_rows, (n_rows + 63) / 64 * 16, s);
+  return check_hip(launch_compact(d_bitmap, n_rows, d_idx, d_count, static_cast<uint64_t *>(d_ws), s),
+                   "compact launch");
+}
+
+pt_status pt_transfer_workspace_size(const pt_graph *graph, const pt_table *tables,
+                                     const pt_params *params, size_t *bytes) {
+  if (!bytes) return fail(PT_EINVAL, "bytes is NULL");
+  Plan pl;
+  pt_status st = make_plan(graph, tables, params, pl);
+  if (st != PT_OK) return st;
+  *bytes = pl.total;
+  return PT_OK;
+}
+
+pt_status pt_transfer_filter(const pt_graph *graph, const pt_table *tables, const pt_params *params,
+                             void *d_ws, uint32_t pass, uint32_t edge, pt_bloom *out,
+                             uint32_t *builder) {
+  Plan pl;
+  pt_status st = make_plan(graph, tables, params, pl);
+  if (st != PT_OK) return st;
+  if (!out || !d_ws) return fail(PT_EINVAL, "out or d_ws is NULL");
+  if (pass < 1 || pass > 2 || edge >= pl.n_e) return fail(PT_EINVAL, "pass %u / edge %u out of range", pass, edge);
+  char *ws = static_cast<char *>(d_ws);
+  const uint64_t slot = (pass - 1) * pl.n_e + edge;
+  out->words = reinterpret_cast<uint32_t *>(ws + pl.off_filter[slot]);
+  out->cap_words = pl.cap_words[slot];
+  out->d_nb = reinterpret_cast<uint64_t *>(ws + pl.off_nb) + slot;
+  out->params = *params;
+  if (builder) *builder = pass == 1 ? pl.src[edge] : pl.dst[edge];
+  return PT_OK;
+}
+
+pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pred *preds,
+                      uint32_t n_preds, const pt_params *params, void *d_ws, size_t ws_bytes,
+                      uint64_t *const *d_bitmaps, uint64_t *d_counts, pt_stream stream) {
+  Plan pl;
+  pt_status st = make_plan(graph, tables, params, pl);
+  if (st != PT_OK) return st;
+  if (!d_ws) return fail(PT_EINVAL, "d_ws is NULL");
+  if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0) return fail(PT_EINVAL, "d_ws is not 256-byte aligned");
+  if (ws_bytes < pl.total)
+    return fail(PT_ENOMEM, "workspace %zu < %llu bytes", ws_bytes, (unsigned long long)pl.total);
+  if (pl.n_t > 0 && !d_bitmaps) return fail(PT_EINVAL, "d_bitmaps is NULL");
+  for (uint32_t t = 0; t < pl.n_t; t++)
+    if (tables[t].n_rows > 0 && !d_bitmaps[t]) return fail(PT_EINVAL, "d_bitmaps[%u] is NULL", t);
+  if (n_preds > 0 && !preds) return fail(PT_EINVAL, "preds is NULL");
+  for (uint32_t i = 0; i < n_preds; i++) {
+    if (preds[i].table >= pl.n_t) return fail(PT_EINVAL, "predicate %u: table out of range", i);
+    if (preds[i].col >= tables[preds[i].table].n_cols)
+      return fail(PT_EINVAL, "predicate %u: column out of range", i);
+    if (preds[i].op > PT_BETWEEN) return fail(PT_EINVAL, "predicate %u: op %u", i, preds[i].op);
+  }
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *ws = static_cast<char *>(d_ws);
+  uint64_t *counts = reinterpret_cast<uint64_t *>(ws + pl.off_counts);
+  uint64_t *nbs = reinterpret_cast<uint64_t *>(ws + pl.off_nb);
+  auto bloom_at = [&](uint32_t slot) {
+    pt_bloom b{};
+    b.words = reinterpret_cast<uint32_t *>(ws + pl.off_filter[slot]);
+    b.cap_words = pl.cap_words[slot];
+    b.d_nb = nbs + slot;
+    b.params = *params;
+    return b;
+  };
+
+  {
+    Timed tm("zero", 0, 0, 0, 3ull * pl.n_t * 8, s);
+    st = check_hip(launch_zero_u64(counts, 3ull * pl.n_t, s), "zero counters");
+    if (st != PT_OK) return st;
+  }
+
+  // Local predicates: every table starts from its own selected rows.
+  std::vector<uint32_t> cur(pl.n_t, 0);  // counter slot (0 local, 1 fwd, 2 bwd) holding t's count
+  std::vector<pt_pred> mine;
+  for (uint32_t t = 0; t < pl.n_t; t++) {
+    mine.clear();
+    for (uint32_t i = 0; i < n_preds; i++)
+      if (preds[i].table == t) mine.push_back(preds[i]);
+    const pt_table &tb = tables[t];
+    uint64_t *cnt = counts + t;
+    uint32_t done = 0;
+    do {
+      PredSet ps{};
+      ps.and_into = done > 0;
+      uint64_t bytes = 0;
+      for (; done < mine.size() && ps.n < kMaxPreds; done++, ps.n++) {
+        const pt_column &c = tb.cols[mine[done].col];
+        ps.p[ps.n] = PredRef{c.data, c.dtype == PT_I64 ? 1u : 0u, mine[done].op, mine[done].lo,
+                             mine[done].hi};
+        bytes += tb.n_rows * key_bytes(c);
+      }
+      const bool last = done >= mine.size();
+      Timed tm("local", t, 0, tb.n_rows, bytes + (tb.n_rows + 63) / 64 * 8, s);
+      st = check_hip(launch_local_filter(ps, tb.n_rows, d_bitmaps[t], last ? cnt : nullptr, s),
+                     "local filter launch");
+      if (st != PT_OK) return st;
+    } while (done < mine.size());
+  }
+
+  // The two passes (Sec. 3.2). In pass p (0 forward, 1 backward) the edge e
+  // goes from `from[e]` to `to[e]`; tables are visited in `seq`.
+  std::vector<uint32_t> rev(pl.order.rbegin(), pl.order.rend());
+  std::vector<pt_column> keys;
+  std::vector<pt_bloom> blooms;
+  for (uint32_t p = 0; p < 2; p++) {
+    const std::vector<uint32_t> &from = p == 0 ? pl.src : pl.dst;
+    const std::vector<uint32_t> &to = p == 0 ? pl.dst : pl.src;
+    const std::vector<uint32_t> &seq = p == 0 ? pl.order : rev;
+    for (uint32_t v : seq) {
+      const pt_table &tb = tables[v];
+      // Incoming filters: probe them all in one scan of v.
+      keys.clear();
+      blooms.clear();
+      for (uint32_t e = 0; e < pl.n_e; e++) {
+        if (to[e] != v) continue;
+        keys.push_back(tb.cols[col_at(graph, e, v)]);
+        blooms.push_back(bloom_at(p * pl.n_e + e));
+      }
+      if (!keys.empty()) {
+        uint64_t *cnt = counts + (p + 1) * pl.n_t + v;
+        st = probe_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), tb.n_rows,
+                           d_bitmaps[v], cnt, s, v, p + 1);
+        if (st != PT_OK) return st;
+        cur[v] = p + 1;
+      }
+      // Outgoing filters: sized from v's count after this pass's probes.
+      keys.clear();
+      blooms.clear();
+      for (uint32_t e = 0; e < pl.n_e; e++) {
+        if (from[e] != v) continue;
+        keys.push_back(tb.cols[col_at(graph, e, v)]);
+        blooms.push_back(bloom_at(p * pl.n_e + e));
+      }
+      if (!keys.empty()) {
+        st = build_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), tb.n_rows,
+                           d_bitmaps[v], counts + cur[v] * pl.n_t + v, s, v, p + 1);
+        if (st != PT_OK) return st;
+      }
+    }
+  }
+
+  if (d_counts) {
+    std::vector<uint32_t> slot(pl.n_t);
+    for (uint32_t t = 0; t < pl.n_t; t++) slot[t] = cur[t] * pl.n_t + t;
+    st = check_hip(launch_copy_counts(counts, slot.data(), pl.n_t, d_counts, s), "count copy");
+    if (st != PT_OK) return st;
+  }
+  return PT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// pt_internal.hpp - launch descriptors shared by the host API and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "pt_device.hpp"
+
+namespace pt {
+
+// One filter as a probe or build launch sees it.
+struct FilterRef {
+  const void *keys;   // key column of the scanned table
+  uint32_t *words;    // filter words (device)
+  uint64_t *nb;       // device: number of blocks in use
+  uint64_t cap_words; // capacity of `words`
+  uint32_t key64;     // key column is int64
+  uint32_t pad;
+};
+
+struct FilterSet {
+  uint32_t n;
+  uint32_t pad;
+  FilterRef f[kMaxFilters];
+};
+
+struct PredRef {
+  const void *col;
+  uint32_t col64;
+  uint32_t op;
+  int64_t lo, hi;
+};
+
+struct PredSet {
+  uint32_t n;
+  uint32_t and_into;  // AND into the existing bitmap instead of overwriting it
+  PredRef p[kMaxPreds];
+};
+
+struct DeviceInfo {
+  int device = -1;
+  int n_cu = 0;
+  int max_lds_block = 0;  // bytes of LDS one workgroup may allocate
+};
+
+const DeviceInfo &device_info();
+
+// Launchers (pt_kernels.hip). Each returns hipSuccess or the launch error.
+hipError_t launch_zero_u64(uint64_t *p, uint64_t n, hipStream_t s);
+hipError_t launch_local_filter(const PredSet &preds, uint64_t n_rows, uint64_t *bitmap,
+                               uint64_t *count, hipStream_t s);
+hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,
+                        uint64_t *bitmap, uint64_t *count, hipStream_t s);
+hipError_t launch_size_zero(uint32_t block_bits, uint32_t bits_per_key, const FilterSet &fs,
+                            const uint64_t *count, uint64_t n_rows, hipStream_t s);
+hipError_t launch_build(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,
+                        const uint64_t *bitmap, hipStream_t s);
+hipError_t launch_copy_counts(const uint64_t *src, const uint32_t *slot, uint32_t n,
+                              uint64_t *dst, hipStream_t s);
+hipError_t launch_compact(const uint64_t *bitmap, uint64_t n_rows, uint32_t *idx, uint64_t *count,
+                          uint64_t *partials, hipStream_t s);
+uint64_t compact_partials(uint64_t n_rows);
+
+}  // namespace pt

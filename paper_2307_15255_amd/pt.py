@@ -1,0 +1,302 @@
+"""Python binding of libpt_hip.so (include/pt.h).
+
+Argument marshalling only: every step of the transfer phase runs in the HIP
+kernels behind the C ABI. torch provides device memory (tensors) and streams.
+The functions keep the C names; the classes at the end assemble the arguments
+of a whole join problem.
+
+Importing this module loads the library and raises if it has not been built
+(``python -m paper_2307_15255_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpt_hip.so")
+
+PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EUNSUPPORTED = 0, 1, 2, 3, 4
+PT_I32, PT_I64 = 0, 1
+OPS = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "eq": 4, "ne": 5, "between": 6}
+
+
+class PtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"pt status {status}: {msg}")
+        self.status = status
+
+
+class pt_column(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class pt_table(C.Structure):
+    _fields_ = [("n_rows", C.c_uint64), ("n_cols", C.c_uint32), ("reserved", C.c_uint32),
+                ("cols", C.POINTER(pt_column))]
+
+
+class pt_edge(C.Structure):
+    _fields_ = [("u", C.c_uint32), ("u_col", C.c_uint32), ("v", C.c_uint32), ("v_col", C.c_uint32)]
+
+
+class pt_graph(C.Structure):
+    _fields_ = [("n_tables", C.c_uint32), ("n_edges", C.c_uint32), ("edges", C.POINTER(pt_edge)),
+                ("orient", C.POINTER(C.c_int8))]
+
+
+class pt_pred(C.Structure):
+    _fields_ = [("table", C.c_uint32), ("col", C.c_uint32), ("op", C.c_uint32),
+                ("reserved", C.c_uint32), ("lo", C.c_int64), ("hi", C.c_int64)]
+
+
+class pt_params(C.Structure):
+    _fields_ = [("block_bits", C.c_uint32), ("k", C.c_uint32), ("bits_per_key", C.c_uint32),
+                ("flags", C.c_uint32)]
+
+
+class pt_bloom(C.Structure):
+    _fields_ = [("words", C.c_void_p), ("cap_words", C.c_uint64), ("d_nb", C.c_void_p),
+                ("params", pt_params)]
+
+
+class pt_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char * 24), ("table", C.c_uint32), ("pass_", C.c_uint32),
+                ("rows", C.c_uint64), ("bytes", C.c_uint64), ("ms", C.c_float),
+                ("reserved", C.c_uint32)]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2307_15255_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, u32, u64, st = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
+    sizep = C.POINTER(C.c_size_t)
+    sigs = {
+        "pt_version": ([], C.c_char_p),
+        "pt_last_error": ([], C.c_char_p),
+        "pt_local_filter": ([C.POINTER(pt_table), C.POINTER(pt_pred), u32, vp, vp, vp], st),
+        "pt_bloom_capacity": ([u64, C.POINTER(pt_params), C.POINTER(u64)], st),
+        "pt_bloom_build": ([u32, C.POINTER(pt_column), C.POINTER(pt_bloom), u64, vp, vp, vp], st),
+        "pt_bloom_probe": ([u32, C.POINTER(pt_column), C.POINTER(pt_bloom), u64, vp, vp, vp], st),
+        "pt_compact_workspace_size": ([u64, sizep], st),
+        "pt_compact": ([vp, u64, vp, vp, vp, C.c_size_t, vp], st),
+        "pt_transfer_workspace_size": ([C.POINTER(pt_graph), C.POINTER(pt_table),
+                                        C.POINTER(pt_params), sizep], st),
+        "pt_transfer": ([C.POINTER(pt_graph), C.POINTER(pt_table), C.POINTER(pt_pred), u32,
+                         C.POINTER(pt_params), vp, C.c_size_t, C.POINTER(vp), vp, vp], st),
+        "pt_transfer_filter": ([C.POINTER(pt_graph), C.POINTER(pt_table), C.POINTER(pt_params), vp,
+                                u32, u32, C.POINTER(pt_bloom), C.POINTER(u32)], st),
+        "pt_profile_enable": ([C.c_int], st),
+        "pt_profile_read": ([C.POINTER(pt_kernel_time), u32, C.POINTER(u32)], st),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+_lib = _load()
+EXPORTS = ("pt_version", "pt_last_error", "pt_local_filter", "pt_bloom_capacity", "pt_bloom_build",
+           "pt_bloom_probe", "pt_compact_workspace_size", "pt_compact", "pt_transfer_workspace_size",
+           "pt_transfer", "pt_transfer_filter", "pt_profile_enable", "pt_profile_read")
+
+
+def lib() -> C.CDLL:
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != PT_OK:
+        raise PtError(status, _lib.pt_last_error().decode())
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t: torch.Tensor | None) -> C.c_void_p:
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def column(t: torch.Tensor) -> pt_column:
+    if t.dtype not in (torch.int32, torch.int64) or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("a column is a contiguous int32 or int64 CUDA tensor")
+    return pt_column(t.data_ptr() if t.numel() else 0, PT_I64 if t.dtype == torch.int64 else PT_I32, 0)
+
+
+def params(block_bits: int = 512, k: int = 3, bits_per_key: int = 10) -> pt_params:
+    return pt_params(block_bits, k, bits_per_key, 0)
+
+
+def bitmap_words(n_rows: int) -> int:
+    return (n_rows + 63) // 64
+
+
+def pt_version() -> str:
+    return _lib.pt_version().decode()
+
+
+# ------------------------------------------------------------- primitives
+
+def pt_local_filter(cols: list[torch.Tensor], preds: list[tuple], n_rows: int,
+                    bitmap: torch.Tensor, count: torch.Tensor | None = None, stream=None) -> None:
+    """preds: (col_index, op, lo, hi); bitmap: int64 tensor of
+    ceil(n_rows/64) words (written); count: one int64 (written)."""
+    cc = (pt_column * max(1, len(cols)))(*[column(c) for c in cols])
+    tb = pt_table(n_rows, len(cols), 0, cc)
+    pp = (pt_pred * max(1, len(preds)))(*[pt_pred(0, c, OPS[op], 0, lo, hi) for c, op, lo, hi in preds])
+    _check(_lib.pt_local_filter(C.byref(tb), pp, len(preds), _ptr(bitmap), _ptr(count), _stream(stream)))
+
+
+def pt_bloom_capacity(max_keys: int, p: pt_params) -> int:
+    out = C.c_uint64()
+    _check(_lib.pt_bloom_capacity(max_keys, C.byref(p), C.byref(out)))
+    return out.value
+
+
+class Bloom:
+    """A filter in device memory: `words` (int32 tensor of cap_words) and
+    `nb` (one int64: blocks in use)."""
+
+    def __init__(self, max_keys: int, p: pt_params, device="cuda"):
+        self.params = p
+        self.cap_words = pt_bloom_capacity(max_keys, p)
+        self.words = torch.zeros(self.cap_words, dtype=torch.int32, device=device)
+        self.nb = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def c(self) -> pt_bloom:
+        return pt_bloom(self.words.data_ptr(), self.cap_words, self.nb.data_ptr(), self.params)
+
+    def used_words(self) -> np.ndarray:
+        nb = int(self.nb.item())
+        return self.words[:nb * (self.params.block_bits // 32)].cpu().numpy().view(np.uint32)
+
+
+def pt_bloom_build(keys: list[torch.Tensor], filters: list[Bloom], n_rows: int,
+                   bitmap: torch.Tensor | None = None, count: torch.Tensor | None = None,
+                   stream=None) -> None:
+    kc = (pt_column * max(1, len(keys)))(*[column(k) for k in keys])
+    fc = (pt_bloom * max(1, len(filters)))(*[f.c() for f in filters])
+    _check(_lib.pt_bloom_build(len(keys), kc, fc, n_rows, _ptr(bitmap), _ptr(count), _stream(stream)))
+
+
+def pt_bloom_probe(keys: list[torch.Tensor], filters: list[Bloom], n_rows: int, bitmap: torch.Tensor,
+                   count: torch.Tensor | None = None, stream=None) -> None:
+    kc = (pt_column * max(1, len(keys)))(*[column(k) for k in keys])
+    fc = (pt_bloom * max(1, len(filters)))(*[f.c() for f in filters])
+    _check(_lib.pt_bloom_probe(len(keys), kc, fc, n_rows, _ptr(bitmap), _ptr(count), _stream(stream)))
+
+
+def pt_compact_workspace_size(n_rows: int) -> int:
+    out = C.c_size_t()
+    _check(_lib.pt_compact_workspace_size(n_rows, C.byref(out)))
+    return out.value
+
+
+def pt_compact(bitmap: torch.Tensor, n_rows: int, idx: torch.Tensor, count: torch.Tensor,
+               ws: torch.Tensor, stream=None) -> None:
+    _check(_lib.pt_compact(_ptr(bitmap), n_rows, _ptr(idx), _ptr(count), _ptr(ws), ws.numel(),
+                           _stream(stream)))
+
+
+def pt_profile_enable(on: bool) -> None:
+    _check(_lib.pt_profile_enable(1 if on else 0))
+
+
+def pt_profile_read(max_records: int = 4096) -> list[dict]:
+    buf = (pt_kernel_time * max_records)()
+    n = C.c_uint32()
+    _check(_lib.pt_profile_read(buf, max_records, C.byref(n)))
+    return [dict(name=buf[i].name.decode(), table=buf[i].table, pass_=buf[i].pass_, rows=buf[i].rows,
+                 bytes=buf[i].bytes, ms=buf[i].ms) for i in range(n.value)]
+
+
+# ------------------------------------------------------------ transfer
+
+class DeviceProblem:
+    """A join problem (`workloads.Problem`) with its columns in device memory
+    and the C descriptors of its graph, tables and predicates."""
+
+    def __init__(self, problem, device="cuda", columns=None):
+        self.problem = problem
+        self.n_tables = problem.n_tables
+        self.n_rows = [problem.n_rows(t) for t in range(problem.n_tables)]
+        if columns is None:
+            columns = [{c: torch.from_numpy(np.ascontiguousarray(a)).to(device) for c, a in cols.items()}
+                       for cols in problem.columns]
+        self.columns = columns
+        self._ccols = []
+        self.tables = (pt_table * max(1, self.n_tables))()
+        for t in range(self.n_tables):
+            cc = (pt_column * max(1, len(columns[t])))(*[column(a) for a in columns[t].values()])
+            self._ccols.append(cc)
+            self.tables[t] = pt_table(self.n_rows[t], len(columns[t]), 0, cc)
+        self.edges = (pt_edge * max(1, len(problem.edges)))(*[
+            pt_edge(u, problem.col_index(u, uc), v, problem.col_index(v, vc)) for u, uc, v, vc in problem.edges])
+        self._orient = None
+        orient_ptr = None
+        if problem.orient is not None:
+            self._orient = (C.c_int8 * len(problem.orient))(*problem.orient)
+            orient_ptr = C.cast(self._orient, C.POINTER(C.c_int8))
+        self.graph = pt_graph(self.n_tables, len(problem.edges), self.edges, orient_ptr)
+        self.preds = (pt_pred * max(1, len(problem.preds)))(*[
+            pt_pred(t, problem.col_index(t, c), OPS[op], 0, lo, hi) for t, c, op, lo, hi in problem.preds])
+        self.n_preds = len(problem.preds)
+
+
+def pt_transfer_workspace_size(dp: DeviceProblem, p: pt_params) -> int:
+    out = C.c_size_t()
+    _check(_lib.pt_transfer_workspace_size(C.byref(dp.graph), dp.tables, C.byref(p), C.byref(out)))
+    return out.value
+
+
+def pt_transfer(dp: DeviceProblem, p: pt_params, ws: torch.Tensor, bitmaps: list[torch.Tensor],
+                counts: torch.Tensor | None = None, stream=None) -> None:
+    bm = (C.c_void_p * max(1, dp.n_tables))(*[b.data_ptr() if b.numel() else 0 for b in bitmaps])
+    _check(_lib.pt_transfer(C.byref(dp.graph), dp.tables, dp.preds, dp.n_preds, C.byref(p), _ptr(ws),
+                            ws.numel(), bm, _ptr(counts), _stream(stream)))
+
+
+def pt_transfer_filter(dp: DeviceProblem, p: pt_params, ws: torch.Tensor, pass_: int, edge: int):
+    out = pt_bloom()
+    builder = C.c_uint32()
+    _check(_lib.pt_transfer_filter(C.byref(dp.graph), dp.tables, C.byref(p), _ptr(ws), pass_, edge,
+                                   C.byref(out), C.byref(builder)))
+    return out, builder.value
+
+
+class Transfer:
+    """Holds the workspace, bitmaps and counts of one problem and runs the
+    transfer phase on it (all allocation happens here, once)."""
+
+    def __init__(self, dp: DeviceProblem, p: pt_params | None = None, device="cuda"):
+        self.dp = dp
+        self.params = p if p is not None else params()
+        self.ws_bytes = pt_transfer_workspace_size(dp, self.params)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.bitmaps = [torch.empty(bitmap_words(n), dtype=torch.int64, device=device) for n in dp.n_rows]
+        self.counts = torch.zeros(dp.n_tables, dtype=torch.int64, device=device)
+
+    def run(self, stream=None) -> None:
+        pt_transfer(self.dp, self.params, self.ws, self.bitmaps, self.counts, stream)
+
+    def bitmap(self, t: int) -> np.ndarray:
+        return self.bitmaps[t].cpu().numpy().view(np.uint64)
+
+    def filter(self, pass_: int, edge: int) -> tuple[np.ndarray, int, int]:
+        """(used words, nb, builder) of the filter `edge` carried in pass 1
+        (forward) or 2 (backward)."""
+        b, builder = pt_transfer_filter(self.dp, self.params, self.ws, pass_, edge)
+        off = b.words - self.ws.data_ptr()
+        nb_off = b.d_nb - self.ws.data_ptr()
+        nb = int(self.ws[nb_off:nb_off + 8].cpu().numpy().view(np.uint64)[0])
+        n = nb * (self.params.block_bits // 32)
+        words = self.ws[off:off + 4 * n].cpu().numpy().view(np.uint32)
+        return words, nb, builder

@@ -1,0 +1,110 @@
+"""The C ABI library loads and exports every symbol include/pt.h declares;
+host-side argument checks and sizing run without a GPU (no kernel is
+launched by anything in this file)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pt.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pt_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def ptlib():
+    from paper_2307_15255_amd import pt
+    return pt
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("pt_local_filter", "pt_bloom_build", "pt_bloom_probe", "pt_compact",
+                     "pt_transfer"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(ptlib):
+    lib = C.CDLL(ptlib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(ptlib.EXPORTS)
+
+
+def test_version(ptlib):
+    assert "gfx950" in ptlib.pt_version()
+
+
+def test_capacity_and_workspace_sizes(ptlib):
+    import oracle
+    p = ptlib.params(512, 3, 10)
+    for n in (0, 1, 51, 52, 20_000, 100_000_000):
+        assert ptlib.pt_bloom_capacity(n, p) == oracle.filter_blocks(n, 10, 512) * 16
+    assert ptlib.pt_compact_workspace_size(0) == 8
+    assert ptlib.pt_compact_workspace_size(65536 * 3 + 1) == 5 * 8
+
+
+def test_parameter_validation(ptlib):
+    bad = [ptlib.pt_params(48, 3, 10, 0), ptlib.pt_params(2048, 3, 10, 0), ptlib.pt_params(512, 0, 10, 0),
+           ptlib.pt_params(512, 17, 10, 0), ptlib.pt_params(512, 3, 0, 0), ptlib.pt_params(512, 3, 65, 0),
+           ptlib.pt_params(512, 3, 10, 1)]
+    for p in bad:
+        with pytest.raises(ptlib.PtError) as ei:
+            ptlib.pt_bloom_capacity(10, p)
+        assert ei.value.status == ptlib.PT_EINVAL
+
+
+class _HostProblem:
+    """C descriptors for a graph whose columns point at host memory: enough
+    for the planner (workspace size), which never touches column data."""
+
+    def __init__(self, ptlib, rows, edges, orient=None):
+        self.keep = []
+        self.tables = (ptlib.pt_table * len(rows))()
+        for t, n in enumerate(rows):
+            a = np.zeros(max(n, 1), np.int32)
+            self.keep.append(a)
+            cc = (ptlib.pt_column * 2)(ptlib.pt_column(a.ctypes.data, 0, 0), ptlib.pt_column(a.ctypes.data, 0, 0))
+            self.keep.append(cc)
+            self.tables[t] = ptlib.pt_table(n, 2, 0, cc)
+        self.edges = (ptlib.pt_edge * max(1, len(edges)))(*[ptlib.pt_edge(*e) for e in edges])
+        o = None
+        if orient is not None:
+            self.o = (C.c_int8 * len(orient))(*orient)
+            o = C.cast(self.o, C.POINTER(C.c_int8))
+        self.graph = ptlib.pt_graph(len(rows), len(edges), self.edges, o)
+
+    def ws(self, ptlib, p):
+        out = C.c_size_t()
+        st = ptlib.lib().pt_transfer_workspace_size(C.byref(self.graph), self.tables, C.byref(p), C.byref(out))
+        return st, out.value
+
+
+def test_planner_validation(ptlib):
+    p = ptlib.params()
+    ok = _HostProblem(ptlib, [10, 100, 1000], [(0, 0, 1, 0), (1, 1, 2, 0)])
+    st, size = ok.ws(ptlib, p)
+    assert st == ptlib.PT_OK and size > 0
+    # every filter at its largest size: forward builders R (10 rows) and S (100); backward S and T
+    cap = lambda n: ptlib.pt_bloom_capacity(n, p) * 4
+    assert size >= cap(10) + cap(100) + cap(100) + cap(1000)
+    for rows, edges, orient in [
+        ([10, 100], [(0, 0, 0, 1)], None),          # self-join edge
+        ([10, 100], [(0, 0, 2, 0)], None),          # table out of range
+        ([10, 100], [(0, 5, 1, 0)], None),          # column out of range
+        ([10, 100, 5], [(0, 0, 1, 0), (1, 0, 2, 0), (2, 0, 0, 0)], [1, 1, 1]),  # directed cycle
+        ([10, 100], [(0, 0, 1, 0)], [0]),           # orientation not +-1
+        ([2**32, 5], [(0, 0, 1, 0)], None),         # too many rows
+    ]:
+        st, _ = _HostProblem(ptlib, rows, edges, orient).ws(ptlib, p)
+        assert st == ptlib.PT_EINVAL, (rows, edges, orient)
+    # a cycle in the join graph itself is fine: the size rule orients it acyclically
+    st, _ = _HostProblem(ptlib, [10, 100, 5], [(0, 0, 1, 0), (1, 0, 2, 0), (2, 0, 0, 0)]).ws(ptlib, p)
+    assert st == ptlib.PT_OK
