@@ -382,8 +382,13 @@ static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const 
   return PT_OK;
 }
 
+// Probes n_filters filters in one scan per group of kMaxProbe. `sel` and
+// `rows` (optional) give each filter's builder count and row total, which
+// only order the tests. input_all: the bitmap holds every row and is not
+// read by the first launch.
 static pt_status probe_filters(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
-                               uint64_t n_rows, uint64_t *d_bitmap, uint64_t *d_count,
+                               const uint64_t *const *sel, const uint64_t *rows, uint64_t n_rows,
+                               uint64_t *d_bitmap, uint64_t *d_count, bool input_all,
                                hipStream_t s, uint32_t table, uint32_t pass) {
   const pt_params &p = filters[0].params;
   if (d_count) {
@@ -392,15 +397,20 @@ static pt_status probe_filters(uint32_t n_filters, const pt_column *keys, const 
   }
   for (uint32_t done = 0; done < n_filters;) {
     FilterSet fs{};
-    uint64_t bytes = 2 * ((n_rows + 63) / 64 * 8);
+    const bool first = done == 0;
+    uint64_t bytes = ((input_all && first) ? 1 : 2) * ((n_rows + 63) / 64 * 8);
     for (; done < n_filters && fs.n < kMaxProbe; done++, fs.n++) {
       fs.f[fs.n] = make_ref(keys[done], filters[done]);
+      if (sel && rows) {
+        fs.f[fs.n].sel = sel[done];
+        fs.f[fs.n].rows = rows[done];
+      }
       bytes += n_rows * key_bytes(keys[done]);
     }
     const bool last = done >= n_filters;
     Timed tm("probe", table, pass, n_rows, bytes, s);
     pt_status st = check_hip(launch_probe(p.block_bits, p.k, fs, n_rows, d_bitmap,
-                                          last ? d_count : nullptr, s),
+                                          last ? d_count : nullptr, input_all && first, s),
                              "probe launch");
     if (st != PT_OK) return st;
   }
@@ -450,7 +460,8 @@ pt_status pt_bloom_probe(uint32_t n_filters, const pt_column *keys, const pt_blo
     if (st != PT_OK) return st;
     return check_hip(launch_local_filter(ps, n_rows, d_bitmap, d_count, s), "count launch");
   }
-  return probe_filters(n_filters, keys, filters, n_rows, d_bitmap, d_count, s, 0, 0);
+  return probe_filters(n_filters, keys, filters, nullptr, nullptr, n_rows, d_bitmap, d_count, false,
+                       s, 0, 0);
 }
 
 pt_status pt_compact_workspace_size(uint64_t n_rows, size_t *bytes) {
@@ -543,13 +554,19 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
     if (st != PT_OK) return st;
   }
 
-  // Local predicates: every table starts from its own selected rows.
+  // Local predicates: every table starts from its own selected rows. A
+  // table without predicates keeps all rows; its bitmap is not materialised
+  // until something changes it (its first probe writes every word) or the
+  // end of the call.
   std::vector<uint32_t> cur(pl.n_t, 0);  // counter slot (0 local, 1 fwd, 2 bwd) holding t's count
+  std::vector<char> all_rows(pl.n_t, 1);
   std::vector<pt_pred> mine;
   for (uint32_t t = 0; t < pl.n_t; t++) {
     mine.clear();
     for (uint32_t i = 0; i < n_preds; i++)
       if (preds[i].table == t) mine.push_back(preds[i]);
+    if (mine.empty()) continue;
+    all_rows[t] = 0;
     const pt_table &tb = tables[t];
     uint64_t *cnt = counts + t;
     uint32_t done = 0;
@@ -576,6 +593,9 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
   std::vector<uint32_t> rev(pl.order.rbegin(), pl.order.rend());
   std::vector<pt_column> keys;
   std::vector<pt_bloom> blooms;
+  std::vector<const uint64_t *> sel;
+  std::vector<uint64_t> rows;
+  std::vector<const uint64_t *> built_sel(2ull * pl.n_e, nullptr);  // builder count per filter
   for (uint32_t p = 0; p < 2; p++) {
     const std::vector<uint32_t> &from = p == 0 ? pl.src : pl.dst;
     const std::vector<uint32_t> &to = p == 0 ? pl.dst : pl.src;
@@ -585,17 +605,22 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
       // Incoming filters: probe them all in one scan of v.
       keys.clear();
       blooms.clear();
+      sel.clear();
+      rows.clear();
       for (uint32_t e = 0; e < pl.n_e; e++) {
         if (to[e] != v) continue;
         keys.push_back(tb.cols[col_at(graph, e, v)]);
         blooms.push_back(bloom_at(p * pl.n_e + e));
+        sel.push_back(built_sel[p * pl.n_e + e]);
+        rows.push_back(tables[from[e]].n_rows);
       }
       if (!keys.empty()) {
         uint64_t *cnt = counts + (p + 1) * pl.n_t + v;
-        st = probe_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), tb.n_rows,
-                           d_bitmaps[v], cnt, s, v, p + 1);
+        st = probe_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), sel.data(),
+                           rows.data(), tb.n_rows, d_bitmaps[v], cnt, all_rows[v] != 0, s, v, p + 1);
         if (st != PT_OK) return st;
         cur[v] = p + 1;
+        all_rows[v] = 0;
       }
       // Outgoing filters: sized from v's count after this pass's probes.
       keys.clear();
@@ -604,13 +629,24 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
         if (from[e] != v) continue;
         keys.push_back(tb.cols[col_at(graph, e, v)]);
         blooms.push_back(bloom_at(p * pl.n_e + e));
+        built_sel[p * pl.n_e + e] = all_rows[v] ? nullptr : counts + cur[v] * pl.n_t + v;
       }
       if (!keys.empty()) {
+        const bool all = all_rows[v] != 0;
         st = build_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), tb.n_rows,
-                           d_bitmaps[v], counts + cur[v] * pl.n_t + v, s, v, p + 1);
+                           all ? nullptr : d_bitmaps[v], all ? nullptr : counts + cur[v] * pl.n_t + v,
+                           s, v, p + 1);
         if (st != PT_OK) return st;
       }
     }
+  }
+
+  // Tables nothing has filtered keep every row.
+  for (uint32_t t = 0; t < pl.n_t; t++) {
+    if (!all_rows[t]) continue;
+    Timed tm("fill", t, 0, tables[t].n_rows, (tables[t].n_rows + 63) / 64 * 8, s);
+    st = check_hip(launch_fill_all(d_bitmaps[t], tables[t].n_rows, counts + t, s), "fill launch");
+    if (st != PT_OK) return st;
   }
 
   if (d_counts) {

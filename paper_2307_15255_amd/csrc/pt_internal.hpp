@@ -18,6 +18,10 @@ struct FilterRef {
   uint64_t cap_words; // capacity of `words`
   uint32_t key64;     // key column is int64
   uint32_t pad;
+  // Probe order hint: the builder kept *sel of its `rows` rows (NULL or 0:
+  // unknown). Filters with the smallest ratio are tested first.
+  const uint64_t *sel;
+  uint64_t rows;
 };
 
 struct FilterSet {
@@ -51,8 +55,10 @@ const DeviceInfo &device_info();
 hipError_t launch_zero_u64(uint64_t *p, uint64_t n, hipStream_t s);
 hipError_t launch_local_filter(const PredSet &preds, uint64_t n_rows, uint64_t *bitmap,
                                uint64_t *count, hipStream_t s);
+hipError_t launch_fill_all(uint64_t *bitmap, uint64_t n_rows, uint64_t *count, hipStream_t s);
+// input_all: every row starts selected (the bitmap is not read, only written).
 hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,
-                        uint64_t *bitmap, uint64_t *count, hipStream_t s);
+                        uint64_t *bitmap, uint64_t *count, bool input_all, hipStream_t s);
 hipError_t launch_size_zero(uint32_t block_bits, uint32_t bits_per_key, const FilterSet &fs,
                             const uint64_t *count, uint64_t n_rows, hipStream_t s);
 hipError_t launch_build(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,

@@ -1,9 +1,10 @@
 // pt_kernels.hip - gfx950 kernels of the predicate-transfer phase.
 //
-// Every kernel works on 64-row groups: one wave64 owns one 64-bit bitmap
-// word at a time (lane l holds row 64 * w + l), so a wave's ballot is the
-// word and each word has exactly one writer. Rows are streamed with
-// coalesced 256-byte (int32) or 512-byte (int64) loads per wave.
+// A wave64 owns 64-row groups: lane l holds row 64 * w + l of bitmap word w,
+// so a wave's ballot is the word. Every branch in the streaming loops is
+// wave-uniform; per-lane work that does not matter (rows already removed,
+// rows past the end) is computed anyway on clamped, in-bounds addresses and
+// masked out, which keeps the exec mask full and the code straight-line.
 #include "pt_internal.hpp"
 
 namespace pt {
@@ -11,21 +12,44 @@ namespace pt {
 namespace {
 
 constexpr int kThreads = 256;        // local filter, build, size, compact
-constexpr int kProbeThreads = 1024;  // probe: one or two workgroups per CU
+constexpr int kProbeThreads = 1024;  // probe: sixteen waves per workgroup
+constexpr int kProbeWaves = kProbeThreads / kWave;
 
-__device__ __forceinline__ uint64_t lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
 
+// The wave's index in the grid, as a wave-uniform (scalar) value: the
+// compiler cannot tell on its own that threadIdx.x / 64 is the same for
+// every lane, and would otherwise keep loop counters derived from it in
+// vector registers and turn every uniform branch into an exec-mask branch.
 __device__ __forceinline__ uint64_t global_wave() {
-  return (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  return static_cast<uint64_t>(blockIdx.x) * (blockDim.x / kWave) + w;
 }
 
 __device__ __forceinline__ uint64_t wave_count() {
   return static_cast<uint64_t>(gridDim.x) * blockDim.x / kWave;
 }
 
-// Adds a per-wave count (held by lane 0) into *out with one atomic per
-// workgroup.
-__device__ __forceinline__ void block_count_add(uint64_t wave_cnt, unsigned long long *s_cnt,
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, static_cast<uint32_t>(__shfl_xor(v, off)));
+  return v;
+}
+
+// Adds a wave-uniform count into *out with one global atomic per workgroup.
+__device__ __forceinline__ void block_count_add(int64_t wave_cnt, unsigned long long *s_cnt,
                                                 unsigned long long *out) {
   if (lane_id() == 0 && wave_cnt) atomicAdd(s_cnt, static_cast<unsigned long long>(wave_cnt));
   __syncthreads();
@@ -39,6 +63,12 @@ __device__ __forceinline__ uint32_t clamp_blocks(uint64_t nb, uint64_t cap_block
   return static_cast<uint32_t>(nb == 0 ? 1 : nb);
 }
 
+// Bits of word w that belong to rows below n_rows.
+__device__ __forceinline__ uint64_t tail_mask(uint64_t w, uint64_t n_words, uint64_t n_rows) {
+  if (w >= n_words) return 0;
+  return (w + 1 == n_words && (n_rows & 63)) ? (1ull << (n_rows & 63)) - 1 : ~0ull;
+}
+
 // Selects filter i of a set without a dynamically indexed kernel argument.
 __device__ __forceinline__ FilterRef pick(const FilterSet &fs, uint32_t i) {
   FilterRef r = fs.f[0];
@@ -46,6 +76,52 @@ __device__ __forceinline__ FilterRef pick(const FilterSet &fs, uint32_t i) {
   for (int j = 1; j < kMaxFilters; j++)
     if (i == static_cast<uint32_t>(j)) r = fs.f[j];
   return r;
+}
+
+// The filter hash of an int32 key: the same value as hash_key on its
+// sign-extended image, with the sign correction done by a mask instead of
+// a second full multiply.
+__device__ __forceinline__ void hash_key32(uint32_t lo, uint32_t &h1, uint32_t &h2) {
+  constexpr uint32_t a_lo = static_cast<uint32_t>(kHashMul);
+  constexpr uint32_t a_hi = static_cast<uint32_t>(kHashMul >> 32);
+  const uint64_t p = static_cast<uint64_t>(lo) * a_lo;
+  const uint32_t fix = static_cast<uint32_t>(static_cast<int32_t>(lo) >> 31) & (0u - a_lo);
+  const uint32_t hi = static_cast<uint32_t>(p >> 32) + lo * a_hi + fix;
+  uint32_t t = static_cast<uint32_t>(p) ^ hi;
+  t ^= t >> 16;
+  h1 = hi;
+  h2 = t * kMixMul;
+}
+
+__device__ __forceinline__ void hash_parts(uint32_t lo, uint32_t hi, bool key64, uint32_t &h1,
+                                           uint32_t &h2) {
+  if (key64)
+    hash_key((static_cast<uint64_t>(hi) << 32) | lo, h1, h2);
+  else
+    hash_key32(lo, h1, h2);
+}
+
+// Set the k bits of a key. The test read bypasses the per-CU cache so it
+// sees bits other workgroups have set; bits only go from 0 to 1 during a
+// build, so a stale read costs an extra atomic, never a lost bit.
+template <int B, int K>
+__device__ __forceinline__ void insert_bits(uint32_t *words, uint32_t nb, uint32_t k, uint32_t h1,
+                                            uint32_t h2) {
+  using S = BlockShape<B>;
+  uint32_t *blk = words + static_cast<uint64_t>(block_of(h1, nb)) * S::kWords;
+  const uint32_t g1 = h2 >> (32 - S::kLog2);
+  const uint32_t g2 = ((h2 >> (32 - 2 * S::kLog2)) & (B - 1)) | 1u;
+  uint32_t pos = g1;
+  const uint32_t kk = K > 0 ? static_cast<uint32_t>(K) : k;
+#pragma unroll
+  for (uint32_t i = 0; i < kk; i++) {
+    const uint32_t p = pos & (B - 1);
+    const uint32_t bit = 1u << (p & 31);
+    uint32_t *w = blk + (p >> 5);
+    if ((__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit) == 0)
+      atomicOr(w, bit);
+    pos += g2;
+  }
 }
 
 // ------------------------------------------------------------------ zero
@@ -56,7 +132,21 @@ __global__ void __launch_bounds__(kThreads) k_zero_u64(uint64_t *p, uint64_t n) 
     p[i] = 0;
 }
 
+// All rows selected: the bitmap of a table without predicates.
+__global__ void __launch_bounds__(kThreads)
+    k_fill_all(uint64_t *bitmap, uint64_t n_rows, uint64_t *count) {
+  const uint64_t n_words = (n_rows + 63) / 64;
+  for (uint64_t w = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; w < n_words;
+       w += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    bitmap[w] = tail_mask(w, n_words, n_rows);
+  if (count && blockIdx.x == 0 && threadIdx.x == 0) *count = n_rows;
+}
+
 // ---------------------------------------------------------- local filter
+//
+// Each wave takes 64 consecutive words (4096 rows), builds word j with the
+// ballot of iteration j, keeps it in lane j, and stores the 64 words with
+// one coalesced store.
 
 __device__ __forceinline__ bool pred_holds(uint32_t op, int64_t v, int64_t lo, int64_t hi) {
   switch (op) {
@@ -76,154 +166,325 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ unsigned long long s_cnt;
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
-  const uint64_t lane = lane_id();
+  const uint32_t lane = lane_id();
   const uint64_t n_words = (n_rows + 63) / 64;
   uint64_t cnt = 0;
-  for (uint64_t w = global_wave(); w < n_words; w += wave_count()) {
-    const uint64_t row = w * 64 + lane;
-    bool keep = row < n_rows;
-    if (ps.and_into) keep = keep && ((bitmap[w] >> lane) & 1);
+  for (uint64_t seg = global_wave(); seg * 64 < n_words; seg += wave_count()) {
+    uint64_t mine = 0;
+    const uint32_t n_j = static_cast<uint32_t>(n_words - seg * 64 < 64 ? n_words - seg * 64 : 64);
+    for (uint32_t j = 0; j < n_j; j++) {
+      const uint64_t w = seg * 64 + j;
+      const uint64_t row = w * 64 + lane;
+      const uint64_t r = row < n_rows ? row : n_rows - 1;
+      bool keep = row < n_rows;
+      if (ps.and_into) keep = keep && ((uniform64(bitmap[w]) >> lane) & 1);
 #pragma unroll
-    for (int i = 0; i < kMaxPreds; i++) {
-      if (i < static_cast<int>(ps.n) && keep) {
-        const PredRef &p = ps.p[i];
-        const int64_t v = static_cast<int64_t>(load_key(p.col, p.col64, row));
-        keep = pred_holds(p.op, v, p.lo, p.hi);
+      for (int i = 0; i < kMaxPreds; i++) {
+        if (i < static_cast<int>(ps.n)) {
+          const PredRef &p = ps.p[i];
+          const int64_t v = static_cast<int64_t>(load_key(p.col, p.col64, r));
+          keep = keep && pred_holds(p.op, v, p.lo, p.hi);
+        }
       }
+      const uint64_t m = __ballot(keep);
+      if (lane == j) mine = m;
     }
-    const uint64_t word = __ballot(keep);
-    if (lane == 0) bitmap[w] = word;
-    cnt += __popcll(word);
+    const uint64_t w = seg * 64 + lane;
+    if (w < n_words) bitmap[w] = mine;
+    cnt += __popcll(mine);
   }
-  block_count_add(cnt, &s_cnt, count);
+  block_count_add(static_cast<int64_t>(wave_sum(cnt)), &s_cnt, count);
 }
 
 // ------------------------------------------------------------------ probe
 //
 // One scan of the table probes every incoming filter (the incoming half of
-// the filter transformation). Each workgroup first copies the filters that
-// fit into its LDS (in filter order, by their current size), then streams
-// U bitmap words per wave per iteration: all key columns of the alive rows
-// are loaded before any test so every load of the iteration is in flight at
-// once.
+// the filter transformation). At start each workgroup:
+//   - orders the filters by their estimated pass rate (builder rows kept /
+//     builder rows), most selective first - the order cannot change the
+//     result, only the work;
+//   - copies all filters into its LDS when they fit together, else reads
+//     all of them from global memory (L2 / Infinity Cache / HBM).
+// Each wave then streams U bitmap words per iteration: it loads every key
+// column of those rows, tests the first filter on all of them, and, when
+// at most 64 rows survive, compacts the survivors (word, lane and
+// remaining keys) into its LDS slice so that one fully occupied wave
+// instruction stream tests them against the remaining filters. Failures are
+// folded back into the group's words through an LDS mask, and every word is
+// stored once. Groups with more survivors test the remaining filters on the
+// words directly.
 
-template <int B, int K, bool ANY64>
-__global__ void __launch_bounds__(kProbeThreads)
-    k_probe(FilterSet fs, uint32_t k, uint64_t n_rows, uint64_t *__restrict__ bitmap,
-            unsigned long long *count, uint32_t lds_cap_words) {
-  extern __shared__ uint32_t lds[];
+struct Slot {
+  const void *keys;
+  const uint32_t *words;
+  uint32_t nb;
+  uint32_t key64;
+};
+
+template <int B, int K, bool STAGED>
+__device__ __forceinline__ bool slot_has(const Slot &s, const uint32_t *lds_filter, uint32_t h1,
+                                         uint32_t h2, uint32_t k) {
   constexpr int W = BlockShape<B>::kWords;
-  constexpr int U = ANY64 ? 4 : 8;
-  __shared__ uint32_t s_nb[kMaxProbe];
-  __shared__ uint32_t s_off[kMaxProbe];
-  __shared__ uint32_t s_staged[kMaxProbe];
-  __shared__ unsigned long long s_cnt;
+  const uint32_t blk = block_of(h1, s.nb);
+  if (STAGED) return block_has<B, K>(lds_filter + blk * W, h2, k);
+  return block_has<B, K>(s.words + static_cast<uint64_t>(blk) * W, h2, k);
+}
 
-  if (threadIdx.x == 0) {
-    uint64_t off = 0;
-#pragma unroll
-    for (int i = 0; i < kMaxProbe; i++) {
-      if (i < static_cast<int>(fs.n)) {
-        const uint32_t nb = clamp_blocks(*fs.f[i].nb, fs.f[i].cap_words / W);
-        const uint64_t need = static_cast<uint64_t>(nb) * W;
-        const bool st = off + need <= lds_cap_words;
-        s_nb[i] = nb;
-        s_off[i] = static_cast<uint32_t>(off);
-        s_staged[i] = st;
-        if (st) off += need;
-      }
-    }
-    s_cnt = 0;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < kMaxProbe; i++) {
-    if (i < static_cast<int>(fs.n) && s_staged[i]) {
-      const uint32_t n = s_nb[i] * W;
-      const uint32_t *src = fs.f[i].words;
-      uint32_t *dst = lds + s_off[i];
-      for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) dst[j] = src[j];
-    }
-  }
-  __syncthreads();
+template <bool ANY64>
+constexpr int probe_group_words() {
+  return ANY64 ? 4 : 8;
+}
 
-  uint32_t nb[kMaxProbe], off[kMaxProbe];
-  bool staged[kMaxProbe];
-#pragma unroll
-  for (int i = 0; i < kMaxProbe; i++) {
-    nb[i] = i < static_cast<int>(fs.n) ? s_nb[i] : 0;
-    off[i] = i < static_cast<int>(fs.n) ? s_off[i] : 0;
-    staged[i] = i < static_cast<int>(fs.n) ? s_staged[i] != 0 : false;
-  }
+// 32-bit words of one wave's LDS slice: compacted survivors (word-and-lane
+// tag, remaining keys) plus one 64-bit failure mask per word of the group.
+template <bool ANY64>
+constexpr int probe_slice_words() {
+  return kWave * (1 + (kMaxProbe - 1) * (ANY64 ? 2 : 1)) + 2 * probe_group_words<ANY64>();
+}
 
-  const uint64_t lane = lane_id();
+template <int B, int K, bool ANY64, bool STAGED>
+__device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe],
+                                              const uint32_t (&lds_off)[kMaxProbe], uint32_t n_f,
+                                              uint32_t k, uint64_t n_rows, uint64_t *bitmap,
+                                              uint32_t input_all, const uint32_t *lds_filters,
+                                              uint32_t *slice) {
+  constexpr int U = probe_group_words<ANY64>();
+  constexpr int kRest = kMaxProbe - 1;
+  uint32_t *q_tag = slice;                                          // [kWave]
+  uint32_t *q_lo = slice + kWave;                                   // [kRest][kWave]
+  uint32_t *q_hi = slice + kWave * (1 + kRest);                     // [kRest][kWave] (int64)
+  unsigned long long *fail_mask = reinterpret_cast<unsigned long long *>(
+      slice + kWave * (1 + kRest * (ANY64 ? 2 : 1)));               // [U]
+  const uint32_t lane = lane_id();
   const uint64_t n_words = (n_rows + 63) / 64;
   const uint64_t stride = wave_count() * U;
-  uint64_t cnt = 0;
+  int64_t cnt = 0;
+
   for (uint64_t w0 = global_wave() * U; w0 < n_words; w0 += stride) {
+    // The group's U words: lane u loads word w0 + u (one load), then every
+    // lane reads them back as scalars.
+    uint64_t mine = 0;
+    if (!input_all) {
+      const uint64_t wl = w0 + (lane < U ? lane : 0);
+      mine = bitmap[wl < n_words ? wl : n_words - 1];
+    }
     uint64_t word[U];
-    bool alive[U];
     uint64_t any = 0;
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      const uint64_t w = w0 + u;
-      word[u] = w < n_words ? bitmap[w] : 0;
-      alive[u] = ((word[u] >> lane) & 1) && (w * 64 + lane) < n_rows;
+      const uint64_t m = tail_mask(w0 + u, n_words, n_rows);
+      // readlane returns int: widen through uint32_t (no sign extension)
+      const uint32_t b_hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(mine >> 32), u);
+      const uint32_t b_lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(mine), u);
+      const uint64_t b = (static_cast<uint64_t>(b_hi) << 32) | b_lo;
+      word[u] = input_all ? m : (b & m);
       any |= word[u];
     }
     if (any == 0) continue;
 
+    // Every key column of the group, for every lane, in straight-line code so
+    // that all loads of the group are in flight together. Rows past the end
+    // are clamped; slots past n_f read slot 0's column again (cache hits).
+    // Offsets are 32-bit from a per-group scalar base.
+    const uint64_t base_row = w0 * 64;
+    const uint64_t left = n_rows - 1 - base_row;  // rows left after base_row (>= 0)
+    const uint32_t last = left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu;
+    uint32_t rel[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) rel[u] = min(static_cast<uint32_t>(u * 64) + lane, last);
     uint32_t lo[kMaxProbe][U];
     uint32_t hi[ANY64 ? kMaxProbe : 1][U];
 #pragma unroll
-    for (int i = 0; i < kMaxProbe; i++) {
-      if (i < static_cast<int>(fs.n)) {
+    for (int s = 0; s < kMaxProbe; s++) {
+      if (ANY64 && sl[s].key64) {
+        const uint64_t *col = static_cast<const uint64_t *>(sl[s].keys) + base_row;
 #pragma unroll
         for (int u = 0; u < U; u++) {
-          if (alive[u]) {
-            const uint64_t row = (w0 + u) * 64 + lane;
-            if (ANY64 && fs.f[i].key64) {
-              const uint64_t x = static_cast<const uint64_t *>(fs.f[i].keys)[row];
-              lo[i][u] = static_cast<uint32_t>(x);
-              hi[ANY64 ? i : 0][u] = static_cast<uint32_t>(x >> 32);
-            } else {
-              const int32_t x = static_cast<const int32_t *>(fs.f[i].keys)[row];
-              lo[i][u] = static_cast<uint32_t>(x);
-              if (ANY64) hi[ANY64 ? i : 0][u] = static_cast<uint32_t>(x >> 31);
+          const uint64_t x = col[rel[u]];
+          lo[s][u] = static_cast<uint32_t>(x);
+          hi[ANY64 ? s : 0][u] = static_cast<uint32_t>(x >> 32);
+        }
+      } else {
+        const int32_t *col = static_cast<const int32_t *>(sl[s].keys) + base_row;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const int32_t x = col[rel[u]];
+          lo[s][u] = static_cast<uint32_t>(x);
+          if (ANY64) hi[ANY64 ? s : 0][u] = static_cast<uint32_t>(x >> 31);
+        }
+      }
+    }
+
+    // The first (most selective) filter on every row of the group.
+    uint64_t m0[U];
+    uint32_t total = 0;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      uint32_t h1, h2;
+      hash_parts(lo[0][u], ANY64 ? hi[0][u] : 0, ANY64 && sl[0].key64, h1, h2);
+      const bool ok = slot_has<B, K, STAGED>(sl[0], lds_filters + lds_off[0], h1, h2, k);
+      m0[u] = __ballot(ok && ((word[u] >> lane) & 1));
+      total += __popcll(m0[u]);
+    }
+
+    if (n_f > 1 && total > kWave) {
+      // Many survivors: test the remaining filters on the words themselves.
+#pragma unroll
+      for (int s = 1; s < kMaxProbe; s++) {
+        if (s < static_cast<int>(n_f)) {
+#pragma unroll
+          for (int u = 0; u < U; u++) {
+            if (m0[u]) {
+              uint32_t h1, h2;
+              hash_parts(lo[s][u], ANY64 ? hi[ANY64 ? s : 0][u] : 0, ANY64 && sl[s].key64, h1, h2);
+              const bool ok = slot_has<B, K, STAGED>(sl[s], lds_filters + lds_off[s], h1, h2, k);
+              m0[u] = __ballot(ok && ((m0[u] >> lane) & 1));
             }
           }
         }
       }
+    } else if (n_f > 1 && total > 0) {
+      // Few survivors: compact them into the LDS slice, one lane each.
+      uint32_t pos0 = 0;
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        if (lane == 0) fail_mask[u] = 0;
+        if ((m0[u] >> lane) & 1) {
+          const uint32_t pos = pos0 + __popcll(m0[u] & ((1ull << lane) - 1));
+          q_tag[pos] = (static_cast<uint32_t>(u) << 6) | lane;
+#pragma unroll
+          for (int s = 1; s < kMaxProbe; s++) {
+            if (s < static_cast<int>(n_f)) {
+              q_lo[(s - 1) * kWave + pos] = lo[s][u];
+              if (ANY64) q_hi[(s - 1) * kWave + pos] = hi[ANY64 ? s : 0][u];
+            }
+          }
+        }
+        pos0 += __popcll(m0[u]);
+      }
+      // The LDS accesses of one wave execute in program order; the wave
+      // barrier only keeps the compiler from moving them across.
+      __builtin_amdgcn_wave_barrier();
+      const bool act = lane < total;
+      const uint32_t idx = act ? lane : 0;
+      bool ok = act;
+#pragma unroll
+      for (int s = 1; s < kMaxProbe; s++) {
+        if (s < static_cast<int>(n_f)) {
+          const uint32_t klo = q_lo[(s - 1) * kWave + idx];
+          const uint32_t khi = ANY64 ? q_hi[(s - 1) * kWave + idx] : 0;
+          uint32_t h1, h2;
+          hash_parts(klo, khi, ANY64 && sl[s].key64, h1, h2);
+          ok = ok && slot_has<B, K, STAGED>(sl[s], lds_filters + lds_off[s], h1, h2, k);
+        }
+      }
+      if (act && !ok) {
+        const uint32_t tag = q_tag[idx];
+        atomicOr(&fail_mask[tag >> 6], 1ull << (tag & 63));
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int u = 0; u < U; u++) m0[u] &= ~uniform64(fail_mask[u]);
+      __builtin_amdgcn_wave_barrier();
     }
+
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint64_t w = w0 + u;
+      if (lane == 0 && w < n_words) bitmap[w] = m0[u];
+      cnt += __popcll(m0[u]);
+    }
+  }
+  return cnt;
+}
+
+template <int B, int K, bool ANY64>
+__global__ void __launch_bounds__(kProbeThreads)
+    k_probe(FilterSet fs, uint32_t k, uint64_t n_rows, uint64_t *__restrict__ bitmap,
+            unsigned long long *count, uint32_t lds_filter_words, uint32_t input_all) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  constexpr int W = BlockShape<B>::kWords;
+  constexpr int kSliceWords = probe_slice_words<ANY64>();
+  __shared__ uint32_t s_ord[kMaxProbe];
+  __shared__ uint32_t s_nb[kMaxProbe];
+  __shared__ uint32_t s_off[kMaxProbe];
+  __shared__ uint32_t s_staged;
+  __shared__ unsigned long long s_cnt;
+
+  const uint32_t n_f = fs.n;
+  if (threadIdx.x == 0) {
+    uint32_t ord[kMaxProbe];
+    uint64_t sel[kMaxProbe], rows[kMaxProbe];
 #pragma unroll
     for (int i = 0; i < kMaxProbe; i++) {
-      if (i < static_cast<int>(fs.n)) {
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-          if (alive[u]) {
-            uint64_t x;
-            if (ANY64)
-              x = (static_cast<uint64_t>(hi[ANY64 ? i : 0][u]) << 32) | lo[i][u];
-            else
-              x = static_cast<uint64_t>(static_cast<int64_t>(static_cast<int32_t>(lo[i][u])));
-            uint32_t h1, h2;
-            hash_key(x, h1, h2);
-            const uint32_t blk = block_of(h1, nb[i]);
-            if (staged[i])
-              alive[u] = block_has<B, K>(lds + off[i] + blk * W, h2, k);
-            else
-              alive[u] = block_has<B, K>(fs.f[i].words + static_cast<uint64_t>(blk) * W, h2, k);
-          }
+      ord[i] = i;
+      sel[i] = 1;
+      rows[i] = 1;
+      if (i < static_cast<int>(n_f)) {
+        if (fs.f[i].sel && fs.f[i].rows) {
+          sel[i] = *fs.f[i].sel;
+          rows[i] = fs.f[i].rows;
         }
       }
     }
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const uint64_t out = __ballot(alive[u]);
-      if (lane == 0 && w0 + u < n_words) bitmap[w0 + u] = out;
-      cnt += __popcll(out);
+    // stable insertion sort by sel / rows
+    for (uint32_t a = 1; a < n_f; a++) {
+      for (uint32_t b = a; b > 0; b--) {
+        const uint32_t x = ord[b - 1], y = ord[b];
+        if (sel[y] * rows[x] < sel[x] * rows[y]) {
+          ord[b - 1] = y;
+          ord[b] = x;
+        } else {
+          break;
+        }
+      }
+    }
+    uint64_t need = 0;
+    for (uint32_t j = 0; j < n_f; j++) {
+      const FilterRef f = pick(fs, ord[j]);
+      const uint32_t nb = clamp_blocks(*f.nb, f.cap_words / W);
+      s_ord[j] = ord[j];
+      s_nb[j] = nb;
+      s_off[j] = static_cast<uint32_t>(need);
+      need += static_cast<uint64_t>(nb) * W;
+    }
+    s_staged = need <= lds_filter_words;
+    s_cnt = 0;
+  }
+  __syncthreads();
+  const bool staged = s_staged != 0;
+  if (staged) {
+    for (uint32_t j = 0; j < n_f; j++) {
+      const uint32_t n = s_nb[j] * W;
+      const uint32_t *src = pick(fs, s_ord[j]).words;
+      uint32_t *dst = lds + s_off[j];
+      for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
     }
   }
+  __syncthreads();
+
+  // Slot j is filter s_ord[j]; slots past n_f repeat slot 0 (never tested).
+  Slot sl[kMaxProbe];
+  uint32_t off[kMaxProbe];
+#pragma unroll
+  for (int j = 0; j < kMaxProbe; j++) {
+    const uint32_t jj = j < static_cast<int>(n_f) ? j : 0;
+    const FilterRef f = pick(fs, __builtin_amdgcn_readfirstlane(s_ord[jj]));
+    sl[j].keys = f.keys;
+    sl[j].words = f.words;
+    sl[j].nb = __builtin_amdgcn_readfirstlane(s_nb[jj]);
+    sl[j].key64 = f.key64;
+    off[j] = __builtin_amdgcn_readfirstlane(s_off[jj]);
+  }
+  // The per-wave slices follow the filters; lds_filter_words is even, so
+  // each slice's 64-bit failure masks stay 8-byte aligned.
+  uint32_t *slice =
+      lds + lds_filter_words + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) * kSliceWords;
+  int64_t cnt;
+  if (staged)
+    cnt = probe_loop<B, K, ANY64, true>(sl, off, n_f, k, n_rows, bitmap, input_all, lds, slice);
+  else
+    cnt = probe_loop<B, K, ANY64, false>(sl, off, n_f, k, n_rows, bitmap, input_all, lds, slice);
   block_count_add(cnt, &s_cnt, count);
 }
 
@@ -254,28 +515,66 @@ __global__ void __launch_bounds__(kThreads)
 //
 // The outgoing half of the filter transformation: every selected row's key
 // is inserted into each outgoing filter by atomic OR (order-free, so the
-// filter bits do not depend on scheduling).
+// filter bits do not depend on scheduling). A wave takes 64 bitmap words;
+// a sparse group is walked lane by lane (each lane pops the set bits of its
+// own word), a dense one word by word (lanes = rows, coalesced key loads),
+// whichever needs fewer steps.
+
+template <int B, int K>
+__device__ __forceinline__ void insert_row(const FilterSet &fs, const uint32_t (&nb)[kMaxFilters],
+                                          uint32_t k, uint64_t row) {
+#pragma unroll
+  for (int i = 0; i < kMaxFilters; i++) {
+    if (i < static_cast<int>(fs.n)) {
+      uint32_t h1, h2;
+      if (fs.f[i].key64) {
+        hash_key(static_cast<const uint64_t *>(fs.f[i].keys)[row], h1, h2);
+      } else {
+        hash_key32(static_cast<uint32_t>(static_cast<const int32_t *>(fs.f[i].keys)[row]), h1, h2);
+      }
+      insert_bits<B, K>(fs.f[i].words, nb[i], k, h1, h2);
+    }
+  }
+}
 
 template <int B, int K>
 __global__ void __launch_bounds__(kThreads)
-    k_build(FilterSet fs, uint32_t k, uint64_t n_rows, const uint64_t *__restrict__ bitmap) {
+    k_build(FilterSet fs, uint32_t k, uint64_t n_rows, const uint64_t *__restrict__ bitmap,
+            uint32_t seg_words) {
   uint32_t nb[kMaxFilters];
 #pragma unroll
   for (int i = 0; i < kMaxFilters; i++)
     nb[i] = i < static_cast<int>(fs.n)
                 ? clamp_blocks(*fs.f[i].nb, fs.f[i].cap_words / BlockShape<B>::kWords)
-                : 0;
-  const uint64_t lane = lane_id();
+                : 1;
+  const uint32_t lane = lane_id();
   const uint64_t n_words = (n_rows + 63) / 64;
-  for (uint64_t w = global_wave(); w < n_words; w += wave_count()) {
-    const uint64_t row = w * 64 + lane;
-    const uint64_t word = bitmap ? bitmap[w] : ~0ull;
-    if (word == 0) continue;
-    if (!(((word >> lane) & 1) && row < n_rows)) continue;
-#pragma unroll
-    for (int i = 0; i < kMaxFilters; i++) {
-      if (i < static_cast<int>(fs.n))
-        insert_global<B, K>(fs.f[i].words, nb[i], k, load_key(fs.f[i].keys, fs.f[i].key64, row));
+  // A wave takes seg_words (1..64) consecutive words, so that small tables
+  // still spread over many waves; lane l holds word l of the segment.
+  for (uint64_t seg = global_wave(); seg * seg_words < n_words; seg += wave_count()) {
+    const uint64_t w = seg * seg_words + lane;
+    uint64_t word = lane < seg_words ? tail_mask(w, n_words, n_rows) : 0;
+    if (bitmap && lane < seg_words && w < n_words) word &= bitmap[w];
+    const uint64_t nonzero = __ballot(word != 0);
+    if (nonzero == 0) continue;
+    const uint32_t steps_sparse = wave_max(__popcll(word));
+    const uint32_t steps_dense = __popcll(nonzero);
+    if (steps_sparse <= steps_dense) {
+      while (__ballot(word != 0)) {
+        if (word) {
+          const uint32_t b = __ffsll(static_cast<unsigned long long>(word)) - 1;
+          word &= word - 1;
+          insert_row<B, K>(fs, nb, k, w * 64 + b);
+        }
+      }
+    } else {
+      uint64_t todo = nonzero;
+      while (todo) {
+        const uint32_t j = __ffsll(static_cast<unsigned long long>(todo)) - 1;
+        todo &= todo - 1;
+        const uint64_t wj = __shfl(word, j);
+        if ((wj >> lane) & 1) insert_row<B, K>(fs, nb, k, (seg * seg_words + j) * 64 + lane);
+      }
     }
   }
 }
@@ -298,11 +597,6 @@ __global__ void k_copy_counts(const uint64_t *src, SlotTable t, uint32_t n, uint
 // rescans its words and writes the set rows' ids in ascending order.
 
 constexpr uint64_t kCompactWordsPerBlock = 1024;  // 4 words per thread
-
-// Bits of word w that belong to rows below n_rows.
-__device__ __forceinline__ uint64_t tail_mask(uint64_t w, uint64_t n_words, uint64_t n_rows) {
-  return (w + 1 == n_words && (n_rows & 63)) ? (1ull << (n_rows & 63)) - 1 : ~0ull;
-}
 
 __device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *s, uint64_t &total) {
   const uint32_t t = threadIdx.x;
@@ -394,7 +688,7 @@ hipError_t by_block_bits(uint32_t block_bits, F &&f) {
 uint32_t grid_for(uint64_t waves_of_work, uint32_t threads, uint32_t per_cu) {
   const uint64_t blocks = (waves_of_work * kWave + threads - 1) / threads;
   const uint64_t cap = static_cast<uint64_t>(device_info().n_cu) * per_cu;
-  uint64_t g = blocks < cap ? blocks : cap;
+  const uint64_t g = blocks < cap ? blocks : cap;
   return static_cast<uint32_t>(g == 0 ? 1 : g);
 }
 
@@ -407,20 +701,28 @@ hipError_t launch_zero_u64(uint64_t *p, uint64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_fill_all(uint64_t *bitmap, uint64_t n_rows, uint64_t *count, hipStream_t s) {
+  const uint64_t n_words = (n_rows + 63) / 64;
+  const uint32_t grid = grid_for((n_words + 63) / 64, kThreads, 8);
+  hipLaunchKernelGGL(k_fill_all, dim3(grid), dim3(kThreads), 0, s, n_words ? bitmap : nullptr, n_rows,
+                     count);
+  return hipGetLastError();
+}
+
 hipError_t launch_local_filter(const PredSet &preds, uint64_t n_rows, uint64_t *bitmap,
                                uint64_t *count, hipStream_t s) {
   const uint64_t n_words = (n_rows + 63) / 64;
   if (n_words == 0) return hipSuccess;
-  const uint32_t grid = grid_for(n_words, kThreads, 8);
+  const uint32_t grid = grid_for((n_words + 63) / 64, kThreads, 8);
   hipLaunchKernelGGL(k_local, dim3(grid), dim3(kThreads), 0, s, preds, n_rows, bitmap,
                      reinterpret_cast<unsigned long long *>(count));
   return hipGetLastError();
 }
 
 hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,
-                        uint64_t *bitmap, uint64_t *count, hipStream_t s) {
+                        uint64_t *bitmap, uint64_t *count, bool input_all, hipStream_t s) {
   const uint64_t n_words = (n_rows + 63) / 64;
-  if (n_words == 0) return hipSuccess;
+  if (n_words == 0 || fs.n == 0) return hipSuccess;
   bool any64 = false;
   uint64_t want_words = 0;
   for (uint32_t i = 0; i < fs.n; i++) {
@@ -428,15 +730,19 @@ hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, ui
     want_words += fs.f[i].cap_words;
   }
   const DeviceInfo &di = device_info();
+  const uint64_t queue_bytes = static_cast<uint64_t>(kProbeWaves) * 4 *
+                               (any64 ? probe_slice_words<true>() : probe_slice_words<false>());
   // Leave room for the kernel's own static LDS (a few dozen bytes).
-  const uint64_t budget = static_cast<uint64_t>(di.max_lds_block) - 1024;
-  uint64_t lds_bytes = want_words * 4;
-  if (lds_bytes > budget) lds_bytes = budget;
-  const uint32_t per_cu = lds_bytes * 2 <= budget ? 2 : 1;
+  const uint64_t lds_max = static_cast<uint64_t>(di.max_lds_block) - 1024;
+  uint64_t filter_bytes = lds_max > queue_bytes ? lds_max - queue_bytes : 0;
+  if (filter_bytes > want_words * 4) filter_bytes = want_words * 4;
+  const uint64_t lds_bytes = filter_bytes + queue_bytes;
+  const uint32_t per_cu = lds_bytes * 2 <= lds_max ? 2 : 1;
   const int U = any64 ? 4 : 8;
   const uint32_t grid = grid_for((n_words + U - 1) / U, kProbeThreads, per_cu);
-  const uint32_t cap_words = static_cast<uint32_t>(lds_bytes / 4);
+  const uint32_t filter_words = static_cast<uint32_t>(filter_bytes / 8) * 2;  // keep slices 8-byte aligned
   auto *cnt = reinterpret_cast<unsigned long long *>(count);
+  const uint32_t all = input_all ? 1u : 0u;
   return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
     constexpr int B = decltype(bb)::value;
     auto launch = [&](auto kern) -> hipError_t {
@@ -445,7 +751,7 @@ hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, ui
                                          static_cast<int>(lds_bytes));
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(kern, dim3(grid), dim3(kProbeThreads), lds_bytes, s, fs, k, n_rows,
-                         bitmap, cnt, cap_words);
+                         bitmap, cnt, filter_words, all);
       return hipGetLastError();
     };
     if (k == 3) return any64 ? launch(k_probe<B, 3, true>) : launch(k_probe<B, 3, false>);
@@ -457,7 +763,8 @@ hipError_t launch_size_zero(uint32_t block_bits, uint32_t bits_per_key, const Fi
                             const uint64_t *count, uint64_t n_rows, hipStream_t s) {
   if (fs.n == 0) return hipSuccess;
   uint64_t max_words = 0;
-  for (uint32_t i = 0; i < fs.n; i++) max_words = fs.f[i].cap_words > max_words ? fs.f[i].cap_words : max_words;
+  for (uint32_t i = 0; i < fs.n; i++)
+    max_words = fs.f[i].cap_words > max_words ? fs.f[i].cap_words : max_words;
   uint64_t gx = (max_words + kThreads * 4 - 1) / (kThreads * 4);
   const uint64_t cap = static_cast<uint64_t>(device_info().n_cu) * 2;
   if (gx > cap) gx = cap;
@@ -471,13 +778,20 @@ hipError_t launch_build(uint32_t block_bits, uint32_t k, const FilterSet &fs, ui
                         const uint64_t *bitmap, hipStream_t s) {
   const uint64_t n_words = (n_rows + 63) / 64;
   if (n_words == 0 || fs.n == 0) return hipSuccess;
-  const uint32_t grid = grid_for(n_words, kThreads, 8);
+  // Words per wave: enough waves to cover the device several times over.
+  const uint64_t target_waves = static_cast<uint64_t>(device_info().n_cu) * 32;
+  uint64_t seg = (n_words + target_waves - 1) / target_waves;
+  seg = seg < 1 ? 1 : (seg > 64 ? 64 : seg);
+  const uint32_t grid = grid_for((n_words + seg - 1) / seg, kThreads, 8);
+  const uint32_t seg_words = static_cast<uint32_t>(seg);
   return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
     constexpr int B = decltype(bb)::value;
     if (k == 3)
-      hipLaunchKernelGGL((k_build<B, 3>), dim3(grid), dim3(kThreads), 0, s, fs, k, n_rows, bitmap);
+      hipLaunchKernelGGL((k_build<B, 3>), dim3(grid), dim3(kThreads), 0, s, fs, k, n_rows, bitmap,
+                         seg_words);
     else
-      hipLaunchKernelGGL((k_build<B, 0>), dim3(grid), dim3(kThreads), 0, s, fs, k, n_rows, bitmap);
+      hipLaunchKernelGGL((k_build<B, 0>), dim3(grid), dim3(kThreads), 0, s, fs, k, n_rows, bitmap,
+                         seg_words);
     return hipGetLastError();
   });
 }

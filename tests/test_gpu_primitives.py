@@ -126,6 +126,37 @@ def test_probe_matches(pt, B, k, n):
     assert int(cnt.item()) == rcnt
 
 
+@pytest.mark.parametrize("first_pass", [1.0, 0.5, 0.05, 0.0])
+def test_probe_first_filter_pass_rates(pt, first_pass):
+    """The first filter passing everything, half, few or none of the rows
+    (queue overflow, queue, and empty paths of the probe), with int32 and
+    int64 columns mixed in one launch."""
+    rng = np.random.default_rng(int(first_pass * 100))
+    n = 777_777
+    p = pt.params()
+    domain = 100_000
+    cols = [rng.integers(0, domain, n).astype(np.int32), rng.integers(0, domain, n).astype(np.int64),
+            rng.integers(0, domain, n).astype(np.int32)]
+    members = [np.arange(int(domain * first_pass), dtype=np.int32),
+               rng.integers(0, domain, domain // 3).astype(np.int64),
+               rng.integers(0, domain, domain // 2).astype(np.int32)]
+    filters, refs = [], []
+    for m in members:
+        f = pt.Bloom(max(1, len(m)), p)
+        pt.pt_bloom_build([dev(m)], [f], len(m))
+        filters.append(f)
+        refs.append(oracle.bloom_build(m, None, 512, 3, 10))
+    say("probe first pass", first_pass)
+    bm = bitmap_tensor(oracle.all_rows_bitmap(n))
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    pt.pt_bloom_probe([dev(c) for c in cols], filters, n, bm, cnt)
+    ref = oracle.all_rows_bitmap(n)
+    for c, (w, nb) in zip(cols, refs):
+        ref, rcnt = oracle.bloom_probe(c, w, nb, 512, 3, ref)
+    assert_bitmaps_equal(host_u64(bm), ref, "probe")
+    assert int(cnt.item()) == rcnt
+
+
 @pytest.mark.parametrize("n", SIZES + [65536 * 3 + 17])
 def test_compact(pt, n):
     rng = np.random.default_rng(n + 5)
