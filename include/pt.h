@@ -235,10 +235,11 @@ pt_status pt_transfer_filter(const pt_graph *graph, const pt_table *tables,
                              const pt_params *params, void *d_ws, uint32_t pass, uint32_t edge,
                              pt_bloom *out, uint32_t *builder);
 
-/* Kernel timing. While enabled on the calling thread, every launch of the
- * calls above is bracketed by HIP events recorded on the launch's own
- * stream. pt_profile_read waits for those events, copies up to `max` records
- * into `out`, sets *n to the number copied and clears the list. */
+/* Kernel timing. While enabled on the calling thread (on = 1: every launch
+ * of the calls above; on = 2: probe launches only; 0: off), each launch is
+ * bracketed by HIP events recorded on the launch's own stream.
+ * pt_profile_read waits for those events, copies up to `max` records into
+ * `out`, sets *n to the number copied and clears the list. */
 pt_status pt_profile_enable(int on);
 pt_status pt_profile_read(pt_kernel_time *out, uint32_t max, uint32_t *n);
 

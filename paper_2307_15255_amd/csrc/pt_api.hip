@@ -65,7 +65,7 @@ struct ProfRecord {
   hipEvent_t start, stop;
 };
 
-thread_local bool g_prof_on = false;
+thread_local int g_prof_mode = 0;  // 0 off, 1 every launch, 2 probe launches only
 thread_local std::vector<ProfRecord> g_prof;
 thread_local std::vector<hipEvent_t> g_event_pool;
 
@@ -86,7 +86,7 @@ class Timed {
   Timed(const char *name, uint32_t table, uint32_t pass, uint64_t rows, uint64_t bytes,
         hipStream_t s)
       : s_(s) {
-    if (!g_prof_on) return;
+    if (g_prof_mode == 0 || (g_prof_mode == 2 && std::strcmp(name, "probe") != 0)) return;
     rec_.t = pt_kernel_time{};
     std::snprintf(rec_.t.name, sizeof rec_.t.name, "%s", name);
     rec_.t.table = table;
@@ -194,6 +194,8 @@ struct Plan {
   uint64_t off_counts = 0;         // 3 * n_t uint64: local, forward, backward
   uint64_t off_nb = 0;             // 2 * n_e uint64: forward, backward filters
   std::vector<uint64_t> off_filter, cap_words;  // [pass * n_e + e]
+  uint64_t off_scratch = 0;                     // private filter copies of the builds
+  uint64_t scratch_words = 0;
   uint64_t total = 0;
 };
 
@@ -271,6 +273,30 @@ pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *
       off = align256(off + cap * 4);
     }
   }
+  // Scratch for the builds' private LDS copies: one copy per CU of the
+  // largest group of filters one table builds at once (capped at the LDS).
+  uint64_t group_words = 0;
+  for (uint32_t pass = 0; pass < 2; pass++) {
+    for (uint32_t v = 0; v < pl.n_t; v++) {
+      uint64_t w = 0;
+      uint32_t in_launch = 0;
+      for (uint32_t e = 0; e < pl.n_e; e++) {
+        if ((pass == 0 ? pl.src[e] : pl.dst[e]) != v) continue;
+        if (in_launch == kMaxFilters) {
+          group_words = std::max(group_words, w);
+          w = 0;
+          in_launch = 0;
+        }
+        w += pl.cap_words[pass * pl.n_e + e];
+        in_launch++;
+      }
+      group_words = std::max(group_words, w);
+    }
+  }
+  const uint64_t copy_words = std::min<uint64_t>(group_words, build_lds_words());
+  pl.off_scratch = off;
+  pl.scratch_words = copy_words * static_cast<uint64_t>(device_info().n_cu);
+  off = align256(off + pl.scratch_words * 4);
   pl.total = off;
   return PT_OK;
 }
@@ -291,7 +317,8 @@ const char *pt_version(void) { return "pt-mi355x 0.1 (gfx950)"; }
 const char *pt_last_error(void) { return g_error.c_str(); }
 
 pt_status pt_profile_enable(int on) {
-  g_prof_on = on != 0;
+  if (on < 0 || on > 2) return fail(PT_EINVAL, "pt_profile_enable: mode %d", on);
+  g_prof_mode = on;
   return PT_OK;
 }
 
@@ -360,7 +387,8 @@ pt_status pt_bloom_capacity(uint64_t max_keys, const pt_params *params, uint64_t
 
 static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
                                uint64_t n_rows, const uint64_t *d_bitmap, const uint64_t *d_count,
-                               hipStream_t s, uint32_t table, uint32_t pass) {
+                               uint32_t *scratch, uint64_t scratch_words, hipStream_t s,
+                               uint32_t table, uint32_t pass) {
   const pt_params &p = filters[0].params;
   for (uint32_t done = 0; done < n_filters;) {
     FilterSet fs{};
@@ -376,7 +404,9 @@ static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const 
       if (st != PT_OK) return st;
     }
     Timed tm("build", table, pass, n_rows, bytes, s);
-    pt_status st = check_hip(launch_build(p.block_bits, p.k, fs, n_rows, d_bitmap, s), "build launch");
+    pt_status st = check_hip(launch_build(p.block_bits, p.k, fs, n_rows, d_bitmap, scratch,
+                                          scratch_words, s),
+                             "build launch");
     if (st != PT_OK) return st;
   }
   return PT_OK;
@@ -385,13 +415,13 @@ static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const 
 // Probes n_filters filters in one scan per group of kMaxProbe. `sel` and
 // `rows` (optional) give each filter's builder count and row total, which
 // only order the tests. input_all: the bitmap holds every row and is not
-// read by the first launch.
+// read by the first launch. count_zeroed: *d_count already holds zero.
 static pt_status probe_filters(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
                                const uint64_t *const *sel, const uint64_t *rows, uint64_t n_rows,
                                uint64_t *d_bitmap, uint64_t *d_count, bool input_all,
-                               hipStream_t s, uint32_t table, uint32_t pass) {
+                               bool count_zeroed, hipStream_t s, uint32_t table, uint32_t pass) {
   const pt_params &p = filters[0].params;
-  if (d_count) {
+  if (d_count && !count_zeroed) {
     pt_status st = check_hip(launch_zero_u64(d_count, 1, s), "zero count");
     if (st != PT_OK) return st;
   }
@@ -431,7 +461,7 @@ pt_status pt_bloom_build(uint32_t n_filters, const pt_column *keys, const pt_blo
     if (st != PT_OK) return st;
   }
   return build_filters(n_filters, keys, filters, n_rows, d_bitmap, d_bitmap ? d_count : nullptr,
-                       reinterpret_cast<hipStream_t>(stream), 0, 0);
+                       nullptr, 0, reinterpret_cast<hipStream_t>(stream), 0, 0);
 }
 
 pt_status pt_bloom_probe(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
@@ -461,7 +491,7 @@ pt_status pt_bloom_probe(uint32_t n_filters, const pt_column *keys, const pt_blo
     return check_hip(launch_local_filter(ps, n_rows, d_bitmap, d_count, s), "count launch");
   }
   return probe_filters(n_filters, keys, filters, nullptr, nullptr, n_rows, d_bitmap, d_count, false,
-                       s, 0, 0);
+                       false, s, 0, 0);
 }
 
 pt_status pt_compact_workspace_size(uint64_t n_rows, size_t *bytes) {
@@ -617,7 +647,8 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
       if (!keys.empty()) {
         uint64_t *cnt = counts + (p + 1) * pl.n_t + v;
         st = probe_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), sel.data(),
-                           rows.data(), tb.n_rows, d_bitmaps[v], cnt, all_rows[v] != 0, s, v, p + 1);
+                           rows.data(), tb.n_rows, d_bitmaps[v], cnt, all_rows[v] != 0,
+                           /*count_zeroed=*/true, s, v, p + 1);
         if (st != PT_OK) return st;
         cur[v] = p + 1;
         all_rows[v] = 0;
@@ -635,7 +666,8 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
         const bool all = all_rows[v] != 0;
         st = build_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), tb.n_rows,
                            all ? nullptr : d_bitmaps[v], all ? nullptr : counts + cur[v] * pl.n_t + v,
-                           s, v, p + 1);
+                           reinterpret_cast<uint32_t *>(ws + pl.off_scratch), pl.scratch_words, s, v,
+                           p + 1);
         if (st != PT_OK) return st;
       }
     }

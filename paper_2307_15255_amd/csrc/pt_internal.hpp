@@ -61,8 +61,13 @@ hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, ui
                         uint64_t *bitmap, uint64_t *count, bool input_all, hipStream_t s);
 hipError_t launch_size_zero(uint32_t block_bits, uint32_t bits_per_key, const FilterSet &fs,
                             const uint64_t *count, uint64_t n_rows, hipStream_t s);
+// scratch (optional): room for private per-workgroup filter copies; with
+// it, filters that fit in LDS are built without global atomics.
 hipError_t launch_build(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,
-                        const uint64_t *bitmap, hipStream_t s);
+                        const uint64_t *bitmap, uint32_t *scratch, uint64_t scratch_words,
+                        hipStream_t s);
+// Words of LDS one build workgroup uses for its private filter copies.
+uint64_t build_lds_words();
 hipError_t launch_copy_counts(const uint64_t *src, const uint32_t *slot, uint32_t n,
                               uint64_t *dst, hipStream_t s);
 hipError_t launch_compact(const uint64_t *bitmap, uint64_t n_rows, uint32_t *idx, uint64_t *count,

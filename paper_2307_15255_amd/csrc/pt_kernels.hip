@@ -5,6 +5,9 @@
 // wave-uniform; per-lane work that does not matter (rows already removed,
 // rows past the end) is computed anyway on clamped, in-bounds addresses and
 // masked out, which keeps the exec mask full and the code straight-line.
+#include <map>
+#include <mutex>
+
 #include "pt_internal.hpp"
 
 namespace pt {
@@ -13,6 +16,7 @@ namespace {
 
 constexpr int kThreads = 256;        // local filter, build, size, compact
 constexpr int kProbeThreads = 1024;  // probe: sixteen waves per workgroup
+constexpr int kWideThreads = 1024;   // kernels that count: one workgroup (one atomic) per CU
 constexpr int kProbeWaves = kProbeThreads / kWave;
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
@@ -144,9 +148,10 @@ __global__ void __launch_bounds__(kThreads)
 
 // ---------------------------------------------------------- local filter
 //
-// Each wave takes 64 consecutive words (4096 rows), builds word j with the
-// ballot of iteration j, keeps it in lane j, and stores the 64 words with
-// one coalesced store.
+// Each wave takes seg_words (1..64) consecutive words, builds word j with the
+// ballot of step j, keeps it in lane j, and stores the segment with one
+// coalesced store. Eight words are evaluated per step so their loads
+// overlap.
 
 __device__ __forceinline__ bool pred_holds(uint32_t op, int64_t v, int64_t lo, int64_t hi) {
   switch (op) {
@@ -160,37 +165,49 @@ __device__ __forceinline__ bool pred_holds(uint32_t op, int64_t v, int64_t lo, i
   }
 }
 
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kWideThreads)
     k_local(PredSet ps, uint64_t n_rows, uint64_t *__restrict__ bitmap,
-            unsigned long long *count) {
+            unsigned long long *count, uint32_t seg_words) {
+  constexpr int T = 8;
   __shared__ unsigned long long s_cnt;
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
   const uint32_t lane = lane_id();
   const uint64_t n_words = (n_rows + 63) / 64;
   uint64_t cnt = 0;
-  for (uint64_t seg = global_wave(); seg * 64 < n_words; seg += wave_count()) {
+  for (uint64_t seg = global_wave(); seg * seg_words < n_words; seg += wave_count()) {
+    const uint64_t w_base = seg * seg_words;
+    const uint32_t n_j = static_cast<uint32_t>(n_words - w_base < seg_words ? n_words - w_base : seg_words);
     uint64_t mine = 0;
-    const uint32_t n_j = static_cast<uint32_t>(n_words - seg * 64 < 64 ? n_words - seg * 64 : 64);
-    for (uint32_t j = 0; j < n_j; j++) {
-      const uint64_t w = seg * 64 + j;
-      const uint64_t row = w * 64 + lane;
-      const uint64_t r = row < n_rows ? row : n_rows - 1;
-      bool keep = row < n_rows;
-      if (ps.and_into) keep = keep && ((uniform64(bitmap[w]) >> lane) & 1);
+    for (uint32_t j0 = 0; j0 < n_j; j0 += T) {
+      bool keep[T];
+      uint64_t r[T];
+#pragma unroll
+      for (int t = 0; t < T; t++) {
+        const uint64_t row = (w_base + j0 + t) * 64 + lane;
+        keep[t] = j0 + t < n_j && row < n_rows;
+        r[t] = row < n_rows ? row : n_rows - 1;
+        if (ps.and_into && j0 + t < n_j)
+          keep[t] = keep[t] && ((uniform64(bitmap[w_base + j0 + t]) >> lane) & 1);
+      }
 #pragma unroll
       for (int i = 0; i < kMaxPreds; i++) {
         if (i < static_cast<int>(ps.n)) {
           const PredRef &p = ps.p[i];
-          const int64_t v = static_cast<int64_t>(load_key(p.col, p.col64, r));
-          keep = keep && pred_holds(p.op, v, p.lo, p.hi);
+#pragma unroll
+          for (int t = 0; t < T; t++) {
+            const int64_t v = static_cast<int64_t>(load_key(p.col, p.col64, r[t]));
+            keep[t] = keep[t] && pred_holds(p.op, v, p.lo, p.hi);
+          }
         }
       }
-      const uint64_t m = __ballot(keep);
-      if (lane == j) mine = m;
+#pragma unroll
+      for (int t = 0; t < T; t++) {
+        const uint64_t m = __ballot(keep[t]);
+        if (lane == j0 + t) mine = m;
+      }
     }
-    const uint64_t w = seg * 64 + lane;
-    if (w < n_words) bitmap[w] = mine;
+    if (lane < n_j) bitmap[w_base + lane] = mine;
     cnt += __popcll(mine);
   }
   block_count_add(static_cast<int64_t>(wave_sum(cnt)), &s_cnt, count);
@@ -411,7 +428,16 @@ __global__ void __launch_bounds__(kProbeThreads)
   __shared__ uint32_t s_staged;
   __shared__ unsigned long long s_cnt;
 
+  __shared__ uint64_t s_sel[kMaxProbe];
+  __shared__ uint64_t s_nb_raw[kMaxProbe];
   const uint32_t n_f = fs.n;
+  // Thread i reads filter i's builder count and block count (in parallel).
+  if (threadIdx.x < n_f) {
+    const FilterRef f = pick(fs, threadIdx.x);
+    s_sel[threadIdx.x] = (f.sel && f.rows) ? *f.sel : 1;
+    s_nb_raw[threadIdx.x] = *f.nb;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t ord[kMaxProbe];
     uint64_t sel[kMaxProbe], rows[kMaxProbe];
@@ -422,7 +448,7 @@ __global__ void __launch_bounds__(kProbeThreads)
       rows[i] = 1;
       if (i < static_cast<int>(n_f)) {
         if (fs.f[i].sel && fs.f[i].rows) {
-          sel[i] = *fs.f[i].sel;
+          sel[i] = s_sel[i];
           rows[i] = fs.f[i].rows;
         }
       }
@@ -442,7 +468,7 @@ __global__ void __launch_bounds__(kProbeThreads)
     uint64_t need = 0;
     for (uint32_t j = 0; j < n_f; j++) {
       const FilterRef f = pick(fs, ord[j]);
-      const uint32_t nb = clamp_blocks(*f.nb, f.cap_words / W);
+      const uint32_t nb = clamp_blocks(s_nb_raw[ord[j]], f.cap_words / W);
       s_ord[j] = ord[j];
       s_nb[j] = nb;
       s_off[j] = static_cast<uint32_t>(need);
@@ -514,43 +540,25 @@ __global__ void __launch_bounds__(kThreads)
 // ------------------------------------------------------------------ build
 //
 // The outgoing half of the filter transformation: every selected row's key
-// is inserted into each outgoing filter by atomic OR (order-free, so the
-// filter bits do not depend on scheduling). A wave takes 64 bitmap words;
-// a sparse group is walked lane by lane (each lane pops the set bits of its
+// is inserted into each outgoing filter by OR (order-free, so the filter
+// bits do not depend on scheduling). A wave takes a segment of bitmap words;
+// a sparse segment is walked lane by lane (each lane pops the set bits of its
 // own word), a dense one word by word (lanes = rows, coalesced key loads),
 // whichever needs fewer steps.
+//
+// Filters that fit in LDS together are built without global atomics: each
+// workgroup sets the bits of its rows in private LDS copies (LDS atomics),
+// writes the copies to scratch memory, and a second kernel ORs the copies
+// word by word into the filters. Larger filters are built in place with
+// global atomic OR, skipped when a read already shows the bit set.
 
-template <int B, int K>
-__device__ __forceinline__ void insert_row(const FilterSet &fs, const uint32_t (&nb)[kMaxFilters],
-                                          uint32_t k, uint64_t row) {
-#pragma unroll
-  for (int i = 0; i < kMaxFilters; i++) {
-    if (i < static_cast<int>(fs.n)) {
-      uint32_t h1, h2;
-      if (fs.f[i].key64) {
-        hash_key(static_cast<const uint64_t *>(fs.f[i].keys)[row], h1, h2);
-      } else {
-        hash_key32(static_cast<uint32_t>(static_cast<const int32_t *>(fs.f[i].keys)[row]), h1, h2);
-      }
-      insert_bits<B, K>(fs.f[i].words, nb[i], k, h1, h2);
-    }
-  }
-}
-
-template <int B, int K>
-__global__ void __launch_bounds__(kThreads)
-    k_build(FilterSet fs, uint32_t k, uint64_t n_rows, const uint64_t *__restrict__ bitmap,
-            uint32_t seg_words) {
-  uint32_t nb[kMaxFilters];
-#pragma unroll
-  for (int i = 0; i < kMaxFilters; i++)
-    nb[i] = i < static_cast<int>(fs.n)
-                ? clamp_blocks(*fs.f[i].nb, fs.f[i].cap_words / BlockShape<B>::kWords)
-                : 1;
+// Calls f(row) for every selected row, spread over the grid's waves.
+template <typename F>
+__device__ __forceinline__ void walk_rows(uint64_t n_rows, const uint64_t *bitmap,
+                                          uint32_t seg_words, F &&f) {
   const uint32_t lane = lane_id();
   const uint64_t n_words = (n_rows + 63) / 64;
-  // A wave takes seg_words (1..64) consecutive words, so that small tables
-  // still spread over many waves; lane l holds word l of the segment.
+  // lane l holds word l of a segment of seg_words (1..64) words
   for (uint64_t seg = global_wave(); seg * seg_words < n_words; seg += wave_count()) {
     const uint64_t w = seg * seg_words + lane;
     uint64_t word = lane < seg_words ? tail_mask(w, n_words, n_rows) : 0;
@@ -564,7 +572,7 @@ __global__ void __launch_bounds__(kThreads)
         if (word) {
           const uint32_t b = __ffsll(static_cast<unsigned long long>(word)) - 1;
           word &= word - 1;
-          insert_row<B, K>(fs, nb, k, w * 64 + b);
+          f(w * 64 + b);
         }
       }
     } else {
@@ -573,9 +581,165 @@ __global__ void __launch_bounds__(kThreads)
         const uint32_t j = __ffsll(static_cast<unsigned long long>(todo)) - 1;
         todo &= todo - 1;
         const uint64_t wj = __shfl(word, j);
-        if ((wj >> lane) & 1) insert_row<B, K>(fs, nb, k, (seg * seg_words + j) * 64 + lane);
+        if ((wj >> lane) & 1) f((seg * seg_words + j) * 64 + lane);
       }
     }
+  }
+}
+
+__device__ __forceinline__ void key_hash(const FilterRef &f, uint64_t row, uint32_t &h1, uint32_t &h2) {
+  if (f.key64)
+    hash_key(static_cast<const uint64_t *>(f.keys)[row], h1, h2);
+  else
+    hash_key32(static_cast<uint32_t>(static_cast<const int32_t *>(f.keys)[row]), h1, h2);
+}
+
+// Sets the k bits of (h1, h2) in a filter held in LDS.
+template <int B, int K>
+__device__ __forceinline__ void insert_lds(uint32_t *filter, uint32_t nb, uint32_t k, uint32_t h1,
+                                           uint32_t h2) {
+  using S = BlockShape<B>;
+  uint32_t *blk = filter + block_of(h1, nb) * S::kWords;
+  const uint32_t g1 = h2 >> (32 - S::kLog2);
+  const uint32_t g2 = ((h2 >> (32 - 2 * S::kLog2)) & (B - 1)) | 1u;
+  uint32_t pos = g1;
+  const uint32_t kk = K > 0 ? static_cast<uint32_t>(K) : k;
+#pragma unroll
+  for (uint32_t i = 0; i < kk; i++) {
+    const uint32_t p = pos & (B - 1);
+    atomicOr(blk + (p >> 5), 1u << (p & 31));
+    pos += g2;
+  }
+}
+
+template <int B, int K>
+__global__ void __launch_bounds__(kThreads)
+    k_build(FilterSet fs, uint32_t k, uint64_t n_rows, const uint64_t *__restrict__ bitmap,
+            uint32_t seg_words) {
+  uint32_t nb[kMaxFilters];
+#pragma unroll
+  for (int i = 0; i < kMaxFilters; i++)
+    nb[i] = i < static_cast<int>(fs.n)
+                ? clamp_blocks(*fs.f[i].nb, fs.f[i].cap_words / BlockShape<B>::kWords)
+                : 1;
+  walk_rows(n_rows, bitmap, seg_words, [&](uint64_t row) {
+#pragma unroll
+    for (int i = 0; i < kMaxFilters; i++) {
+      if (i < static_cast<int>(fs.n)) {
+        uint32_t h1, h2;
+        key_hash(fs.f[i], row, h1, h2);
+        insert_bits<B, K>(fs.f[i].words, nb[i], k, h1, h2);
+      }
+    }
+  });
+}
+
+// Layout shared by the LDS build and its reduction: filter i's private copy
+// starts at word off[i]; `fits` is false when the copies exceed lds_words.
+struct LdsPlan {
+  uint32_t nb[kMaxFilters];
+  uint32_t off[kMaxFilters];
+  uint32_t total;
+  bool fits;
+};
+
+template <int B>
+__device__ __forceinline__ LdsPlan lds_plan(const FilterSet &fs, uint32_t lds_words) {
+  LdsPlan pl{};
+  uint64_t total = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxFilters; i++) {
+    pl.nb[i] = 1;
+    pl.off[i] = 0;
+    if (i < static_cast<int>(fs.n)) {
+      pl.nb[i] = clamp_blocks(*fs.f[i].nb, fs.f[i].cap_words / BlockShape<B>::kWords);
+      pl.off[i] = static_cast<uint32_t>(total < 0xFFFFFFFFull ? total : 0);
+      total += static_cast<uint64_t>(pl.nb[i]) * BlockShape<B>::kWords;
+    }
+  }
+  pl.fits = total <= lds_words;
+  pl.total = pl.fits ? static_cast<uint32_t>(total) : 0;
+  return pl;
+}
+
+template <int B, int K>
+__global__ void __launch_bounds__(kWideThreads)
+    k_build_lds(FilterSet fs, uint32_t k, uint64_t n_rows, const uint64_t *__restrict__ bitmap,
+                uint32_t seg_words, uint32_t *__restrict__ partials, uint32_t lds_words) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const LdsPlan pl = lds_plan<B>(fs, lds_words);
+  if (!pl.fits) {
+    // Too large for LDS: insert in place with global atomics.
+    walk_rows(n_rows, bitmap, seg_words, [&](uint64_t row) {
+#pragma unroll
+      for (int i = 0; i < kMaxFilters; i++) {
+        if (i < static_cast<int>(fs.n)) {
+          uint32_t h1, h2;
+          key_hash(fs.f[i], row, h1, h2);
+          insert_bits<B, K>(fs.f[i].words, pl.nb[i], k, h1, h2);
+        }
+      }
+    });
+    return;
+  }
+  for (uint32_t j = threadIdx.x; j < pl.total; j += blockDim.x) lds[j] = 0;
+  __syncthreads();
+  walk_rows(n_rows, bitmap, seg_words, [&](uint64_t row) {
+#pragma unroll
+    for (int i = 0; i < kMaxFilters; i++) {
+      if (i < static_cast<int>(fs.n)) {
+        uint32_t h1, h2;
+        key_hash(fs.f[i], row, h1, h2);
+        insert_lds<B, K>(lds + pl.off[i], pl.nb[i], k, h1, h2);
+      }
+    }
+  });
+  __syncthreads();
+  uint32_t *out = partials + static_cast<uint64_t>(blockIdx.x) * lds_words;
+  for (uint32_t j = threadIdx.x; j < pl.total; j += blockDim.x) out[j] = lds[j];
+}
+
+// filter i (blockIdx.y) = OR over the n_parts private copies. A workgroup
+// takes 64 consecutive words: its 16 waves each OR every 16th copy (loads
+// issued together, coalesced across the 64 lanes), then one wave combines
+// the 16 partial results through LDS.
+template <int B>
+__global__ void __launch_bounds__(kWideThreads)
+    k_build_reduce(FilterSet fs, const uint32_t *__restrict__ partials, uint32_t n_parts,
+                   uint32_t lds_words) {
+  constexpr int kGroups = kWideThreads / kWave;
+  __shared__ uint32_t s_or[kGroups][kWave];
+  const LdsPlan pl = lds_plan<B>(fs, lds_words);
+  if (!pl.fits) return;
+  uint32_t i = 0, off = pl.off[0], nb = pl.nb[0];
+#pragma unroll
+  for (int j = 1; j < kMaxFilters; j++)
+    if (blockIdx.y == static_cast<uint32_t>(j)) {
+      i = j;
+      off = pl.off[j];
+      nb = pl.nb[j];
+    }
+  uint32_t *words = pick(fs, i).words;
+  const uint32_t n = nb * BlockShape<B>::kWords;
+  const uint32_t lane = lane_id();
+  const uint32_t g = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  for (uint32_t base = blockIdx.x * kWave; base < n; base += gridDim.x * kWave) {
+    const uint32_t w = base + lane;
+    uint32_t v = 0;
+    if (w < n) {
+#pragma unroll 8
+      for (uint32_t p = g; p < n_parts; p += kGroups)
+        v |= partials[static_cast<uint64_t>(p) * lds_words + off + w];
+    }
+    s_or[g][lane] = v;
+    __syncthreads();
+    if (g == 0 && w < n) {
+      uint32_t r = 0;
+#pragma unroll
+      for (int q = 0; q < kGroups; q++) r |= s_or[q][lane];
+      words[w] = r;
+    }
+    __syncthreads();
   }
 }
 
@@ -685,6 +849,31 @@ hipError_t by_block_bits(uint32_t block_bits, F &&f) {
   }
 }
 
+// Raises a kernel's dynamic-LDS limit once per device (to the largest
+// request seen); later launches that fit skip the call.
+hipError_t allow_lds(const void *kern, uint64_t bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void *>, uint64_t> granted;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  uint64_t &g = granted[{dev, kern}];
+  if (bytes <= g) return hipSuccess;
+  const uint64_t want = static_cast<uint64_t>(device_info().max_lds_block) - 1024;
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     static_cast<int>(bytes > want ? bytes : want));
+  if (e == hipSuccess) g = bytes > want ? bytes : want;
+  return e;
+}
+
+// Bitmap words per wave for the word-segment kernels: enough waves to cover
+// the device several times over, at most one word per lane.
+uint32_t segment_words(uint64_t n_words) {
+  const uint64_t target_waves = static_cast<uint64_t>(device_info().n_cu) * 32;
+  uint64_t seg = (n_words + target_waves - 1) / target_waves;
+  return static_cast<uint32_t>(seg < 1 ? 1 : (seg > 64 ? 64 : seg));
+}
+
 uint32_t grid_for(uint64_t waves_of_work, uint32_t threads, uint32_t per_cu) {
   const uint64_t blocks = (waves_of_work * kWave + threads - 1) / threads;
   const uint64_t cap = static_cast<uint64_t>(device_info().n_cu) * per_cu;
@@ -713,9 +902,10 @@ hipError_t launch_local_filter(const PredSet &preds, uint64_t n_rows, uint64_t *
                                uint64_t *count, hipStream_t s) {
   const uint64_t n_words = (n_rows + 63) / 64;
   if (n_words == 0) return hipSuccess;
-  const uint32_t grid = grid_for((n_words + 63) / 64, kThreads, 8);
-  hipLaunchKernelGGL(k_local, dim3(grid), dim3(kThreads), 0, s, preds, n_rows, bitmap,
-                     reinterpret_cast<unsigned long long *>(count));
+  const uint32_t seg_words = segment_words(n_words);
+  const uint32_t grid = grid_for((n_words + seg_words - 1) / seg_words, kWideThreads, 1);
+  hipLaunchKernelGGL(k_local, dim3(grid), dim3(kWideThreads), 0, s, preds, n_rows, bitmap,
+                     reinterpret_cast<unsigned long long *>(count), seg_words);
   return hipGetLastError();
 }
 
@@ -746,9 +936,7 @@ hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, ui
   return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
     constexpr int B = decltype(bb)::value;
     auto launch = [&](auto kern) -> hipError_t {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         static_cast<int>(lds_bytes));
+      hipError_t e = allow_lds(reinterpret_cast<const void *>(kern), lds_bytes);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(kern, dim3(grid), dim3(kProbeThreads), lds_bytes, s, fs, k, n_rows,
                          bitmap, cnt, filter_words, all);
@@ -774,24 +962,56 @@ hipError_t launch_size_zero(uint32_t block_bits, uint32_t bits_per_key, const Fi
   return hipGetLastError();
 }
 
+uint64_t build_lds_words() {
+  // LDS of one build workgroup: the private filter copies.
+  return (static_cast<uint64_t>(device_info().max_lds_block) - 1024) / 4;
+}
+
 hipError_t launch_build(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,
-                        const uint64_t *bitmap, hipStream_t s) {
+                        const uint64_t *bitmap, uint32_t *scratch, uint64_t scratch_words,
+                        hipStream_t s) {
   const uint64_t n_words = (n_rows + 63) / 64;
   if (n_words == 0 || fs.n == 0) return hipSuccess;
-  // Words per wave: enough waves to cover the device several times over.
-  const uint64_t target_waves = static_cast<uint64_t>(device_info().n_cu) * 32;
-  uint64_t seg = (n_words + target_waves - 1) / target_waves;
-  seg = seg < 1 ? 1 : (seg > 64 ? 64 : seg);
-  const uint32_t grid = grid_for((n_words + seg - 1) / seg, kThreads, 8);
-  const uint32_t seg_words = static_cast<uint32_t>(seg);
+  const uint32_t seg_words = segment_words(n_words);
+  const uint64_t lds_words = build_lds_words();
+  // Private copies only pay off while they fit in LDS; filters whose
+  // capacity is at most the LDS (known on the host) always take that path,
+  // larger ones decide on the device from their actual size.
+  uint64_t cap_words = 0;
+  for (uint32_t i = 0; i < fs.n; i++) cap_words += fs.f[i].cap_words;
+  const uint64_t copy_words = cap_words < lds_words ? cap_words : lds_words;
+  uint64_t parts = scratch && copy_words ? scratch_words / copy_words : 0;
+  const uint64_t work_parts = (n_words + seg_words * 16 - 1) / (seg_words * 16);
+  if (parts > static_cast<uint64_t>(device_info().n_cu)) parts = device_info().n_cu;
+  if (parts > work_parts) parts = work_parts;
+  if (parts == 0) {
+    const uint32_t grid = grid_for((n_words + seg_words - 1) / seg_words, kThreads, 8);
+    return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
+      constexpr int B = decltype(bb)::value;
+      if (k == 3)
+        hipLaunchKernelGGL((k_build<B, 3>), dim3(grid), dim3(kThreads), 0, s, fs, k, n_rows, bitmap,
+                           seg_words);
+      else
+        hipLaunchKernelGGL((k_build<B, 0>), dim3(grid), dim3(kThreads), 0, s, fs, k, n_rows, bitmap,
+                           seg_words);
+      return hipGetLastError();
+    });
+  }
+  const uint32_t cw = static_cast<uint32_t>(copy_words);
+  const uint32_t n_parts = static_cast<uint32_t>(parts);
   return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
     constexpr int B = decltype(bb)::value;
-    if (k == 3)
-      hipLaunchKernelGGL((k_build<B, 3>), dim3(grid), dim3(kThreads), 0, s, fs, k, n_rows, bitmap,
-                         seg_words);
-    else
-      hipLaunchKernelGGL((k_build<B, 0>), dim3(grid), dim3(kThreads), 0, s, fs, k, n_rows, bitmap,
-                         seg_words);
+    auto kern = k == 3 ? k_build_lds<B, 3> : k_build_lds<B, 0>;
+    hipError_t e = allow_lds(reinterpret_cast<const void *>(kern), copy_words * 4);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(n_parts), dim3(kWideThreads), copy_words * 4, s, fs, k, n_rows, bitmap,
+                       seg_words, scratch, cw);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint64_t gx = (copy_words + kWave - 1) / kWave;
+    if (gx > 1024) gx = 1024;
+    hipLaunchKernelGGL((k_build_reduce<B>), dim3(static_cast<uint32_t>(gx), fs.n), dim3(kWideThreads),
+                       0, s, fs, scratch, n_parts, cw);
     return hipGetLastError();
   });
 }

@@ -206,8 +206,9 @@ def pt_compact(bitmap: torch.Tensor, n_rows: int, idx: torch.Tensor, count: torc
                            _stream(stream)))
 
 
-def pt_profile_enable(on: bool) -> None:
-    _check(_lib.pt_profile_enable(1 if on else 0))
+def pt_profile_enable(on: bool | int) -> None:
+    """on: False/0 off, True/1 every launch, 2 probe launches only."""
+    _check(_lib.pt_profile_enable(int(on)))
 
 
 def pt_profile_read(max_records: int = 4096) -> list[dict]:
