@@ -31,7 +31,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="star", choices=["star", "chain"])
+    ap.add_argument("--workload", default="star", choices=["star", "chain", "snowflake"])
+    ap.add_argument("--bpk", type=int, default=None, help="bits per key (default 10; snowflake 12)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="compare the result with the oracle")
@@ -82,13 +83,19 @@ def main():
         cfg = {"workload": "star", "fact_rows": 100_000_000, "dims": list(W.STAR_DIMS),
                "fk_dtype": "int32", "predicates": "D0 1%, D1 20%", "block_bits": 512, "k": 3,
                "bits_per_key": 10}
+    elif args.workload == "snowflake":
+        prob = W.snowflake(seed=args.seed)
+        cfg = {"workload": "snowflake", "rows": W.SNOWFLAKE_ROWS, "key_dtype": "int64",
+               "fk_distribution": "Zipf(1.1)", "cycle": "F-D2-D3", "block_bits": 512, "k": 3,
+               "bits_per_key": args.bpk or 12}
     else:
         prob = W.chain(seed=args.seed)
         cfg = {"workload": "chain", "rows": [1000, 10000, 1000], "block_bits": 512, "k": 3,
                "bits_per_key": 10}
+    bpk = cfg["bits_per_key"] = args.bpk or cfg["bits_per_key"]
     gen_s = time.time() - t0
     dp = pt.DeviceProblem(prob)
-    tr = pt.Transfer(dp, pt.params(512, 3, 10))
+    tr = pt.Transfer(dp, pt.params(512, 3, bpk))
     torch.cuda.synchronize()
     print(f"# inputs ready in {time.time() - t0:.1f}s (generation {gen_s:.1f}s)", file=sys.stderr, flush=True)
 
@@ -139,7 +146,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": "int64" if args.workload == "snowflake" else "int32",
         "data": "synthetic",
         "config": cfg,
         "rows_probed_per_step": n_probed,
@@ -169,7 +176,7 @@ def main():
         import oracle
         host = os.cpu_count()
         t = time.perf_counter()
-        ref = oracle.transfer(prob, 512, 3, 10)
+        ref = oracle.transfer(prob, 512, 3, bpk)
         cpu_s = time.perf_counter() - t
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = {

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -196,8 +197,13 @@ struct Plan {
   std::vector<uint64_t> off_filter, cap_words;  // [pass * n_e + e]
   uint64_t off_scratch = 0;                     // private filter copies of the builds
   uint64_t scratch_words = 0;
+  uint64_t off_hist = 0, off_totals = 0, off_starts = 0, off_entries = 0;  // partitioned builds
+  uint32_t hist_groups = 0;
+  uint64_t entries_cap = 0;
   uint64_t total = 0;
 };
+
+constexpr uint64_t kMaxEntries = 64ull << 20;  // partitioned-build entries (8 bytes each)
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
@@ -297,6 +303,37 @@ pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *
   pl.off_scratch = off;
   pl.scratch_words = copy_words * static_cast<uint64_t>(device_info().n_cu);
   off = align256(off + pl.scratch_words * 4);
+  // Partitioned builds (filters larger than LDS): histogram rows, bucket
+  // totals and starts, and entries for the largest group (filters x rows of
+  // its builder), at most kMaxEntries.
+  uint64_t group_entries = 0;
+  for (uint32_t pass = 0; pass < 2; pass++) {
+    for (uint32_t v = 0; v < pl.n_t; v++) {
+      uint32_t f = 0;
+      for (uint32_t e = 0; e < pl.n_e; e++)
+        if ((pass == 0 ? pl.src[e] : pl.dst[e]) == v) f++;
+      group_entries = std::max<uint64_t>(group_entries, static_cast<uint64_t>(std::min<uint32_t>(f, kMaxFilters)) *
+                                                            tables[v].n_rows);
+    }
+  }
+  const char *force = std::getenv("PT_BUILD_PATH");
+  const bool force_part = force && std::strcmp(force, "part") == 0;
+  if ((group_words > build_lds_words() || force_part) && group_entries > 0) {
+    pl.hist_groups = static_cast<uint32_t>(device_info().n_cu);
+    pl.off_hist = off;
+    off = align256(off + static_cast<uint64_t>(pl.hist_groups) * kMaxBuckets * 4);
+    pl.off_totals = off;
+    off = align256(off + static_cast<uint64_t>(kMaxBuckets) * 8);
+    pl.off_starts = off;
+    off = align256(off + (static_cast<uint64_t>(kMaxBuckets) + 1) * 8);
+    uint64_t max_entries = kMaxEntries;
+    // PT_MAX_ENTRIES (testing): a smaller entry buffer, to exercise the
+    // in-place fallback of the partitioned build.
+    if (const char *env = std::getenv("PT_MAX_ENTRIES")) max_entries = std::strtoull(env, nullptr, 10);
+    pl.entries_cap = std::min(group_entries, max_entries);
+    pl.off_entries = off;
+    off = align256(off + pl.entries_cap * 8);
+  }
   pl.total = off;
   return PT_OK;
 }
@@ -387,8 +424,8 @@ pt_status pt_bloom_capacity(uint64_t max_keys, const pt_params *params, uint64_t
 
 static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
                                uint64_t n_rows, const uint64_t *d_bitmap, const uint64_t *d_count,
-                               uint32_t *scratch, uint64_t scratch_words, hipStream_t s,
-                               uint32_t table, uint32_t pass) {
+                               const BuildScratch *scratch, hipStream_t s, uint32_t table,
+                               uint32_t pass) {
   const pt_params &p = filters[0].params;
   for (uint32_t done = 0; done < n_filters;) {
     FilterSet fs{};
@@ -397,15 +434,9 @@ static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const 
       fs.f[fs.n] = make_ref(keys[done], filters[done]);
       bytes += n_rows * key_bytes(keys[done]);
     }
-    {
-      Timed tm("size", table, pass, 0, 0, s);
-      pt_status st = check_hip(launch_size_zero(p.block_bits, p.bits_per_key, fs, d_count, n_rows, s),
-                               "size launch");
-      if (st != PT_OK) return st;
-    }
     Timed tm("build", table, pass, n_rows, bytes, s);
-    pt_status st = check_hip(launch_build(p.block_bits, p.k, fs, n_rows, d_bitmap, scratch,
-                                          scratch_words, s),
+    pt_status st = check_hip(launch_build(p.block_bits, p.k, p.bits_per_key, fs, n_rows, d_bitmap,
+                                          d_count, scratch, s),
                              "build launch");
     if (st != PT_OK) return st;
   }
@@ -461,7 +492,7 @@ pt_status pt_bloom_build(uint32_t n_filters, const pt_column *keys, const pt_blo
     if (st != PT_OK) return st;
   }
   return build_filters(n_filters, keys, filters, n_rows, d_bitmap, d_bitmap ? d_count : nullptr,
-                       nullptr, 0, reinterpret_cast<hipStream_t>(stream), 0, 0);
+                       nullptr, reinterpret_cast<hipStream_t>(stream), 0, 0);
 }
 
 pt_status pt_bloom_probe(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
@@ -618,6 +649,18 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
     } while (done < mine.size());
   }
 
+  BuildScratch scratch;
+  scratch.copies = reinterpret_cast<uint32_t *>(ws + pl.off_scratch);
+  scratch.copies_words = pl.scratch_words;
+  if (pl.entries_cap) {
+    scratch.hist = reinterpret_cast<uint32_t *>(ws + pl.off_hist);
+    scratch.hist_groups = pl.hist_groups;
+    scratch.totals = reinterpret_cast<uint64_t *>(ws + pl.off_totals);
+    scratch.starts = reinterpret_cast<uint64_t *>(ws + pl.off_starts);
+    scratch.entries = reinterpret_cast<uint64_t *>(ws + pl.off_entries);
+    scratch.entries_cap = pl.entries_cap;
+  }
+
   // The two passes (Sec. 3.2). In pass p (0 forward, 1 backward) the edge e
   // goes from `from[e]` to `to[e]`; tables are visited in `seq`.
   std::vector<uint32_t> rev(pl.order.rbegin(), pl.order.rend());
@@ -666,8 +709,7 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
         const bool all = all_rows[v] != 0;
         st = build_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), tb.n_rows,
                            all ? nullptr : d_bitmaps[v], all ? nullptr : counts + cur[v] * pl.n_t + v,
-                           reinterpret_cast<uint32_t *>(ws + pl.off_scratch), pl.scratch_words, s, v,
-                           p + 1);
+                           &scratch, s, v, p + 1);
         if (st != PT_OK) return st;
       }
     }

@@ -59,13 +59,29 @@ hipError_t launch_fill_all(uint64_t *bitmap, uint64_t n_rows, uint64_t *count, h
 // input_all: every row starts selected (the bitmap is not read, only written).
 hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,
                         uint64_t *bitmap, uint64_t *count, bool input_all, hipStream_t s);
-hipError_t launch_size_zero(uint32_t block_bits, uint32_t bits_per_key, const FilterSet &fs,
-                            const uint64_t *count, uint64_t n_rows, hipStream_t s);
-// scratch (optional): room for private per-workgroup filter copies; with
-// it, filters that fit in LDS are built without global atomics.
-hipError_t launch_build(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,
-                        const uint64_t *bitmap, uint32_t *scratch, uint64_t scratch_words,
-                        hipStream_t s);
+constexpr uint32_t kTileWords = 16384;   // 64 KB of filter per partitioned-build tile
+constexpr uint32_t kMaxBuckets = 16384;  // (filter, tile) buckets of one partitioned build
+
+// Device buffers a build may use. copies: private per-workgroup LDS copies
+// (filters that fit in LDS); hist / totals / starts / entries: the
+// partitioned build (hist_groups x kMaxBuckets counters, kMaxBuckets totals,
+// kMaxBuckets + 1 starts, entries_cap entries). Any part may be absent.
+struct BuildScratch {
+  uint32_t *copies = nullptr;
+  uint64_t copies_words = 0;
+  uint32_t *hist = nullptr;
+  uint32_t hist_groups = 0;
+  uint64_t *totals = nullptr;
+  uint64_t *starts = nullptr;
+  uint64_t *entries = nullptr;
+  uint64_t entries_cap = 0;
+};
+
+// Sizes filters from *count (n_rows when count is NULL) and builds them
+// from the selected rows (bitmap NULL: all rows).
+hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, const FilterSet &fs,
+                        uint64_t n_rows, const uint64_t *bitmap, const uint64_t *count,
+                        const BuildScratch *scratch, hipStream_t s);
 // Words of LDS one build workgroup uses for its private filter copies.
 uint64_t build_lds_words();
 hipError_t launch_copy_counts(const uint64_t *src, const uint32_t *slot, uint32_t n,

@@ -5,6 +5,8 @@
 // wave-uniform; per-lane work that does not matter (rows already removed,
 // rows past the end) is computed anyway on clamped, in-bounds addresses and
 // masked out, which keeps the exec mask full and the code straight-line.
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 
@@ -71,6 +73,23 @@ __device__ __forceinline__ uint32_t clamp_blocks(uint64_t nb, uint64_t cap_block
 __device__ __forceinline__ uint64_t tail_mask(uint64_t w, uint64_t n_words, uint64_t n_rows) {
   if (w >= n_words) return 0;
   return (w + 1 == n_words && (n_rows & 63)) ? (1ull << (n_rows & 63)) - 1 : ~0ull;
+}
+
+// Exclusive prefix sum of v over the workgroup (blockDim.x entries of s).
+__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *s, uint64_t &total) {
+  const uint32_t t = threadIdx.x;
+  s[t] = v;
+  __syncthreads();
+  for (uint32_t d = 1; d < blockDim.x; d <<= 1) {
+    const uint64_t add = t >= d ? s[t - d] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  total = s[blockDim.x - 1];
+  const uint64_t incl = s[t];
+  __syncthreads();
+  return incl - v;
 }
 
 // Selects filter i of a set without a dynamically indexed kernel argument.
@@ -518,19 +537,73 @@ __global__ void __launch_bounds__(kProbeThreads)
 //
 // Filter i (blockIdx.y) gets nb = max(1, ceil(count * bits_per_key / B))
 // blocks, read from the device counter so the launch sequence never waits
-// for the host; its first nb blocks are zeroed.
+// for the host. Its first nb blocks are zeroed unless the partitioned build
+// (which writes every block) will run.
+
+
+__device__ __forceinline__ uint64_t blocks_needed(uint64_t n_sel, uint32_t block_bits,
+                                                  uint32_t bits_per_key, uint64_t cap_blocks) {
+  uint64_t nb = (n_sel * bits_per_key + block_bits - 1) / block_bits;
+  if (nb == 0) nb = 1;
+  return nb > cap_blocks ? cap_blocks : nb;  // the cap is unreachable when it was checked
+}
+
+// Partitioned-build plan of one group of filters: filter f's tiles are
+// buckets [base[f], base[f] + tiles[f]). ok: it fits the bucket table and
+// the entry buffer (entries_cap entries).
+constexpr uint64_t kTargetBuckets = 1024;
+
+struct PartPlan {
+  uint32_t nb[kMaxFilters];
+  uint32_t base[kMaxFilters + 1];
+  uint32_t tile_blocks;
+  uint64_t n_sel;
+  bool ok;
+};
+
+__device__ __forceinline__ PartPlan part_plan(const FilterSet &fs, uint32_t block_bits,
+                                              uint32_t bits_per_key, const uint64_t *count,
+                                              uint64_t n_rows, uint64_t entries_cap, bool from_count) {
+  PartPlan pl{};
+  const uint32_t W = block_bits / 32;
+  pl.n_sel = count ? *count : n_rows;
+  uint64_t all_blocks = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxFilters; i++) {
+    pl.nb[i] = 1;
+    if (i < static_cast<int>(fs.n)) {
+      const uint64_t cap_blocks = fs.f[i].cap_words / W;
+      pl.nb[i] = from_count ? static_cast<uint32_t>(blocks_needed(pl.n_sel, block_bits, bits_per_key, cap_blocks))
+                            : clamp_blocks(*fs.f[i].nb, cap_blocks);
+      all_blocks += pl.nb[i];
+    }
+  }
+  // Tiles of at most 64 KB, small enough that the group has about
+  // kTargetBuckets of them (the fill kernel runs one workgroup per tile).
+  uint64_t tb = (all_blocks + kTargetBuckets - 1) / kTargetBuckets;
+  const uint64_t max_tb = kTileWords / W;
+  pl.tile_blocks = static_cast<uint32_t>(tb < 1 ? 1 : (tb > max_tb ? max_tb : tb));
+  uint64_t buckets = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxFilters; i++) {
+    pl.base[i] = static_cast<uint32_t>(buckets < kMaxBuckets ? buckets : kMaxBuckets);
+    if (i < static_cast<int>(fs.n)) buckets += (pl.nb[i] + pl.tile_blocks - 1) / pl.tile_blocks;
+  }
+  pl.base[kMaxFilters] = static_cast<uint32_t>(buckets < kMaxBuckets ? buckets : kMaxBuckets);
+  pl.ok = entries_cap > 0 && buckets <= kMaxBuckets && pl.n_sel * fs.n <= entries_cap;
+  return pl;
+}
 
 __global__ void __launch_bounds__(kThreads)
     k_size_zero(FilterSet fs, uint32_t block_bits, uint32_t bits_per_key, const uint64_t *count,
-                uint64_t n_rows) {
+                uint64_t n_rows, uint64_t entries_cap) {
   const FilterRef f = pick(fs, blockIdx.y);
-  const uint64_t n_sel = count ? *count : n_rows;
   const uint64_t words_per_block = block_bits / 32;
-  uint64_t nb = (n_sel * bits_per_key + block_bits - 1) / block_bits;
-  if (nb == 0) nb = 1;
-  const uint64_t cap_blocks = f.cap_words / words_per_block;
-  if (nb > cap_blocks) nb = cap_blocks;  // unreachable when the capacity was checked
+  const uint64_t nb = blocks_needed(count ? *count : n_rows, block_bits, bits_per_key,
+                                    f.cap_words / words_per_block);
   if (blockIdx.x == 0 && threadIdx.x == 0) *f.nb = nb;
+  if (entries_cap && part_plan(fs, block_bits, bits_per_key, count, n_rows, entries_cap, true).ok)
+    return;
   const uint64_t n = nb * words_per_block;
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
@@ -552,8 +625,10 @@ __global__ void __launch_bounds__(kThreads)
 // word by word into the filters. Larger filters are built in place with
 // global atomic OR, skipped when a read already shows the bit set.
 
-// Calls f(row) for every selected row, spread over the grid's waves.
-template <typename F>
+// Calls f(rows, ok) for the selected rows, spread over the grid's waves,
+// U rows per lane at a time: rows[u] is valid where bit u of ok is set. A
+// batch of U rows lets the caller issue U key loads before it waits.
+template <int U, typename F>
 __device__ __forceinline__ void walk_rows(uint64_t n_rows, const uint64_t *bitmap,
                                           uint32_t seg_words, F &&f) {
   const uint32_t lane = lane_id();
@@ -565,33 +640,88 @@ __device__ __forceinline__ void walk_rows(uint64_t n_rows, const uint64_t *bitma
     if (bitmap && lane < seg_words && w < n_words) word &= bitmap[w];
     const uint64_t nonzero = __ballot(word != 0);
     if (nonzero == 0) continue;
+    // Sparse steps load 64 scattered rows at once; dense steps load 64
+    // consecutive rows (one coalesced access). Walk sparsely only when that
+    // needs clearly fewer steps.
     const uint32_t steps_sparse = wave_max(__popcll(word));
     const uint32_t steps_dense = __popcll(nonzero);
-    if (steps_sparse <= steps_dense) {
+    if (4 * steps_sparse < steps_dense) {
       while (__ballot(word != 0)) {
-        if (word) {
-          const uint32_t b = __ffsll(static_cast<unsigned long long>(word)) - 1;
-          word &= word - 1;
-          f(w * 64 + b);
+        uint64_t rows[U];
+        uint32_t ok = 0;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          rows[u] = 0;
+          if (word) {
+            rows[u] = w * 64 + (__ffsll(static_cast<unsigned long long>(word)) - 1);
+            word &= word - 1;
+            ok |= 1u << u;
+          }
         }
+        f(rows, ok);
       }
     } else {
       uint64_t todo = nonzero;
       while (todo) {
-        const uint32_t j = __ffsll(static_cast<unsigned long long>(todo)) - 1;
-        todo &= todo - 1;
-        const uint64_t wj = __shfl(word, j);
-        if ((wj >> lane) & 1) f((seg * seg_words + j) * 64 + lane);
+        uint64_t rows[U];
+        uint32_t ok = 0;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          rows[u] = 0;
+          if (todo) {
+            const uint32_t j = __ffsll(static_cast<unsigned long long>(todo)) - 1;
+            todo &= todo - 1;
+            const uint64_t wj = __shfl(word, j);
+            rows[u] = (seg * seg_words + j) * 64 + lane;
+            if ((wj >> lane) & 1) ok |= 1u << u;
+          }
+        }
+        f(rows, ok);
       }
     }
   }
 }
 
-__device__ __forceinline__ void key_hash(const FilterRef &f, uint64_t row, uint32_t &h1, uint32_t &h2) {
-  if (f.key64)
-    hash_key(static_cast<const uint64_t *>(f.keys)[row], h1, h2);
-  else
-    hash_key32(static_cast<uint32_t>(static_cast<const int32_t *>(f.keys)[row]), h1, h2);
+// Filter hashes of the keys of up to U rows (those set in ok) in f's key
+// column; the loads are issued together.
+template <int U>
+__device__ __forceinline__ void hash_rows(const FilterRef &f, const uint64_t (&row)[U], uint32_t ok,
+                                          uint32_t (&h1)[U], uint32_t (&h2)[U]) {
+  if (f.key64) {
+    uint64_t x[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) x[u] = (ok >> u) & 1 ? static_cast<const uint64_t *>(f.keys)[row[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < U; u++) hash_key(x[u], h1[u], h2[u]);
+  } else {
+    uint32_t x[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) x[u] = (ok >> u) & 1 ? static_cast<const uint32_t *>(f.keys)[row[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < U; u++) hash_key32(x[u], h1[u], h2[u]);
+  }
+}
+
+constexpr int kWalkBatch = 8;
+
+// Calls g(i, h1, h2) for every selected row and every filter i of fs, with
+// the hashes of the row's key in filter i's key column.
+template <typename G>
+__device__ __forceinline__ void for_each_key(const FilterSet &fs, uint64_t n_rows, const uint64_t *bitmap,
+                                             uint32_t seg_words, G &&g) {
+  constexpr int U = kWalkBatch;
+  walk_rows<U>(n_rows, bitmap, seg_words, [&](const uint64_t (&row)[U], uint32_t ok) {
+#pragma unroll
+    for (int i = 0; i < kMaxFilters; i++) {
+      if (i < static_cast<int>(fs.n)) {
+        uint32_t h1[U], h2[U];
+        hash_rows<U>(fs.f[i], row, ok, h1, h2);
+#pragma unroll
+        for (int u = 0; u < U; u++)
+          if ((ok >> u) & 1) g(i, h1[u], h2[u]);
+      }
+    }
+  });
 }
 
 // Sets the k bits of (h1, h2) in a filter held in LDS.
@@ -622,15 +752,8 @@ __global__ void __launch_bounds__(kThreads)
     nb[i] = i < static_cast<int>(fs.n)
                 ? clamp_blocks(*fs.f[i].nb, fs.f[i].cap_words / BlockShape<B>::kWords)
                 : 1;
-  walk_rows(n_rows, bitmap, seg_words, [&](uint64_t row) {
-#pragma unroll
-    for (int i = 0; i < kMaxFilters; i++) {
-      if (i < static_cast<int>(fs.n)) {
-        uint32_t h1, h2;
-        key_hash(fs.f[i], row, h1, h2);
-        insert_bits<B, K>(fs.f[i].words, nb[i], k, h1, h2);
-      }
-    }
+  for_each_key(fs, n_rows, bitmap, seg_words, [&](int i, uint32_t h1, uint32_t h2) {
+    insert_bits<B, K>(fs.f[i].words, nb[i], k, h1, h2);
   });
 }
 
@@ -670,29 +793,15 @@ __global__ void __launch_bounds__(kWideThreads)
   const LdsPlan pl = lds_plan<B>(fs, lds_words);
   if (!pl.fits) {
     // Too large for LDS: insert in place with global atomics.
-    walk_rows(n_rows, bitmap, seg_words, [&](uint64_t row) {
-#pragma unroll
-      for (int i = 0; i < kMaxFilters; i++) {
-        if (i < static_cast<int>(fs.n)) {
-          uint32_t h1, h2;
-          key_hash(fs.f[i], row, h1, h2);
-          insert_bits<B, K>(fs.f[i].words, pl.nb[i], k, h1, h2);
-        }
-      }
+    for_each_key(fs, n_rows, bitmap, seg_words, [&](int i, uint32_t h1, uint32_t h2) {
+      insert_bits<B, K>(fs.f[i].words, pl.nb[i], k, h1, h2);
     });
     return;
   }
   for (uint32_t j = threadIdx.x; j < pl.total; j += blockDim.x) lds[j] = 0;
   __syncthreads();
-  walk_rows(n_rows, bitmap, seg_words, [&](uint64_t row) {
-#pragma unroll
-    for (int i = 0; i < kMaxFilters; i++) {
-      if (i < static_cast<int>(fs.n)) {
-        uint32_t h1, h2;
-        key_hash(fs.f[i], row, h1, h2);
-        insert_lds<B, K>(lds + pl.off[i], pl.nb[i], k, h1, h2);
-      }
-    }
+  for_each_key(fs, n_rows, bitmap, seg_words, [&](int i, uint32_t h1, uint32_t h2) {
+    insert_lds<B, K>(lds + pl.off[i], pl.nb[i], k, h1, h2);
   });
   __syncthreads();
   uint32_t *out = partials + static_cast<uint64_t>(blockIdx.x) * lds_words;
@@ -743,6 +852,159 @@ __global__ void __launch_bounds__(kWideThreads)
   }
 }
 
+// ---------------------------------------------------- partitioned build
+//
+// Filters too large for LDS are built tile by tile: the filter's blocks are
+// cut into 64 KB tiles and every (filter, tile) pair is a bucket.
+//   count    each workgroup walks its rows and histograms their bucket
+//            in LDS, then stores its histogram row;
+//   scan     per bucket, an exclusive scan over the workgroups' counts, then
+//            one scan over the bucket totals: every (workgroup, bucket) gets
+//            its own range of the entry buffer;
+//   scatter  the same walk again (same grid, so the same rows per
+//            workgroup) writes each entry - block within the tile and H2 -
+//            at its range's next slot (LDS cursors); when the plan does not
+//            fit, this kernel inserts in place with global atomics instead;
+//   fill     one workgroup per bucket sets the bits of its entries in an LDS
+//            tile and stores the whole tile (every block of the filter is
+//            written exactly once).
+// No step needs a global atomic.
+
+template <int B>
+__device__ __forceinline__ uint32_t bucket_of(const PartPlan &pl, int f, uint32_t h1, uint32_t &blk) {
+  blk = block_of(h1, pl.nb[f]);
+  return pl.base[f] + blk / pl.tile_blocks;
+}
+
+template <int B>
+__global__ void __launch_bounds__(kWideThreads)
+    k_part_count(FilterSet fs, uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
+                 const uint64_t *__restrict__ bitmap, uint32_t seg_words, uint64_t entries_cap,
+                 uint32_t *__restrict__ hist) {
+  extern __shared__ __align__(16) uint32_t s_hist[];
+  const PartPlan pl = part_plan(fs, B, bits_per_key, count, n_rows, entries_cap, false);
+  if (!pl.ok) return;
+  const uint32_t buckets = pl.base[kMaxFilters];
+  for (uint32_t b = threadIdx.x; b < buckets; b += blockDim.x) s_hist[b] = 0;
+  __syncthreads();
+  for_each_key(fs, n_rows, bitmap, seg_words, [&](int i, uint32_t h1, uint32_t h2) {
+    uint32_t blk;
+    atomicAdd(&s_hist[bucket_of<B>(pl, i, h1, blk)], 1u);
+  });
+  __syncthreads();
+  uint32_t *row_out = hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets;
+  for (uint32_t b = threadIdx.x; b < buckets; b += blockDim.x) row_out[b] = s_hist[b];
+}
+
+// Bucket b (blockIdx.x): exclusive scan of hist[g][b] over the n_groups
+// workgroups, in place; the bucket's total goes to totals[b].
+__global__ void __launch_bounds__(kWideThreads)
+    k_part_scan_groups(FilterSet fs, uint32_t block_bits, uint32_t bits_per_key,
+                       const uint64_t *count, uint64_t n_rows, uint64_t entries_cap,
+                       uint32_t *__restrict__ hist, uint32_t n_groups, uint64_t *__restrict__ totals) {
+  __shared__ uint64_t s[kWideThreads];
+  const PartPlan pl = part_plan(fs, block_bits, bits_per_key, count, n_rows, entries_cap, false);
+  if (!pl.ok) return;
+  for (uint32_t b = blockIdx.x; b < pl.base[kMaxFilters]; b += gridDim.x) {
+    const uint32_t g = threadIdx.x;
+    const uint64_t v = g < n_groups ? hist[static_cast<uint64_t>(g) * kMaxBuckets + b] : 0;
+    uint64_t total;
+    const uint64_t ex = block_exclusive_scan(v, s, total);
+    if (g < n_groups) hist[static_cast<uint64_t>(g) * kMaxBuckets + b] = static_cast<uint32_t>(ex);
+    if (g == 0) totals[b] = total;
+  }
+}
+
+// starts[b] = sum of totals[0..b) for every bucket, starts[buckets] = all.
+__global__ void __launch_bounds__(kWideThreads)
+    k_part_scan_buckets(FilterSet fs, uint32_t block_bits, uint32_t bits_per_key,
+                        const uint64_t *count, uint64_t n_rows, uint64_t entries_cap,
+                        const uint64_t *__restrict__ totals, uint64_t *__restrict__ starts) {
+  __shared__ uint64_t s[kWideThreads];
+  const PartPlan pl = part_plan(fs, block_bits, bits_per_key, count, n_rows, entries_cap, false);
+  if (!pl.ok) return;
+  const uint32_t buckets = pl.base[kMaxFilters];
+  uint64_t carry = 0;
+  for (uint32_t base = 0; base < buckets; base += blockDim.x) {
+    const uint32_t b = base + threadIdx.x;
+    const uint64_t v = b < buckets ? totals[b] : 0;
+    uint64_t total;
+    const uint64_t ex = block_exclusive_scan(v, s, total);
+    if (b < buckets) starts[b] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) starts[buckets] = carry;
+}
+
+template <int B, int K>
+__global__ void __launch_bounds__(kWideThreads)
+    k_part_scatter(FilterSet fs, uint32_t k, uint32_t bits_per_key, const uint64_t *count,
+                   uint64_t n_rows, const uint64_t *__restrict__ bitmap, uint32_t seg_words,
+                   uint64_t entries_cap, const uint32_t *__restrict__ hist,
+                   const uint64_t *__restrict__ starts, uint64_t *__restrict__ entries) {
+  extern __shared__ __align__(16) uint64_t s_cur[];
+  const PartPlan pl = part_plan(fs, B, bits_per_key, count, n_rows, entries_cap, false);
+  if (!pl.ok) {
+    // The plan does not fit: insert in place with global atomics (the size
+    // kernel zeroed the filters in this case).
+    for_each_key(fs, n_rows, bitmap, seg_words, [&](int i, uint32_t h1, uint32_t h2) {
+      insert_bits<B, K>(fs.f[i].words, pl.nb[i], k, h1, h2);
+    });
+    return;
+  }
+  const uint32_t buckets = pl.base[kMaxFilters];
+  const uint32_t *my = hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets;
+  // s_cur[b]: the next entry slot of this workgroup in bucket b
+  for (uint32_t b = threadIdx.x; b < buckets; b += blockDim.x) s_cur[b] = starts[b] + my[b];
+  __syncthreads();
+  for_each_key(fs, n_rows, bitmap, seg_words, [&](int i, uint32_t h1, uint32_t h2) {
+    uint32_t blk;
+    const uint32_t b = bucket_of<B>(pl, i, h1, blk);
+    const uint64_t pos = atomicAdd(&s_cur[b], static_cast<uint64_t>(1));
+    if (pos < entries_cap)  // always true while *count is the bitmap's popcount
+      entries[pos] = (static_cast<uint64_t>(blk % pl.tile_blocks) << 32) | h2;
+  });
+}
+
+template <int B, int K>
+__global__ void __launch_bounds__(kWideThreads)
+    k_part_fill(FilterSet fs, uint32_t k, uint32_t bits_per_key, const uint64_t *count,
+                uint64_t n_rows, uint64_t entries_cap, const uint64_t *__restrict__ starts,
+                const uint64_t *__restrict__ entries) {
+  constexpr int W = BlockShape<B>::kWords;
+  extern __shared__ __align__(16) uint32_t tile[];
+  const PartPlan pl = part_plan(fs, B, bits_per_key, count, n_rows, entries_cap, false);
+  if (!pl.ok) return;
+  for (uint32_t b = blockIdx.x; b < pl.base[kMaxFilters]; b += gridDim.x) {
+    int f = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxFilters; i++)
+      if (i < static_cast<int>(fs.n) && b >= pl.base[i]) f = i;
+    uint32_t nb = pl.nb[0], base = pl.base[0];
+#pragma unroll
+    for (int i = 1; i < kMaxFilters; i++)
+      if (i == f) {
+        nb = pl.nb[i];
+        base = pl.base[i];
+      }
+    const uint32_t t = b - base;
+    const uint32_t first = t * pl.tile_blocks;
+    const uint32_t n_blocks = min(pl.tile_blocks, nb - first);
+    for (uint32_t j = threadIdx.x; j < n_blocks * W; j += blockDim.x) tile[j] = 0;
+    __syncthreads();
+    for (uint64_t e = starts[b] + threadIdx.x; e < starts[b + 1]; e += blockDim.x) {
+      const uint64_t v = entries[e];
+      // the entry names its block inside the tile; with nb = 1 and h1 = 0,
+      // insert_lds sets the key's k bits in the block it is pointed at
+      insert_lds<B, K>(tile + static_cast<uint32_t>(v >> 32) * W, 1, k, 0, static_cast<uint32_t>(v));
+    }
+    __syncthreads();
+    uint32_t *out = pick(fs, f).words + static_cast<uint64_t>(first) * W;
+    for (uint32_t j = threadIdx.x; j < n_blocks * W; j += blockDim.x) out[j] = tile[j];
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------- counters
 
 struct SlotTable {
@@ -761,22 +1023,6 @@ __global__ void k_copy_counts(const uint64_t *src, SlotTable t, uint32_t n, uint
 // rescans its words and writes the set rows' ids in ascending order.
 
 constexpr uint64_t kCompactWordsPerBlock = 1024;  // 4 words per thread
-
-__device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *s, uint64_t &total) {
-  const uint32_t t = threadIdx.x;
-  s[t] = v;
-  __syncthreads();
-  for (uint32_t d = 1; d < blockDim.x; d <<= 1) {
-    const uint64_t add = t >= d ? s[t - d] : 0;
-    __syncthreads();
-    s[t] += add;
-    __syncthreads();
-  }
-  total = s[blockDim.x - 1];
-  const uint64_t incl = s[t];
-  __syncthreads();
-  return incl - v;
-}
 
 __global__ void __launch_bounds__(kThreads)
     k_compact_count(const uint64_t *__restrict__ bitmap, uint64_t n_words, uint64_t n_rows,
@@ -947,44 +1193,48 @@ hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, ui
   });
 }
 
-hipError_t launch_size_zero(uint32_t block_bits, uint32_t bits_per_key, const FilterSet &fs,
-                            const uint64_t *count, uint64_t n_rows, hipStream_t s) {
-  if (fs.n == 0) return hipSuccess;
-  uint64_t max_words = 0;
-  for (uint32_t i = 0; i < fs.n; i++)
-    max_words = fs.f[i].cap_words > max_words ? fs.f[i].cap_words : max_words;
-  uint64_t gx = (max_words + kThreads * 4 - 1) / (kThreads * 4);
-  const uint64_t cap = static_cast<uint64_t>(device_info().n_cu) * 2;
-  if (gx > cap) gx = cap;
-  if (gx == 0) gx = 1;
-  hipLaunchKernelGGL(k_size_zero, dim3(static_cast<uint32_t>(gx), fs.n), dim3(kThreads), 0, s, fs,
-                     block_bits, bits_per_key, count, n_rows);
-  return hipGetLastError();
-}
-
 uint64_t build_lds_words() {
   // LDS of one build workgroup: the private filter copies.
   return (static_cast<uint64_t>(device_info().max_lds_block) - 1024) / 4;
 }
 
-hipError_t launch_build(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,
-                        const uint64_t *bitmap, uint32_t *scratch, uint64_t scratch_words,
-                        hipStream_t s) {
+hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, const FilterSet &fs,
+                        uint64_t n_rows, const uint64_t *bitmap, const uint64_t *count,
+                        const BuildScratch *scratch, hipStream_t s) {
+  if (fs.n == 0) return hipSuccess;
   const uint64_t n_words = (n_rows + 63) / 64;
-  if (n_words == 0 || fs.n == 0) return hipSuccess;
-  const uint32_t seg_words = segment_words(n_words);
+  const uint32_t seg_words = segment_words(n_words ? n_words : 1);
   const uint64_t lds_words = build_lds_words();
-  // Private copies only pay off while they fit in LDS; filters whose
-  // capacity is at most the LDS (known on the host) always take that path,
-  // larger ones decide on the device from their actual size.
-  uint64_t cap_words = 0;
-  for (uint32_t i = 0; i < fs.n; i++) cap_words += fs.f[i].cap_words;
-  const uint64_t copy_words = cap_words < lds_words ? cap_words : lds_words;
-  uint64_t parts = scratch && copy_words ? scratch_words / copy_words : 0;
-  const uint64_t work_parts = (n_words + seg_words * 16 - 1) / (seg_words * 16);
-  if (parts > static_cast<uint64_t>(device_info().n_cu)) parts = device_info().n_cu;
-  if (parts > work_parts) parts = work_parts;
-  if (parts == 0) {
+  uint64_t cap_words = 0, max_cap_words = 0;
+  for (uint32_t i = 0; i < fs.n; i++) {
+    cap_words += fs.f[i].cap_words;
+    max_cap_words = fs.f[i].cap_words > max_cap_words ? fs.f[i].cap_words : max_cap_words;
+  }
+  // Which path: private LDS copies when all filters surely fit in LDS, the
+  // partitioned build when the caller gave its buffers, else atomics.
+  enum { kLds, kPart, kAtomic } path = kAtomic;
+  if (scratch && scratch->copies && cap_words <= lds_words) path = kLds;
+  else if (scratch && scratch->entries && scratch->entries_cap) path = kPart;
+  // PT_BUILD_PATH=atomic|part (testing): take that path where it is allowed.
+  if (const char *force = std::getenv("PT_BUILD_PATH")) {
+    if (std::strcmp(force, "atomic") == 0) path = kAtomic;
+    else if (std::strcmp(force, "part") == 0 && scratch && scratch->entries && scratch->entries_cap)
+      path = kPart;
+  }
+  const uint64_t entries_cap = path == kPart ? scratch->entries_cap : 0;
+
+  // Size (and zero, when the build writes in place).
+  {
+    uint64_t gx = (max_cap_words + kThreads * 4 - 1) / (kThreads * 4);
+    const uint64_t cap = static_cast<uint64_t>(device_info().n_cu) * 2;
+    gx = gx > cap ? cap : (gx == 0 ? 1 : gx);
+    hipLaunchKernelGGL(k_size_zero, dim3(static_cast<uint32_t>(gx), fs.n), dim3(kThreads), 0, s, fs,
+                       block_bits, bits_per_key, count, n_rows, entries_cap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n_words == 0) return e;
+  }
+
+  if (path == kAtomic) {
     const uint32_t grid = grid_for((n_words + seg_words - 1) / seg_words, kThreads, 8);
     return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
       constexpr int B = decltype(bb)::value;
@@ -997,21 +1247,78 @@ hipError_t launch_build(uint32_t block_bits, uint32_t k, const FilterSet &fs, ui
       return hipGetLastError();
     });
   }
-  const uint32_t cw = static_cast<uint32_t>(copy_words);
-  const uint32_t n_parts = static_cast<uint32_t>(parts);
+
+  if (path == kLds) {
+    const uint64_t copy_words = cap_words;
+    uint64_t parts = scratch->copies_words / copy_words;
+    const uint64_t work_parts = (n_words + seg_words * 16 - 1) / (seg_words * 16);
+    if (parts > static_cast<uint64_t>(device_info().n_cu)) parts = device_info().n_cu;
+    if (parts > work_parts) parts = work_parts;
+    if (parts == 0) parts = 1;
+    const uint32_t cw = static_cast<uint32_t>(copy_words);
+    const uint32_t n_parts = static_cast<uint32_t>(parts);
+    return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
+      constexpr int B = decltype(bb)::value;
+      auto kern = k == 3 ? k_build_lds<B, 3> : k_build_lds<B, 0>;
+      hipError_t e = allow_lds(reinterpret_cast<const void *>(kern), copy_words * 4);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(kern, dim3(n_parts), dim3(kWideThreads), copy_words * 4, s, fs, k, n_rows,
+                         bitmap, seg_words, scratch->copies, cw);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      uint64_t gx = (copy_words + kWave - 1) / kWave;
+      if (gx > 1024) gx = 1024;
+      hipLaunchKernelGGL((k_build_reduce<B>), dim3(static_cast<uint32_t>(gx), fs.n), dim3(kWideThreads),
+                         0, s, fs, scratch->copies, n_parts, cw);
+      return hipGetLastError();
+    });
+  }
+
+  // Partitioned build. The count and scatter kernels use the same grid, so
+  // each workgroup walks the same rows in both.
+  uint64_t groups = (n_words + seg_words * 16 - 1) / (seg_words * 16);
+  if (groups > scratch->hist_groups) groups = scratch->hist_groups;
+  if (groups == 0) groups = 1;
+  const uint32_t n_groups = static_cast<uint32_t>(groups);
+  const uint32_t W = block_bits / 32;
+  // Upper bound of the device's bucket count: kTargetBuckets plus one
+  // partial tile per filter, or the 64 KB tiles of the largest filters.
+  uint64_t max_buckets = kTargetBuckets + fs.n;
+  {
+    uint64_t big = 0;
+    for (uint32_t i = 0; i < fs.n; i++)
+      big += (fs.f[i].cap_words / W + kTileWords / W - 1) / (kTileWords / W);
+    if (big > max_buckets) max_buckets = big;
+  }
+  if (max_buckets > kMaxBuckets) max_buckets = kMaxBuckets;
+  const uint32_t scan_grid = static_cast<uint32_t>(max_buckets < 2048 ? max_buckets : 2048);
+  uint64_t fill_grid = static_cast<uint64_t>(device_info().n_cu) * 2;
+  if (fill_grid > max_buckets) fill_grid = max_buckets;
   return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
     constexpr int B = decltype(bb)::value;
-    auto kern = k == 3 ? k_build_lds<B, 3> : k_build_lds<B, 0>;
-    hipError_t e = allow_lds(reinterpret_cast<const void *>(kern), copy_words * 4);
+    auto count_k = k_part_count<B>;
+    auto scatter_k = k == 3 ? k_part_scatter<B, 3> : k_part_scatter<B, 0>;
+    auto fill_k = k == 3 ? k_part_fill<B, 3> : k_part_fill<B, 0>;
+    const uint64_t hist_bytes = max_buckets * 4;
+    const uint64_t cursor_bytes = max_buckets * 8;
+    const uint64_t tile_bytes = static_cast<uint64_t>(kTileWords) * 4;
+    hipError_t e = allow_lds(reinterpret_cast<const void *>(count_k), hist_bytes);
+    if (e == hipSuccess) e = allow_lds(reinterpret_cast<const void *>(scatter_k), cursor_bytes);
+    if (e == hipSuccess) e = allow_lds(reinterpret_cast<const void *>(fill_k), tile_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(n_parts), dim3(kWideThreads), copy_words * 4, s, fs, k, n_rows, bitmap,
-                       seg_words, scratch, cw);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    uint64_t gx = (copy_words + kWave - 1) / kWave;
-    if (gx > 1024) gx = 1024;
-    hipLaunchKernelGGL((k_build_reduce<B>), dim3(static_cast<uint32_t>(gx), fs.n), dim3(kWideThreads),
-                       0, s, fs, scratch, n_parts, cw);
+    hipLaunchKernelGGL(count_k, dim3(n_groups), dim3(kWideThreads), hist_bytes, s, fs, bits_per_key,
+                       count, n_rows, bitmap, seg_words, entries_cap, scratch->hist);
+    hipLaunchKernelGGL(k_part_scan_groups, dim3(scan_grid ? scan_grid : 1), dim3(kWideThreads), 0, s, fs,
+                       block_bits, bits_per_key, count, n_rows, entries_cap, scratch->hist, n_groups,
+                       scratch->totals);
+    hipLaunchKernelGGL(k_part_scan_buckets, dim3(1), dim3(kWideThreads), 0, s, fs, block_bits,
+                       bits_per_key, count, n_rows, entries_cap, scratch->totals, scratch->starts);
+    hipLaunchKernelGGL(scatter_k, dim3(n_groups), dim3(kWideThreads), cursor_bytes, s, fs, k, bits_per_key,
+                       count, n_rows, bitmap, seg_words, entries_cap, scratch->hist, scratch->starts,
+                       scratch->entries);
+    hipLaunchKernelGGL(fill_k, dim3(static_cast<uint32_t>(fill_grid ? fill_grid : 1)), dim3(kWideThreads),
+                       tile_bytes, s, fs, k, bits_per_key, count, n_rows, entries_cap, scratch->starts,
+                       scratch->entries);
     return hipGetLastError();
   });
 }

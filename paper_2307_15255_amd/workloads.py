@@ -15,6 +15,7 @@ one spawned child stream per table so tables are independent of each other.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -129,6 +130,53 @@ def star(seed: int = 1, n_fact: int = 100_000_000, dims: tuple[int, ...] = STAR_
                    label=f"star fact {n_fact} rows, dims {list(dims)}, keeps {list(keeps)}")
 
 
+# ----------------------------------------------------------------- snowflake
+
+SNOWFLAKE_ROWS = {"F": 200_000_000, "D1": 50_000_000, "D2": 10_000_000, "D3": 2_000_000,
+                  "D4": 500_000, "D5": 100_000, "D6": 10_000, "D7": 1_000}
+# (table, fk column) -> referenced dimension; D2.k3 -> D3 closes the cycle F - D2 - D3
+SNOWFLAKE_FKS = [("F", "k1", "D1"), ("F", "k2", "D2"), ("F", "k3", "D3"), ("D2", "k3", "D3"),
+                 ("D1", "k4", "D4"), ("D2", "k5", "D5"), ("D3", "k6", "D6"), ("D5", "k7", "D7")]
+SNOWFLAKE_KEEPS = {"D3": 0.005, "D5": 0.05, "D7": 0.10, "D6": 0.30}
+_SCRAMBLE = 0xD6E8FEB86659FD93  # odd: multiplication by it is a bijection of uint64
+
+
+def scrambled_ids(ids: np.ndarray) -> np.ndarray:
+    """Dense ids mapped to int64 keys with non-zero high words (a fixed
+    bijection of the 64-bit integers), so that equal ids give equal keys."""
+    with np.errstate(over="ignore"):
+        return (ids.astype(np.uint64) * np.uint64(_SCRAMBLE) + np.uint64(0x9E37)).view(np.int64)
+
+
+def snowflake(seed: int = 1, scale: float = 1.0, zipf_s: float = 1.1) -> Problem:
+    """Cyclic snowflake of eight tables: fact F with foreign keys into D1, D2,
+    D3; D2 also references D3 (a three-table cycle F - D2 - D3); D1 -> D4,
+    D2 -> D5, D3 -> D6, D5 -> D7. Every key is int64. A dimension's primary
+    key is its scrambled dense id; a foreign key is the scrambled id of a
+    Zipf(zipf_s)-distributed rank, mapped to ids by a seeded permutation.
+    Range predicates keep 0.5 % of D3, 5 % of D5, 10 % of D7, 30 % of D6.
+    `scale` shrinks every table (at least 1 000 rows, 100 for the smallest)."""
+    names = list(SNOWFLAKE_ROWS)
+    rows = {t: max(min(n, 100) if n <= 1000 else 1000, int(round(n * scale))) for t, n in SNOWFLAKE_ROWS.items()}
+    g = dict(zip(names, _streams(seed, len(names))))
+    columns: dict[str, dict[str, np.ndarray]] = {t: {} for t in names}
+    rank_to_id = {}
+    for t in names:
+        if t != "F":
+            n = rows[t]
+            columns[t]["pk"] = scrambled_ids(g[t].permutation(n))
+            columns[t]["attr"] = _uniform_i32(g[t], 0, 1_000_000, n)
+            rank_to_id[t] = g[t].permutation(n)
+    for t, c, ref in SNOWFLAKE_FKS:
+        ranks = zipf_ranks(g[t], rows[ref], zipf_s, rows[t])
+        columns[t][c] = scrambled_ids(rank_to_id[ref][ranks])
+    edges = [(names.index(t), c, names.index(ref), "pk") for t, c, ref in SNOWFLAKE_FKS]
+    preds = [(names.index(t), "attr", "lt", int(round(keep * 1_000_000)), 0)
+             for t, keep in SNOWFLAKE_KEEPS.items()]
+    return Problem(names, [columns[t] for t in names], edges, preds,
+                   label=f"snowflake scale {scale:g} (F {rows['F']} rows), int64 Zipf({zipf_s}) keys")
+
+
 # ------------------------------------------------------------ tiny / random
 
 def tiny_random(rng: np.random.Generator, shape: str = "tree", max_tables: int = 6,
@@ -198,12 +246,11 @@ def tiny_random(rng: np.random.Generator, shape: str = "tree", max_tables: int =
     return Problem([f"T{t}" for t in range(n_t)], columns, edges, preds, label=f"tiny-{shape}")
 
 
-def zipf_ranks(rng: np.random.Generator, n: int, s: float, size: int) -> np.ndarray:
-    """Zipf(s) ranks in [0, n): rank r is drawn with probability proportional
-    to (r+1)^-s. Rejection-inversion sampling (Hormann and Derflinger 1996)
-    with the hat function h(x) = x^-s over [0.5, n + 0.5]."""
-    if abs(s - 1.0) < 1e-12 or s <= 0:
-        raise ValueError("need s > 0, s != 1")
+_ZIPF_CHUNK = 1 << 22
+
+
+def _zipf_chunk(seed_seq: np.random.SeedSequence, n: int, s: float, size: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed_seq))
 
     def h(x):
         return np.power(x, -s)
@@ -220,7 +267,7 @@ def zipf_ranks(rng: np.random.Generator, n: int, s: float, size: int) -> np.ndar
     out = np.empty(size, np.int64)
     filled = 0
     while filled < size:
-        m = min(int((size - filled) * 1.05) + 1024, 1 << 24)
+        m = int((size - filled) * 1.05) + 1024
         u = h_n + rng.random(m) * (h_x1 - h_n)
         x = H_inv(u)
         kk = np.clip(np.floor(x + 0.5), 1, n)
@@ -230,6 +277,26 @@ def zipf_ranks(rng: np.random.Generator, n: int, s: float, size: int) -> np.ndar
         out[filled:filled + take] = good[:take]
         filled += take
     return out
+
+
+def zipf_ranks(rng: np.random.Generator, n: int, s: float, size: int) -> np.ndarray:
+    """Zipf(s) ranks in [0, n): rank r is drawn with probability proportional
+    to (r+1)^-s. Rejection-inversion sampling (Hormann and Derflinger 1996)
+    with the hat function h(x) = x^-s over [0.5, n + 0.5]. Fixed chunks of
+    2^22 draws, each from its own seeded stream, run on a thread pool, so the
+    result depends on `rng` alone and not on the number of threads."""
+    if abs(s - 1.0) < 1e-12 or s <= 0:
+        raise ValueError("need s > 0, s != 1")
+    n_chunks = (size + _ZIPF_CHUNK - 1) // _ZIPF_CHUNK
+    seqs = np.random.SeedSequence(int(rng.integers(0, 2**63 - 1))).spawn(max(1, n_chunks))
+    sizes = [min(_ZIPF_CHUNK, size - i * _ZIPF_CHUNK) for i in range(n_chunks)]
+    if n_chunks <= 1:
+        return _zipf_chunk(seqs[0], n, s, size)
+    import concurrent.futures as cf
+    workers = min(16, os.cpu_count() or 1, n_chunks)
+    with cf.ThreadPoolExecutor(workers) as ex:
+        parts = list(ex.map(lambda i: _zipf_chunk(seqs[i], n, s, sizes[i]), range(n_chunks)))
+    return np.concatenate(parts)
 
 
 def log_uniform_int(rng: np.random.Generator, lo: int, hi: int) -> int:

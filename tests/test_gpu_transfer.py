@@ -114,3 +114,40 @@ def test_repeatable_and_stream_ordered(pt):
     s.synchronize()
     for a, b in zip(first, tr.bitmaps):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("bpk", [8, 12, 16])
+def test_snowflake_scaled(pt, bpk):
+    """Cyclic snowflake (int64 Zipf keys, a three-table cycle) at 1 % size:
+    every bitmap, count and filter word of both passes."""
+    prob = W.snowflake(seed=bpk, scale=0.01)
+    say("snowflake 1%", bpk)
+    check_transfer(pt, prob, 512, 3, bpk)
+
+
+def test_snowflake_full_size(pt):
+    """The full snowflake: 200 M fact rows, 50 M-row D1 whose filter (50 M
+    keys) is read from HBM, every key int64 Zipf(1.1); all bitmaps and
+    counts against the oracle."""
+    t0 = time.time()
+    prob = W.snowflake(seed=1)
+    say("snowflake full: generated", round(time.time() - t0, 1), "s")
+    tr, ref = check_transfer(pt, prob, 512, 3, 12, filters=False)
+    say("snowflake full: counts", ref.counts, "after", round(time.time() - t0, 1), "s")
+
+
+@pytest.mark.parametrize("path,max_entries", [("atomic", None), ("part", None), ("part", "1000")])
+def test_build_paths(pt, monkeypatch, path, max_entries):
+    """Every build path - per-workgroup LDS copies (the default for small
+    filters), the partitioned tile build, and in-place atomic OR (forced, or
+    the partitioned build's fallback when its entry buffer is too small) -
+    writes the same filter words."""
+    monkeypatch.setenv("PT_BUILD_PATH", path)
+    if max_entries:
+        monkeypatch.setenv("PT_MAX_ENTRIES", max_entries)
+    for s in range(4):
+        prob = W.tiny_random(np.random.default_rng(4242 + s), SHAPES[s], max_rows=400, domain=40)
+        say("build path", path, max_entries, s)
+        check_transfer(pt, prob)
+    say("build path", path, max_entries, "star")
+    check_transfer(pt, W.star(seed=9, n_fact=300_000, dims=(60_000, 7_000, 500, 25), payload=0))
