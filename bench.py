@@ -31,8 +31,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="star", choices=["star", "chain", "snowflake"])
+    ap.add_argument("--workload", default="star", choices=["star", "chain", "snowflake", "batch"])
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch: B = 512, k = 3, 10 bits per key for every problem instead of autotuning")
+    ap.add_argument("--problems", type=int, default=256, help="batch: number of problems")
     ap.add_argument("--bpk", type=int, default=None, help="bits per key (default 10; snowflake 12)")
+    ap.add_argument("--no-append", action="store_true",
+                    help="builds rescan the table instead of reading keys appended by its probe")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="compare the result with the oracle")
@@ -77,6 +82,9 @@ def main():
     from paper_2307_15255_amd import pt
     from paper_2307_15255_amd import workloads as W
 
+    if args.workload == "batch":
+        return bench_batch(args, torch, pt, W)
+
     t0 = time.time()
     if args.workload == "star":
         prob = W.star(seed=args.seed)
@@ -95,7 +103,7 @@ def main():
     bpk = cfg["bits_per_key"] = args.bpk or cfg["bits_per_key"]
     gen_s = time.time() - t0
     dp = pt.DeviceProblem(prob)
-    tr = pt.Transfer(dp, pt.params(512, 3, bpk))
+    tr = pt.Transfer(dp, pt.params(512, 3, bpk, pt.PT_FLAG_NO_APPEND if args.no_append else 0))
     torch.cuda.synchronize()
     print(f"# inputs ready in {time.time() - t0:.1f}s (generation {gen_s:.1f}s)", file=sys.stderr, flush=True)
 
@@ -190,6 +198,102 @@ def main():
         if args.check:
             ok = all(np.array_equal(tr.bitmap(t), ref.bitmaps[t]) for t in range(prob.n_tables))
             out["check"] = "bit-exact" if ok else "MISMATCH"
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, torch, pt, W):
+    """256 independent chain and star problems (tables log-uniform on
+    [10 k, 5 M] rows) run as one batch: one graph launch per step. Beside it,
+    the same problems one at a time with plain pt_transfer launches."""
+    from paper_2307_15255_amd import autotune
+    t0 = time.time()
+    probs = W.batch(seed=args.seed, n_problems=args.problems)
+    dps = [pt.DeviceProblem(p) for p in probs]
+    torch.cuda.synchronize()
+    print(f"# batch inputs ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    if args.no_tune:
+        ps, tune_s = [pt.params(512, 3, 10) for _ in probs], 0.0
+    else:
+        t1 = time.time()
+        ps, _ = autotune.tune(probs)
+        tune_s = time.time() - t1
+    chosen: dict[str, int] = {}
+    for p in ps:
+        key = f"B{p.block_bits}/k{p.k}/bpk{p.bits_per_key}"
+        chosen[key] = chosen.get(key, 0) + 1
+    bt = pt.Batch(dps, ps)
+    n_launch, n_probed = bt.info()
+    for _ in range(args.warmup):
+        bt.run()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        bt.run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1000 / args.steps
+    # probe launches timed with HIP events on an eager run
+    pt.pt_profile_enable(2)
+    bt.run(eager=True)
+    torch.cuda.synchronize()
+    pt.pt_profile_enable(False)
+    recs = pt.pt_profile_read(4096)
+    dom = max(recs, key=lambda r: r["ms"])
+    achieved = dom["bytes"] / (dom["ms"] / 1000) / 1e9
+    all_probe_gbs = sum(r["bytes"] for r in recs) / (sum(r["ms"] for r in recs) / 1000) / 1e9
+    # one query at a time, plain launches
+    trs = [pt.Transfer(dp, p) for dp, p in zip(dps, ps)]
+    for tr in trs:
+        tr.run()
+    torch.cuda.synchronize()
+    reps = max(1, min(5, args.steps // 10))
+    t = time.perf_counter()
+    for _ in range(reps):
+        for tr in trs:
+            tr.run()
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - t) * 1000 / reps
+    out = {
+        "metric": "G rows probed/s",
+        "value": round(n_probed / (ms / 1000) / 1e9, 3),
+        "unit": "G rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "batch", "problems": len(probs), "rows": sum(sum(d.n_rows) for d in dps),
+                   "table_rows": "log-uniform [10k, 5M]", "params": chosen, "autotune_s": round(tune_s, 2),
+                   "launches_per_run": n_launch},
+        "rows_probed_per_step": n_probed,
+        "one_at_a_time": {"ms_per_step": round(single_ms, 4),
+                          "value": round(n_probed / (single_ms / 1000) / 1e9, 3),
+                          "speedup_of_batch": round(single_ms / ms, 2)},
+        "roofline": {"bound": "hbm", "kernel": f"batch probe launch {dom['table']} pass {dom['pass_']}",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes": dom["bytes"], "avg_ms": round(dom["ms"], 5),
+                     "all_probe_launches_gbs": round(all_probe_gbs, 1)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        # a bounded sample: the first problems until about 10 s of oracle work
+        t = time.perf_counter()
+        rows = 0
+        for i, prob in enumerate(probs):
+            p = ps[i]
+            oracle.transfer(prob, p.block_bits, p.k, p.bits_per_key)
+            rows += rows_probed(prob, orientation(prob))
+            if time.perf_counter() - t > 10:
+                break
+        cpu_s = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(rows / cpu_s / 1e9, 4), "unit": "G rows/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"the first {i + 1} problems ({rows} rows probed in {cpu_s:.2f} s, "
+                                         f"single thread)"}
     print(json.dumps(out), flush=True)
 
 

@@ -133,8 +133,15 @@ typedef struct pt_params {
   uint32_t block_bits;   /* B: 32, 64, 128, 256, 512 or 1024 */
   uint32_t k;            /* 1..16 */
   uint32_t bits_per_key; /* 1..64 */
-  uint32_t flags;        /* 0 */
+  uint32_t flags;        /* 0 or PT_FLAG_NO_APPEND */
 } pt_params;
+
+/* pt_transfer normally appends the keys of a probe's surviving rows while it
+ * scans the table, so that the filters the table then builds read those keys
+ * instead of scanning it a second time (Sec. 3.2: the transformation scans
+ * a table once). With this flag the builds scan the table's selected rows
+ * again and the workspace holds no appended keys. The bits are the same. */
+#define PT_FLAG_NO_APPEND 1u
 
 /* A Bloom filter in device memory. `words` holds cap_words uint32 words; the
  * filter in use is its first nb * B/32 words, where nb is the uint64 at
@@ -148,7 +155,7 @@ typedef struct pt_bloom {
 
 /* Per-kernel timing record (see pt_profile_enable). */
 typedef struct pt_kernel_time {
-  char name[24];   /* "local", "probe", "size", "build", "count", "compact" */
+  char name[24];   /* "local", "probe", "size", "build", "count", "compact", "batch probe" */
   uint32_t table;  /* table index inside pt_transfer, else 0 */
   uint32_t pass;   /* 0 local, 1 forward, 2 backward; 0 outside pt_transfer */
   uint64_t rows;   /* rows the kernel scanned */
@@ -234,6 +241,63 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
 pt_status pt_transfer_filter(const pt_graph *graph, const pt_table *tables,
                              const pt_params *params, void *d_ws, uint32_t pass, uint32_t edge,
                              pt_bloom *out, uint32_t *builder);
+
+/* ---------------------------------------------------------------- batches
+ *
+ * Many independent transfer problems run together (the paper evaluates one
+ * query at a time; batching is an addition). Every step of every problem
+ * is grouped with the same step of the others: one launch per step and
+ * schedule level covers all problems (tables of a level depend only on
+ * lower levels, so the bits equal those of pt_transfer on each problem), and
+ * the whole sequence is captured once into a HIP graph that each run
+ * launches with a single call. */
+
+/* One problem of a batch: the arguments of pt_transfer. */
+typedef struct pt_problem {
+  const pt_graph *graph;
+  const pt_table *tables;
+  const pt_pred *preds;
+  uint32_t n_preds;
+  uint32_t reserved;          /* 0 */
+  pt_params params;           /* each problem may use its own parameters */
+  uint64_t *const *d_bitmaps; /* d_bitmaps[t]: table t's final bitmap */
+  uint64_t *d_counts;         /* NULL, or n_tables device uint64 */
+} pt_problem;
+
+/* A prepared batch (host object). */
+typedef struct pt_batch pt_batch;
+
+/* Bytes of workspace a batch of these problems needs (every filter of both
+ * passes of every problem at its largest size, counters and task tables). */
+pt_status pt_batch_workspace_size(uint32_t n_problems, const pt_problem *problems, size_t *bytes);
+
+/* Plans the batch: checks every problem as pt_transfer does, writes the
+ * task tables of every launch into d_ws (256-byte aligned, at least
+ * pt_batch_workspace_size bytes) and returns a handle in *out. Blocking (it
+ * copies the tables and synchronizes the device); call it once, then run
+ * the batch as often as wanted. The problems' device buffers (columns,
+ * bitmaps, counts) and d_ws must stay valid until pt_batch_free. Host
+ * arrays in `problems` are only read during this call. */
+pt_status pt_batch_prepare(uint32_t n_problems, const pt_problem *problems, void *d_ws,
+                           size_t ws_bytes, pt_batch **out);
+
+/* Runs the batch on `stream`: every problem's bitmaps and counts are
+ * written as pt_transfer would write them. flags = 0 launches the captured
+ * graph (captured on the first run); PT_BATCH_EAGER enqueues the kernels one
+ * by one instead. Runs of one batch on overlapping streams race. */
+#define PT_BATCH_EAGER 1u
+pt_status pt_batch_run(pt_batch *batch, pt_stream stream, uint32_t flags);
+
+/* Kernel launches in one run of the batch, and rows it probes (the sum
+ * over probe steps of the probed table's rows). */
+pt_status pt_batch_info(const pt_batch *batch, uint32_t *n_launches, uint64_t *rows_probed);
+
+/* Frees the handle and its graph (after the last run has completed). */
+void pt_batch_free(pt_batch *batch);
+
+/* Convenience: prepare, run eagerly on `stream`, wait, free. */
+pt_status pt_transfer_batch(uint32_t n_problems, const pt_problem *problems, void *d_ws, size_t ws_bytes,
+                            pt_stream stream);
 
 /* Kernel timing. While enabled on the calling thread (on = 1: every launch
  * of the calls above; on = 2: probe launches only; 0: off), each launch is

@@ -7,7 +7,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -87,7 +89,7 @@ class Timed {
   Timed(const char *name, uint32_t table, uint32_t pass, uint64_t rows, uint64_t bytes,
         hipStream_t s)
       : s_(s) {
-    if (g_prof_mode == 0 || (g_prof_mode == 2 && std::strcmp(name, "probe") != 0)) return;
+    if (!name || g_prof_mode == 0 || (g_prof_mode == 2 && std::strstr(name, "probe") == nullptr)) return;
     rec_.t = pt_kernel_time{};
     std::snprintf(rec_.t.name, sizeof rec_.t.name, "%s", name);
     rec_.t.table = table;
@@ -124,7 +126,7 @@ pt_status check_params(const pt_params *p) {
   if (p->k < 1 || p->k > 16) return fail(PT_EINVAL, "k %u outside [1, 16]", p->k);
   if (p->bits_per_key < 1 || p->bits_per_key > 64)
     return fail(PT_EINVAL, "bits_per_key %u outside [1, 64]", p->bits_per_key);
-  if (p->flags != 0) return fail(PT_EINVAL, "params.flags must be 0");
+  if ((p->flags & ~PT_FLAG_NO_APPEND) != 0) return fail(PT_EINVAL, "params.flags: unknown bits 0x%x", p->flags);
   return PT_OK;
 }
 
@@ -200,12 +202,80 @@ struct Plan {
   uint64_t off_hist = 0, off_totals = 0, off_starts = 0, off_entries = 0;  // partitioned builds
   uint32_t hist_groups = 0;
   uint64_t entries_cap = 0;
+  uint64_t off_app_counts = 0, off_app = 0;  // appended survivor keys (one probe's at a time)
   uint64_t total = 0;
 };
 
-constexpr uint64_t kMaxEntries = 64ull << 20;  // partitioned-build entries (8 bytes each)
+constexpr uint64_t kMaxEntries = 64ull << 20;  // partitioned-build entries (4 bytes each)
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+pt_status check_preds(const Plan &pl, const pt_table *tables, const pt_pred *preds, uint32_t n_preds) {
+  if (n_preds > 0 && !preds) return fail(PT_EINVAL, "preds is NULL");
+  for (uint32_t i = 0; i < n_preds; i++) {
+    if (preds[i].table >= pl.n_t) return fail(PT_EINVAL, "predicate %u: table out of range", i);
+    if (preds[i].col >= tables[preds[i].table].n_cols)
+      return fail(PT_EINVAL, "predicate %u: column out of range", i);
+    if (preds[i].op > PT_BETWEEN) return fail(PT_EINVAL, "predicate %u: op %u", i, preds[i].op);
+  }
+  return PT_OK;
+}
+
+uint32_t col_at(const pt_graph *g, uint32_t e, uint32_t table) {
+  return g->edges[e].u == table ? g->edges[e].u_col : g->edges[e].v_col;
+}
+
+// Appended keys (the filter transformation scans a table once, Sec. 3.2):
+// the probe of table v in pass p appends its survivors' keys of `cols`, which
+// the builds of v in pass `pass` then read, when
+//   - v also builds in pass p (cols: its outgoing columns of pass p), or
+//   - p is the forward pass, v builds nothing in it and is its last table:
+//     v is then the first table of the backward pass, and its backward
+//     builds (on the columns of its forward incoming edges) start from the
+//     forward survivors.
+struct AppendPlan {
+  std::vector<uint32_t> cols;  // empty: nothing appended
+  uint32_t pass = 0;
+};
+
+AppendPlan append_plan(const Plan &pl, const pt_graph *g, const pt_table *tables, const pt_params &params,
+                       uint32_t p, uint32_t v) {
+  AppendPlan ap;
+  if ((params.flags & PT_FLAG_NO_APPEND) || tables[v].n_rows == 0) return ap;
+  auto from = [&](uint32_t q, uint32_t e) { return q == 0 ? pl.src[e] : pl.dst[e]; };
+  bool in = false, out = false;
+  for (uint32_t e = 0; e < pl.n_e; e++) {
+    in = in || from(1 - p, e) == v;  // the edge ends at v in pass p
+    out = out || from(p, e) == v;
+  }
+  if (!in) return ap;
+  uint32_t q;
+  if (out)
+    q = p;
+  else if (p == 0 && pl.order.back() == v)
+    q = 1;
+  else
+    return ap;
+  for (uint32_t e = 0; e < pl.n_e; e++) {
+    if (from(q, e) != v) continue;
+    const uint32_t c = col_at(g, e, v);
+    if (std::find(ap.cols.begin(), ap.cols.end(), c) == ap.cols.end()) ap.cols.push_back(c);
+  }
+  if (ap.cols.empty() || ap.cols.size() > static_cast<size_t>(kMaxAppend)) ap.cols.clear();
+  ap.pass = q;
+  return ap;
+}
+
+// Entries per appended column: a quarter of the rows (a region with more
+// survivors is walked instead) plus room for the regions of small tables.
+uint64_t append_capacity(uint64_t n_rows) { return (n_rows + 3) / 4 + 65536; }
+
+uint64_t append_bytes(const AppendPlan &ap, const pt_table &t) {
+  uint64_t b = 0;
+  for (uint32_t c : ap.cols) b += align256(append_capacity(t.n_rows) * key_bytes(t.cols[c]));
+  return b;
+}
+
 
 pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *params, Plan &pl) {
   if (!g) return fail(PT_EINVAL, "graph is NULL");
@@ -332,14 +402,21 @@ pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *
     if (const char *env = std::getenv("PT_MAX_ENTRIES")) max_entries = std::strtoull(env, nullptr, 10);
     pl.entries_cap = std::min(group_entries, max_entries);
     pl.off_entries = off;
-    off = align256(off + pl.entries_cap * 8);
+    off = align256(off + pl.entries_cap * 4);
+  }
+  // Appended keys: region counts and the largest probe's columns.
+  uint64_t app_bytes = 0;
+  for (uint32_t p = 0; p < 2; p++)
+    for (uint32_t v = 0; v < pl.n_t; v++)
+      app_bytes = std::max(app_bytes, append_bytes(append_plan(pl, g, tables, *params, p, v), tables[v]));
+  if (app_bytes > 0) {
+    pl.off_app_counts = off;
+    off = align256(off + static_cast<uint64_t>(kMaxRegions) * 4);
+    pl.off_app = off;
+    off += app_bytes;
   }
   pl.total = off;
   return PT_OK;
-}
-
-uint32_t col_at(const pt_graph *g, uint32_t e, uint32_t table) {
-  return g->edges[e].u == table ? g->edges[e].u_col : g->edges[e].v_col;
 }
 
 }  // namespace
@@ -422,21 +499,24 @@ pt_status pt_bloom_capacity(uint64_t max_keys, const pt_params *params, uint64_t
   return PT_OK;
 }
 
+// Builds n_filters filters, kMaxFilters per scan. With app, filter i reads
+// its keys from appended column app_idx[i] - 1.
 static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
                                uint64_t n_rows, const uint64_t *d_bitmap, const uint64_t *d_count,
-                               const BuildScratch *scratch, hipStream_t s, uint32_t table,
-                               uint32_t pass) {
+                               const BuildScratch *scratch, const AppendSet *app,
+                               const uint32_t *app_idx, hipStream_t s, uint32_t table, uint32_t pass) {
   const pt_params &p = filters[0].params;
   for (uint32_t done = 0; done < n_filters;) {
     FilterSet fs{};
     uint64_t bytes = (n_rows + 63) / 64 * 8;
     for (; done < n_filters && fs.n < kMaxFilters; done++, fs.n++) {
       fs.f[fs.n] = make_ref(keys[done], filters[done]);
+      if (app) fs.f[fs.n].app = app_idx[done];
       bytes += n_rows * key_bytes(keys[done]);
     }
     Timed tm("build", table, pass, n_rows, bytes, s);
     pt_status st = check_hip(launch_build(p.block_bits, p.k, p.bits_per_key, fs, n_rows, d_bitmap,
-                                          d_count, scratch, s),
+                                          d_count, scratch, app, s),
                              "build launch");
     if (st != PT_OK) return st;
   }
@@ -447,10 +527,13 @@ static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const 
 // `rows` (optional) give each filter's builder count and row total, which
 // only order the tests. input_all: the bitmap holds every row and is not
 // read by the first launch. count_zeroed: *d_count already holds zero.
+// app (optional): the last scan appends the survivors' keys (see
+// launch_probe); capacity: entries of each appended column.
 static pt_status probe_filters(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
                                const uint64_t *const *sel, const uint64_t *rows, uint64_t n_rows,
                                uint64_t *d_bitmap, uint64_t *d_count, bool input_all,
-                               bool count_zeroed, hipStream_t s, uint32_t table, uint32_t pass) {
+                               bool count_zeroed, AppendSet *app, uint64_t capacity, hipStream_t s,
+                               uint32_t table, uint32_t pass) {
   const pt_params &p = filters[0].params;
   if (d_count && !count_zeroed) {
     pt_status st = check_hip(launch_zero_u64(d_count, 1, s), "zero count");
@@ -471,7 +554,8 @@ static pt_status probe_filters(uint32_t n_filters, const pt_column *keys, const 
     const bool last = done >= n_filters;
     Timed tm("probe", table, pass, n_rows, bytes, s);
     pt_status st = check_hip(launch_probe(p.block_bits, p.k, fs, n_rows, d_bitmap,
-                                          last ? d_count : nullptr, input_all && first, s),
+                                          last ? d_count : nullptr, input_all && first,
+                                          last ? app : nullptr, capacity, s),
                              "probe launch");
     if (st != PT_OK) return st;
   }
@@ -492,7 +576,7 @@ pt_status pt_bloom_build(uint32_t n_filters, const pt_column *keys, const pt_blo
     if (st != PT_OK) return st;
   }
   return build_filters(n_filters, keys, filters, n_rows, d_bitmap, d_bitmap ? d_count : nullptr,
-                       nullptr, reinterpret_cast<hipStream_t>(stream), 0, 0);
+                       nullptr, nullptr, nullptr, reinterpret_cast<hipStream_t>(stream), 0, 0);
 }
 
 pt_status pt_bloom_probe(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
@@ -522,7 +606,7 @@ pt_status pt_bloom_probe(uint32_t n_filters, const pt_column *keys, const pt_blo
     return check_hip(launch_local_filter(ps, n_rows, d_bitmap, d_count, s), "count launch");
   }
   return probe_filters(n_filters, keys, filters, nullptr, nullptr, n_rows, d_bitmap, d_count, false,
-                       false, s, 0, 0);
+                       false, nullptr, 0, s, 0, 0);
 }
 
 pt_status pt_compact_workspace_size(uint64_t n_rows, size_t *bytes) {
@@ -588,13 +672,8 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
   if (pl.n_t > 0 && !d_bitmaps) return fail(PT_EINVAL, "d_bitmaps is NULL");
   for (uint32_t t = 0; t < pl.n_t; t++)
     if (tables[t].n_rows > 0 && !d_bitmaps[t]) return fail(PT_EINVAL, "d_bitmaps[%u] is NULL", t);
-  if (n_preds > 0 && !preds) return fail(PT_EINVAL, "preds is NULL");
-  for (uint32_t i = 0; i < n_preds; i++) {
-    if (preds[i].table >= pl.n_t) return fail(PT_EINVAL, "predicate %u: table out of range", i);
-    if (preds[i].col >= tables[preds[i].table].n_cols)
-      return fail(PT_EINVAL, "predicate %u: column out of range", i);
-    if (preds[i].op > PT_BETWEEN) return fail(PT_EINVAL, "predicate %u: op %u", i, preds[i].op);
-  }
+  st = check_preds(pl, tables, preds, n_preds);
+  if (st != PT_OK) return st;
 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char *ws = static_cast<char *>(d_ws);
@@ -657,7 +736,7 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
     scratch.hist_groups = pl.hist_groups;
     scratch.totals = reinterpret_cast<uint64_t *>(ws + pl.off_totals);
     scratch.starts = reinterpret_cast<uint64_t *>(ws + pl.off_starts);
-    scratch.entries = reinterpret_cast<uint64_t *>(ws + pl.off_entries);
+    scratch.entries = reinterpret_cast<uint32_t *>(ws + pl.off_entries);
     scratch.entries_cap = pl.entries_cap;
   }
 
@@ -669,6 +748,10 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
   std::vector<const uint64_t *> sel;
   std::vector<uint64_t> rows;
   std::vector<const uint64_t *> built_sel(2ull * pl.n_e, nullptr);  // builder count per filter
+  // The appended keys waiting for their builds: table, pass, columns.
+  AppendSet pending{};
+  uint32_t pending_table = pl.n_t, pending_pass = 2;
+  std::vector<uint32_t> pending_cols, app_idx;
   for (uint32_t p = 0; p < 2; p++) {
     const std::vector<uint32_t> &from = p == 0 ? pl.src : pl.dst;
     const std::vector<uint32_t> &to = p == 0 ? pl.dst : pl.src;
@@ -689,29 +772,57 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
       }
       if (!keys.empty()) {
         uint64_t *cnt = counts + (p + 1) * pl.n_t + v;
+        const AppendPlan ap = append_plan(pl, graph, tables, *params, p, v);
+        AppendSet app{};
+        if (!ap.cols.empty()) {
+          char *dst = ws + pl.off_app;
+          app.n_cols = static_cast<uint32_t>(ap.cols.size());
+          app.counts = reinterpret_cast<uint32_t *>(ws + pl.off_app_counts);
+          for (uint32_t c = 0; c < app.n_cols; c++) {
+            const pt_column &col = tb.cols[ap.cols[c]];
+            app.src[c] = col.data;
+            app.key64[c] = col.dtype == PT_I64;
+            app.dst[c] = dst;
+            dst += align256(append_capacity(tb.n_rows) * key_bytes(col));
+          }
+        }
         st = probe_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), sel.data(),
                            rows.data(), tb.n_rows, d_bitmaps[v], cnt, all_rows[v] != 0,
-                           /*count_zeroed=*/true, s, v, p + 1);
+                           /*count_zeroed=*/true, ap.cols.empty() ? nullptr : &app,
+                           append_capacity(tb.n_rows), s, v, p + 1);
         if (st != PT_OK) return st;
+        if (app.n_cols > 0) {
+          pending = app;
+          pending_table = v;
+          pending_pass = ap.pass;
+          pending_cols = ap.cols;
+        }
         cur[v] = p + 1;
         all_rows[v] = 0;
       }
       // Outgoing filters: sized from v's count after this pass's probes.
+      const bool use_app = pending_table == v && pending_pass == p && !all_rows[v];
       keys.clear();
       blooms.clear();
+      app_idx.clear();
       for (uint32_t e = 0; e < pl.n_e; e++) {
         if (from[e] != v) continue;
-        keys.push_back(tb.cols[col_at(graph, e, v)]);
+        const uint32_t c = col_at(graph, e, v);
+        keys.push_back(tb.cols[c]);
         blooms.push_back(bloom_at(p * pl.n_e + e));
         built_sel[p * pl.n_e + e] = all_rows[v] ? nullptr : counts + cur[v] * pl.n_t + v;
+        if (use_app)
+          app_idx.push_back(static_cast<uint32_t>(
+              std::find(pending_cols.begin(), pending_cols.end(), c) - pending_cols.begin() + 1));
       }
       if (!keys.empty()) {
         const bool all = all_rows[v] != 0;
         st = build_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), tb.n_rows,
                            all ? nullptr : d_bitmaps[v], all ? nullptr : counts + cur[v] * pl.n_t + v,
-                           &scratch, s, v, p + 1);
+                           &scratch, use_app ? &pending : nullptr, app_idx.data(), s, v, p + 1);
         if (st != PT_OK) return st;
       }
+      if (pending_table == v && pending_pass == p) pending_table = pl.n_t;
     }
   }
 
@@ -730,6 +841,488 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
     if (st != PT_OK) return st;
   }
   return PT_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+namespace {
+
+// Longest path from a source of pass p (0: forward edges, 1: reversed) to
+// every table: the schedule level. Tables of one level depend only on lower
+// levels, so all problems can run level by level in lockstep.
+std::vector<uint32_t> levels(const Plan &pl, uint32_t p) {
+  std::vector<uint32_t> lvl(pl.n_t, 0);
+  std::vector<uint32_t> seq = pl.order;
+  if (p == 1) std::reverse(seq.begin(), seq.end());
+  for (uint32_t v : seq)
+    for (uint32_t e = 0; e < pl.n_e; e++) {
+      const uint32_t from = p == 0 ? pl.src[e] : pl.dst[e];
+      const uint32_t to = p == 0 ? pl.dst[e] : pl.src[e];
+      if (to == v) lvl[v] = std::max(lvl[v], lvl[from] + 1);
+    }
+  return lvl;
+}
+
+enum LaunchKind : uint32_t { kZero, kLocal, kSize, kBuild, kProbe, kCopy };
+
+struct BatchLaunch {
+  LaunchKind kind;
+  uint32_t block_bits = 0, k = 0;
+  bool any64 = false;
+  uint64_t tasks_off = 0, first_off = 0;  // workspace offsets
+  uint32_t n = 0, grid = 0, lds_words = 0;
+  uint32_t pass = 0;                      // 1 forward, 2 backward (probes, builds)
+  uint64_t rows = 0, bytes = 0;           // rows scanned, algorithmic bytes (probes)
+};
+
+// Task lists of one launch before they are laid out.
+struct LaunchDraft {
+  BatchLaunch l;
+  std::vector<char> tasks;  // packed task structs
+  std::vector<uint32_t> first{0};
+  template <class T>
+  void add(const T &t, uint32_t blocks) {
+    const char *b = reinterpret_cast<const char *>(&t);
+    tasks.insert(tasks.end(), b, b + sizeof(T));
+    first.push_back(first.back() + std::max<uint32_t>(blocks, 1));
+  }
+};
+
+uint32_t clamp_u32(uint64_t v, uint64_t lo, uint64_t hi) {
+  return static_cast<uint32_t>(std::min(std::max(v, lo), hi));
+}
+
+struct BatchPlan {
+  std::vector<Plan> plans;
+  std::vector<uint64_t> off_problem;  // per problem: its nb and filter region
+  uint64_t off_counts = 0, n_counts = 0;
+  uint64_t data_end = 0, total = 0;
+  std::vector<LaunchDraft> drafts;
+  uint64_t rows_probed = 0;
+};
+
+// Plans a batch. With ws == nullptr only the sizes are computed (device
+// pointers in the task tables are then offsets from 0).
+pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, BatchPlan &bp) {
+  if (n_problems > 0 && !probs) return fail(PT_EINVAL, "problems is NULL");
+  bp.plans.resize(n_problems);
+  bp.off_problem.resize(n_problems);
+  uint64_t off = 256;
+  uint64_t n_counts = 0;
+  for (uint32_t i = 0; i < n_problems; i++) {
+    const pt_problem &pr = probs[i];
+    Plan &pl = bp.plans[i];
+    pt_params params = pr.params;
+    params.flags |= PT_FLAG_NO_APPEND;
+    pt_status st = make_plan(pr.graph, pr.tables, &params, pl);
+    if (st != PT_OK) return fail(st, "problem %u: %s", i, g_error.c_str());
+    st = check_preds(pl, pr.tables, pr.preds, pr.n_preds);
+    if (st != PT_OK) return fail(st, "problem %u: %s", i, g_error.c_str());
+    if (pr.reserved != 0) return fail(PT_EINVAL, "problem %u: reserved field is not 0", i);
+    if (pl.n_t > 0 && !pr.d_bitmaps) return fail(PT_EINVAL, "problem %u: d_bitmaps is NULL", i);
+    for (uint32_t t = 0; t < pl.n_t; t++)
+      if (pr.tables[t].n_rows > 0 && !pr.d_bitmaps[t])
+        return fail(PT_EINVAL, "problem %u: d_bitmaps[%u] is NULL", i, t);
+    n_counts += 3ull * pl.n_t;
+  }
+  bp.off_counts = off;
+  bp.n_counts = n_counts;
+  off = align256(off + n_counts * 8);
+  // Each problem: block counts of both passes, then its filters.
+  for (uint32_t i = 0; i < n_problems; i++) {
+    const Plan &pl = bp.plans[i];
+    bp.off_problem[i] = off;
+    off = align256(off + 2ull * pl.n_e * 8);
+    for (uint32_t slot = 0; slot < 2 * pl.n_e; slot++) off = align256(off + pl.cap_words[slot] * 4);
+  }
+  bp.data_end = off;
+
+  auto ptr = [&](uint64_t o) -> char * { return ws ? ws + o : reinterpret_cast<char *>(o); };
+  const uint64_t lds_max = static_cast<uint64_t>(device_info().max_lds_block) - 1024;
+
+  // Per problem: counter slots, filter refs.
+  uint64_t count_base = bp.off_counts;
+  std::vector<uint64_t> counts_of(n_problems);
+  for (uint32_t i = 0; i < n_problems; i++) {
+    counts_of[i] = count_base;
+    count_base += 3ull * bp.plans[i].n_t * 8;
+  }
+  auto count_ptr = [&](uint32_t i, uint32_t slot, uint32_t t) {
+    return reinterpret_cast<uint64_t *>(ptr(counts_of[i] + (static_cast<uint64_t>(slot) * bp.plans[i].n_t + t) * 8));
+  };
+  auto filter_ref = [&](uint32_t i, uint32_t p, uint32_t e, uint32_t table) {
+    const Plan &pl = bp.plans[i];
+    const uint32_t slot = p * pl.n_e + e;
+    // Filter offsets inside the problem region mirror make_plan's order.
+    uint64_t o = align256(bp.off_problem[i] + 2ull * pl.n_e * 8);
+    for (uint32_t j = 0; j < slot; j++) o = align256(o + pl.cap_words[j] * 4);
+    FilterRef r{};
+    const pt_column &c = probs[i].tables[table].cols[col_at(probs[i].graph, e, table)];
+    r.keys = c.data;
+    r.key64 = c.dtype == PT_I64;
+    r.words = reinterpret_cast<uint32_t *>(ptr(o));
+    r.nb = reinterpret_cast<uint64_t *>(ptr(bp.off_problem[i] + slot * 8ull));
+    r.cap_words = pl.cap_words[slot];
+    return r;
+  };
+
+  // 1. Zero every counter; 2. local predicates of every table (tables
+  // without predicates get every row, so every bitmap is materialised).
+  {
+    LaunchDraft d;
+    d.l.kind = kZero;
+    d.l.n = static_cast<uint32_t>(std::min<uint64_t>(n_counts, 0xFFFFFFFFu));
+    bp.drafts.push_back(std::move(d));
+  }
+  {
+    LaunchDraft d;
+    d.l.kind = kLocal;
+    for (uint32_t i = 0; i < n_problems; i++) {
+      const pt_problem &pr = probs[i];
+      for (uint32_t t = 0; t < bp.plans[i].n_t; t++) {
+        const pt_table &tb = pr.tables[t];
+        if (tb.n_rows == 0) continue;
+        std::vector<const pt_pred *> mine;
+        for (uint32_t j = 0; j < pr.n_preds; j++)
+          if (pr.preds[j].table == t) mine.push_back(&pr.preds[j]);
+        if (mine.size() > static_cast<size_t>(kMaxPreds))
+          return fail(PT_EUNSUPPORTED, "problem %u table %u: more than %d predicates in a batch", i, t, kMaxPreds);
+        LocalTask lt{};
+        for (const pt_pred *q : mine) {
+          const pt_column &c = tb.cols[q->col];
+          lt.ps.p[lt.ps.n++] = PredRef{c.data, c.dtype == PT_I64 ? 1u : 0u, q->op, q->lo, q->hi};
+        }
+        lt.n_rows = tb.n_rows;
+        lt.bitmap = pr.d_bitmaps[t];
+        lt.count = count_ptr(i, 0, t);
+        lt.seg_words = 16;
+        const uint64_t n_words = (tb.n_rows + 63) / 64;
+        d.add(lt, clamp_u32((n_words + 16 * 16 * 4 - 1) / (16 * 16 * 4), 1, 512));
+      }
+    }
+    d.l.n = static_cast<uint32_t>(d.first.size() - 1);
+    bp.drafts.push_back(std::move(d));
+  }
+
+  // 3. Both passes, level by level: the probes of a level, then the sizes
+  // and builds of the filters its tables send.
+  std::vector<std::vector<uint32_t>> cur(n_problems);  // counter slot of each table's count
+  std::vector<std::vector<uint32_t>> lvl[2];
+  uint32_t max_lvl[2] = {0, 0};
+  for (uint32_t p = 0; p < 2; p++) {
+    lvl[p].resize(n_problems);
+    for (uint32_t i = 0; i < n_problems; i++) {
+      lvl[p][i] = levels(bp.plans[i], p);
+      for (uint32_t v : lvl[p][i]) max_lvl[p] = std::max(max_lvl[p], v);
+    }
+  }
+  for (uint32_t i = 0; i < n_problems; i++) cur[i].assign(bp.plans[i].n_t, 0);
+  using Key = std::tuple<uint32_t, uint32_t, bool>;  // block_bits, k, any64
+  for (uint32_t p = 0; p < 2; p++) {
+    for (uint32_t L = 0; L <= max_lvl[p]; L++) {
+      // Probes: one launch per (parameters, key width, chunk of kMaxProbe).
+      std::map<std::pair<Key, uint32_t>, LaunchDraft> probes;
+      std::map<std::pair<Key, uint32_t>, uint64_t> probe_need;
+      for (uint32_t i = 0; i < n_problems; i++) {
+        const Plan &pl = bp.plans[i];
+        const pt_problem &pr = probs[i];
+        for (uint32_t v = 0; v < pl.n_t; v++) {
+          if (lvl[p][i][v] != L || pr.tables[v].n_rows == 0) continue;
+          std::vector<uint32_t> in;
+          for (uint32_t e = 0; e < pl.n_e; e++)
+            if ((p == 0 ? pl.dst[e] : pl.src[e]) == v) in.push_back(e);
+          if (in.empty()) continue;
+          bp.rows_probed += pr.tables[v].n_rows;
+          for (uint32_t c0 = 0, chunk = 0; c0 < in.size(); c0 += kMaxProbe, chunk++) {
+            ProbeTask pt{};
+            bool any64 = false;
+            uint64_t need = 0;
+            for (uint32_t j = c0; j < in.size() && pt.fs.n < static_cast<uint32_t>(kMaxProbe); j++) {
+              const uint32_t e = in[j];
+              const uint32_t from = p == 0 ? pl.src[e] : pl.dst[e];
+              FilterRef r = filter_ref(i, p, e, v);
+              r.sel = count_ptr(i, cur[i][from], from);
+              r.rows = pr.tables[from].n_rows;
+              any64 = any64 || r.key64;
+              need += r.cap_words;
+              pt.fs.f[pt.fs.n++] = r;
+            }
+            const bool last = c0 + kMaxProbe >= in.size();
+            pt.n_rows = pr.tables[v].n_rows;
+            pt.bitmap = pr.d_bitmaps[v];
+            pt.count = last ? count_ptr(i, p + 1, v) : nullptr;
+            pt.input_all = 0;
+            const uint32_t U = any64 ? 4 : 8;
+            const uint64_t n_words = (pt.n_rows + 63) / 64;
+            const Key key{pr.params.block_bits, pr.params.k, any64};
+            LaunchDraft &d = probes[{key, chunk}];
+            d.l.kind = kProbe;
+            d.l.block_bits = pr.params.block_bits;
+            d.l.k = pr.params.k;
+            d.l.any64 = any64;
+            d.add(pt, clamp_u32((n_words + 16ull * U * 4 - 1) / (16ull * U * 4), 1, 1024));
+            d.l.pass = p + 1;
+            d.l.rows += pt.n_rows;
+            d.l.bytes += 2 * n_words * 8;  // bitmap read and written
+            for (uint32_t j = 0; j < pt.fs.n; j++) d.l.bytes += pt.n_rows * (pt.fs.f[j].key64 ? 8 : 4);
+            uint64_t &mx = probe_need[{key, chunk}];
+            mx = std::max(mx, need);
+          }
+          cur[i][v] = p + 1;
+        }
+      }
+      // Chunk 0 of every key first, then chunk 1, ... (a later chunk ANDs
+      // into the bitmap the earlier one wrote).
+      for (uint32_t chunk = 0;; chunk++) {
+        bool any = false;
+        for (auto &kv : probes) {
+          if (kv.first.second != chunk) continue;
+          any = true;
+          LaunchDraft d = std::move(kv.second);
+          const bool any64 = std::get<2>(kv.first.first);
+          const uint64_t room = lds_max > probe_queue_bytes(any64) ? (lds_max - probe_queue_bytes(any64)) / 4 : 0;
+          d.l.lds_words = static_cast<uint32_t>(std::min<uint64_t>(room, probe_need[kv.first]));
+          d.l.n = static_cast<uint32_t>(d.first.size() - 1);
+          bp.drafts.push_back(std::move(d));
+        }
+        if (!any) break;
+      }
+      // Sizes and builds of the filters sent by this level's tables.
+      LaunchDraft size;
+      size.l.kind = kSize;
+      std::map<std::pair<uint32_t, uint32_t>, LaunchDraft> builds;
+      std::map<std::pair<uint32_t, uint32_t>, uint64_t> build_need;
+      for (uint32_t i = 0; i < n_problems; i++) {
+        const Plan &pl = bp.plans[i];
+        const pt_problem &pr = probs[i];
+        for (uint32_t v = 0; v < pl.n_t; v++) {
+          if (lvl[p][i][v] != L) continue;
+          std::vector<uint32_t> out;
+          for (uint32_t e = 0; e < pl.n_e; e++)
+            if ((p == 0 ? pl.src[e] : pl.dst[e]) == v) out.push_back(e);
+          if (out.empty()) continue;
+          const uint64_t n_rows = pr.tables[v].n_rows;
+          const uint64_t *cnt = count_ptr(i, cur[i][v], v);
+          for (uint32_t c0 = 0; c0 < out.size(); c0 += kMaxProbe) {
+            BuildTask bt{};
+            uint64_t need = 0;
+            for (uint32_t j = c0; j < out.size() && bt.fs.n < static_cast<uint32_t>(kMaxProbe); j++) {
+              const FilterRef r = filter_ref(i, p, out[j], v);
+              SizeTask st{};
+              st.f = r;
+              st.count = cnt;
+              st.n_rows = n_rows;
+              st.block_bits = pr.params.block_bits;
+              st.bits_per_key = pr.params.bits_per_key;
+              size.add(st, clamp_u32((r.cap_words + kBatchThreads * 8 - 1) / (kBatchThreads * 8), 1, 256));
+              need += r.cap_words;
+              bt.fs.f[bt.fs.n++] = r;
+            }
+            bt.n_rows = n_rows;
+            bt.bitmap = n_rows ? pr.d_bitmaps[v] : nullptr;
+            bt.seg_words = 16;
+            const uint64_t n_words = (n_rows + 63) / 64;
+            const std::pair<uint32_t, uint32_t> key{pr.params.block_bits, pr.params.k};
+            LaunchDraft &d = builds[key];
+            d.l.kind = kBuild;
+            d.l.block_bits = pr.params.block_bits;
+            d.l.k = pr.params.k;
+            d.add(bt, clamp_u32((n_words + 16 * 16 * 4 - 1) / (16 * 16 * 4), 1, 64));
+            uint64_t &mx = build_need[key];
+            mx = std::max(mx, need);
+          }
+        }
+      }
+      if (size.first.size() > 1) {
+        size.l.n = static_cast<uint32_t>(size.first.size() - 1);
+        bp.drafts.push_back(std::move(size));
+      }
+      for (auto &kv : builds) {
+        LaunchDraft d = std::move(kv.second);
+        d.l.lds_words = static_cast<uint32_t>(std::min<uint64_t>(build_lds_words(), build_need[kv.first]));
+        d.l.n = static_cast<uint32_t>(d.first.size() - 1);
+        bp.drafts.push_back(std::move(d));
+      }
+    }
+  }
+  // 4. Final counts to the callers' arrays.
+  {
+    LaunchDraft d;
+    d.l.kind = kCopy;
+    for (uint32_t i = 0; i < n_problems; i++) {
+      if (!probs[i].d_counts) continue;
+      for (uint32_t t = 0; t < bp.plans[i].n_t; t++) {
+        CopyPair cp{count_ptr(i, cur[i][t], t), probs[i].d_counts + t};
+        const char *b = reinterpret_cast<const char *>(&cp);
+        d.tasks.insert(d.tasks.end(), b, b + sizeof(cp));
+      }
+    }
+    d.l.n = static_cast<uint32_t>(d.tasks.size() / sizeof(CopyPair));
+    bp.drafts.push_back(std::move(d));
+  }
+  // Task tables after the data.
+  off = bp.data_end;
+  for (LaunchDraft &d : bp.drafts) {
+    d.l.tasks_off = off;
+    off = align256(off + d.tasks.size());
+    d.l.first_off = off;
+    off = align256(off + d.first.size() * 4);
+    d.l.grid = d.first.back();
+  }
+  bp.total = off;
+  return PT_OK;
+}
+
+}  // namespace
+
+struct pt_batch {
+  int device = 0;
+  char *ws = nullptr;
+  std::vector<BatchLaunch> launches;
+  uint64_t off_counts = 0, n_counts = 0, rows_probed = 0;
+  hipStream_t capture = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+// timed: bracket the probe launches with profiling events (eager runs).
+static pt_status enqueue_batch(const pt_batch &b, hipStream_t s, bool timed) {
+  for (size_t li = 0; li < b.launches.size(); li++) {
+    const BatchLaunch &l = b.launches[li];
+    Timed tm(timed && l.kind == kProbe ? "batch probe" : nullptr, static_cast<uint32_t>(li), l.pass, l.rows,
+             l.bytes, s);
+    const char *tasks = b.ws + l.tasks_off;
+    const uint32_t *first = reinterpret_cast<const uint32_t *>(b.ws + l.first_off);
+    hipError_t e = hipSuccess;
+    switch (l.kind) {
+      case kZero:
+        e = launch_zero_u64(reinterpret_cast<uint64_t *>(b.ws + b.off_counts), b.n_counts, s);
+        break;
+      case kLocal:
+        e = launch_local_batch(reinterpret_cast<const LocalTask *>(tasks), first, l.n, l.grid, s);
+        break;
+      case kSize:
+        e = launch_size_batch(reinterpret_cast<const SizeTask *>(tasks), first, l.n, l.grid, s);
+        break;
+      case kBuild:
+        e = launch_build_batch(l.block_bits, l.k, reinterpret_cast<const BuildTask *>(tasks), first, l.n,
+                               l.grid, l.lds_words, s);
+        break;
+      case kProbe:
+        e = launch_probe_batch(l.block_bits, l.k, l.any64, reinterpret_cast<const ProbeTask *>(tasks), first,
+                               l.n, l.grid, l.lds_words, s);
+        break;
+      case kCopy:
+        e = launch_copy_pairs(reinterpret_cast<const CopyPair *>(tasks), l.n, s);
+        break;
+    }
+    pt_status st = check_hip(e, "batch launch");
+    if (st != PT_OK) return st;
+  }
+  return PT_OK;
+}
+
+extern "C" {
+
+pt_status pt_batch_workspace_size(uint32_t n_problems, const pt_problem *problems, size_t *bytes) {
+  if (!bytes) return fail(PT_EINVAL, "bytes is NULL");
+  BatchPlan bp;
+  pt_status st = plan_batch(n_problems, problems, nullptr, bp);
+  if (st != PT_OK) return st;
+  *bytes = bp.total;
+  return PT_OK;
+}
+
+pt_status pt_batch_prepare(uint32_t n_problems, const pt_problem *problems, void *d_ws, size_t ws_bytes,
+                           pt_batch **out) {
+  if (!out) return fail(PT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d_ws) return fail(PT_EINVAL, "d_ws is NULL");
+  if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0) return fail(PT_EINVAL, "d_ws is not 256-byte aligned");
+  BatchPlan bp;
+  pt_status st = plan_batch(n_problems, problems, static_cast<char *>(d_ws), bp);
+  if (st != PT_OK) return st;
+  if (ws_bytes < bp.total)
+    return fail(PT_ENOMEM, "workspace %zu < %llu bytes", ws_bytes, (unsigned long long)bp.total);
+  // Raise the LDS limits now: the capture must not change kernel attributes.
+  for (const LaunchDraft &d : bp.drafts) {
+    if (d.l.kind != kBuild && d.l.kind != kProbe) continue;
+    st = check_hip(prepare_batch_kernels(d.l.block_bits, d.l.k, d.l.any64), "batch kernel setup");
+    if (st != PT_OK) return st;
+  }
+  char *ws = static_cast<char *>(d_ws);
+  for (const LaunchDraft &d : bp.drafts) {
+    if (!d.tasks.empty()) {
+      st = check_hip(hipMemcpy(ws + d.l.tasks_off, d.tasks.data(), d.tasks.size(), hipMemcpyHostToDevice),
+                     "task table copy");
+      if (st != PT_OK) return st;
+    }
+    st = check_hip(hipMemcpy(ws + d.l.first_off, d.first.data(), d.first.size() * 4, hipMemcpyHostToDevice),
+                   "task table copy");
+    if (st != PT_OK) return st;
+  }
+  auto *b = new pt_batch();
+  if (hipGetDevice(&b->device) != hipSuccess) b->device = 0;
+  b->ws = ws;
+  b->off_counts = bp.off_counts;
+  b->n_counts = bp.n_counts;
+  b->rows_probed = bp.rows_probed;
+  for (const LaunchDraft &d : bp.drafts) b->launches.push_back(d.l);
+  *out = b;
+  return PT_OK;
+}
+
+pt_status pt_batch_run(pt_batch *b, pt_stream stream, uint32_t flags) {
+  if (!b) return fail(PT_EINVAL, "batch is NULL");
+  if (flags & ~PT_BATCH_EAGER) return fail(PT_EINVAL, "unknown flags 0x%x", flags);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (flags & PT_BATCH_EAGER) return enqueue_batch(*b, s, true);
+  if (!b->exec) {
+    pt_status st = check_hip(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "capture stream");
+    if (st != PT_OK) return st;
+    st = check_hip(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (st != PT_OK) return st;
+    pt_status enq = enqueue_batch(*b, b->capture, false);
+    hipGraph_t g = nullptr;
+    st = check_hip(hipStreamEndCapture(b->capture, &g), "end capture");
+    if (enq != PT_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return enq;
+    }
+    if (st != PT_OK) return st;
+    b->graph = g;
+    st = check_hip(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0), "graph instantiate");
+    if (st != PT_OK) return st;
+  }
+  return check_hip(hipGraphLaunch(b->exec, s), "graph launch");
+}
+
+pt_status pt_batch_info(const pt_batch *b, uint32_t *n_launches, uint64_t *rows_probed) {
+  if (!b) return fail(PT_EINVAL, "batch is NULL");
+  if (n_launches) *n_launches = static_cast<uint32_t>(b->launches.size());
+  if (rows_probed) *rows_probed = b->rows_probed;
+  return PT_OK;
+}
+
+void pt_batch_free(pt_batch *b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  delete b;
+}
+
+pt_status pt_transfer_batch(uint32_t n_problems, const pt_problem *problems, void *d_ws, size_t ws_bytes,
+                            pt_stream stream) {
+  pt_batch *b = nullptr;
+  pt_status st = pt_batch_prepare(n_problems, problems, d_ws, ws_bytes, &b);
+  if (st != PT_OK) return st;
+  st = pt_batch_run(b, stream, PT_BATCH_EAGER);
+  if (st == PT_OK) st = check_hip(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)), "batch wait");
+  pt_batch_free(b);
+  return st;
 }
 
 }  // extern "C"

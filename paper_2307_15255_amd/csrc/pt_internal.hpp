@@ -17,7 +17,7 @@ struct FilterRef {
   uint64_t *nb;       // device: number of blocks in use
   uint64_t cap_words; // capacity of `words`
   uint32_t key64;     // key column is int64
-  uint32_t pad;
+  uint32_t app;       // build: 1 + the appended column holding the keys (0: none)
   // Probe order hint: the builder kept *sel of its `rows` rows (NULL or 0:
   // unknown). Filters with the smallest ratio are tested first.
   const uint64_t *sel;
@@ -51,14 +51,38 @@ struct DeviceInfo {
 
 const DeviceInfo &device_info();
 
+// Survivor keys a probe appends for the builds that follow it (the
+// transformation scans the table once). Region r belongs to wave r of the
+// probe grid and holds, in its first counts[r] slots, the keys of the rows
+// that survived in that wave's word groups (groups r, r + n_regions, ... of
+// group_words words). A region whose survivors exceed region_cap keeps only
+// its count; builds walk that region's bitmap words instead.
+constexpr int kMaxAppend = 4;
+struct AppendSet {
+  uint32_t n_cols = 0;         // 0: nothing appended
+  uint32_t n_regions = 0;
+  uint32_t region_cap = 0;     // entries per region and column
+  uint32_t group_words = 0;
+  uint32_t *counts = nullptr;  // [n_regions]
+  const void *src[kMaxAppend] = {};
+  void *dst[kMaxAppend] = {};  // [n_regions * region_cap] keys of src's width
+  uint32_t key64[kMaxAppend] = {};
+};
+// Upper bound of a probe grid's waves (regions of an AppendSet).
+constexpr uint32_t kMaxRegions = 65536;
+
 // Launchers (pt_kernels.hip). Each returns hipSuccess or the launch error.
 hipError_t launch_zero_u64(uint64_t *p, uint64_t n, hipStream_t s);
 hipError_t launch_local_filter(const PredSet &preds, uint64_t n_rows, uint64_t *bitmap,
                                uint64_t *count, hipStream_t s);
 hipError_t launch_fill_all(uint64_t *bitmap, uint64_t n_rows, uint64_t *count, hipStream_t s);
 // input_all: every row starts selected (the bitmap is not read, only written).
+// app (optional, in/out): columns to append (n_cols, src, dst, key64,
+// counts) and the capacity of each dst in entries (capacity); the launch
+// fills in its region geometry, or sets n_cols = 0 when it appends nothing.
 hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,
-                        uint64_t *bitmap, uint64_t *count, bool input_all, hipStream_t s);
+                        uint64_t *bitmap, uint64_t *count, bool input_all, AppendSet *app,
+                        uint64_t capacity, hipStream_t s);
 constexpr uint32_t kTileWords = 16384;   // 64 KB of filter per partitioned-build tile
 constexpr uint32_t kMaxBuckets = 16384;  // (filter, tile) buckets of one partitioned build
 
@@ -73,15 +97,17 @@ struct BuildScratch {
   uint32_t hist_groups = 0;
   uint64_t *totals = nullptr;
   uint64_t *starts = nullptr;
-  uint64_t *entries = nullptr;
+  uint32_t *entries = nullptr;
   uint64_t entries_cap = 0;
 };
 
 // Sizes filters from *count (n_rows when count is NULL) and builds them
-// from the selected rows (bitmap NULL: all rows).
+// from the selected rows (bitmap NULL: all rows). With app (the AppendSet
+// of the probe that produced the bitmap, every filter's `app` set), the
+// keys are read from the appended columns.
 hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, const FilterSet &fs,
                         uint64_t n_rows, const uint64_t *bitmap, const uint64_t *count,
-                        const BuildScratch *scratch, hipStream_t s);
+                        const BuildScratch *scratch, const AppendSet *app, hipStream_t s);
 // Words of LDS one build workgroup uses for its private filter copies.
 uint64_t build_lds_words();
 hipError_t launch_copy_counts(const uint64_t *src, const uint32_t *slot, uint32_t n,
@@ -89,5 +115,74 @@ hipError_t launch_copy_counts(const uint64_t *src, const uint32_t *slot, uint32_
 hipError_t launch_compact(const uint64_t *bitmap, uint64_t n_rows, uint32_t *idx, uint64_t *count,
                           uint64_t *partials, hipStream_t s);
 uint64_t compact_partials(uint64_t n_rows);
+
+// ------------------------------------------------------------ batched steps
+//
+// A batched launch runs the same step for many tables of many problems. Its
+// tasks live in device memory; task i owns workgroups [first[i], first[i+1])
+// of the launch (first has n + 1 entries, first[n] = the grid size).
+
+// Local predicates of one table (no predicates: every row).
+struct LocalTask {
+  PredSet ps;
+  uint64_t n_rows;
+  uint64_t *bitmap;
+  uint64_t *count;
+  uint32_t seg_words;
+  uint32_t pad;
+};
+
+// Size one filter from its builder's count and zero its blocks.
+struct SizeTask {
+  FilterRef f;
+  const uint64_t *count;
+  uint64_t n_rows;
+  uint32_t block_bits;
+  uint32_t bits_per_key;
+};
+
+// Build up to kMaxProbe filters of one table from its selected rows.
+struct BuildTask {
+  FilterSet fs;
+  uint64_t n_rows;
+  const uint64_t *bitmap;
+  uint32_t seg_words;
+  uint32_t pad;
+};
+
+// Probe up to kMaxProbe filters on one table.
+struct ProbeTask {
+  FilterSet fs;
+  uint64_t n_rows;
+  uint64_t *bitmap;
+  uint64_t *count;
+  uint32_t input_all;
+  uint32_t pad;
+};
+
+struct CopyPair {
+  const uint64_t *src;
+  uint64_t *dst;
+};
+
+constexpr int kBatchThreads = 1024;  // every batched kernel: sixteen waves per workgroup
+
+hipError_t launch_local_batch(const LocalTask *tasks, const uint32_t *first, uint32_t n, uint32_t grid,
+                              hipStream_t s);
+hipError_t launch_size_batch(const SizeTask *tasks, const uint32_t *first, uint32_t n, uint32_t grid,
+                             hipStream_t s);
+// lds_words: LDS words per workgroup for private filter copies (a task whose
+// filters need more inserts with global atomics).
+hipError_t launch_build_batch(uint32_t block_bits, uint32_t k, const BuildTask *tasks, const uint32_t *first,
+                              uint32_t n, uint32_t grid, uint32_t lds_words, hipStream_t s);
+// lds_filter_words: LDS words per workgroup for staged filters.
+hipError_t launch_probe_batch(uint32_t block_bits, uint32_t k, bool any64, const ProbeTask *tasks,
+                              const uint32_t *first, uint32_t n, uint32_t grid, uint32_t lds_filter_words,
+                              hipStream_t s);
+hipError_t launch_copy_pairs(const CopyPair *pairs, uint32_t n, hipStream_t s);
+// Bytes of LDS a probe workgroup needs besides its staged filters.
+uint64_t probe_queue_bytes(bool any64);
+// Kernels whose LDS limit must be raised before a batch is captured.
+hipError_t prepare_batch_kernels(uint32_t block_bits, uint32_t k, bool any64);
 
 }  // namespace pt

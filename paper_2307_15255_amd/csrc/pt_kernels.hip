@@ -27,13 +27,40 @@ __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1)
 // compiler cannot tell on its own that threadIdx.x / 64 is the same for
 // every lane, and would otherwise keep loop counters derived from it in
 // vector registers and turn every uniform branch into an exec-mask branch.
-__device__ __forceinline__ uint64_t global_wave() {
+//
+// A batched launch runs many tasks in one grid: each task owns a range of
+// its workgroups, and sees them as a grid of its own (VGrid: this
+// workgroup's index in the task, and the task's workgroup count).
+struct VGrid {
+  uint32_t block;
+  uint32_t blocks;
+};
+
+__device__ __forceinline__ VGrid whole_grid() { return VGrid{blockIdx.x, gridDim.x}; }
+
+__device__ __forceinline__ uint64_t global_wave(const VGrid &g) {
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  return static_cast<uint64_t>(blockIdx.x) * (blockDim.x / kWave) + w;
+  return static_cast<uint64_t>(g.block) * (blockDim.x / kWave) + w;
 }
 
-__device__ __forceinline__ uint64_t wave_count() {
-  return static_cast<uint64_t>(gridDim.x) * blockDim.x / kWave;
+__device__ __forceinline__ uint64_t wave_count(const VGrid &g) {
+  return static_cast<uint64_t>(g.blocks) * blockDim.x / kWave;
+}
+
+
+// The task of this workgroup: first[t] <= blockIdx.x < first[t + 1]
+// (binary search over the n + 1 prefix entries; uniform).
+__device__ __forceinline__ uint32_t task_of(const uint32_t *first, uint32_t n, VGrid &g) {
+  uint32_t lo = 0, hi = n;  // first[lo] <= blockIdx.x < first[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (first[mid] <= blockIdx.x) lo = mid;
+    else hi = mid;
+  }
+  const uint32_t a = __builtin_amdgcn_readfirstlane(first[lo]);
+  const uint32_t b = __builtin_amdgcn_readfirstlane(first[lo + 1]);
+  g = VGrid{blockIdx.x - a, b - a};
+  return __builtin_amdgcn_readfirstlane(lo);
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -184,9 +211,8 @@ __device__ __forceinline__ bool pred_holds(uint32_t op, int64_t v, int64_t lo, i
   }
 }
 
-__global__ void __launch_bounds__(kWideThreads)
-    k_local(PredSet ps, uint64_t n_rows, uint64_t *__restrict__ bitmap,
-            unsigned long long *count, uint32_t seg_words) {
+__device__ __forceinline__ void local_body(const PredSet &ps, uint64_t n_rows, uint64_t *__restrict__ bitmap,
+                                           unsigned long long *count, uint32_t seg_words, const VGrid &vg) {
   constexpr int T = 8;
   __shared__ unsigned long long s_cnt;
   if (threadIdx.x == 0) s_cnt = 0;
@@ -194,7 +220,7 @@ __global__ void __launch_bounds__(kWideThreads)
   const uint32_t lane = lane_id();
   const uint64_t n_words = (n_rows + 63) / 64;
   uint64_t cnt = 0;
-  for (uint64_t seg = global_wave(); seg * seg_words < n_words; seg += wave_count()) {
+  for (uint64_t seg = global_wave(vg); seg * seg_words < n_words; seg += wave_count(vg)) {
     const uint64_t w_base = seg * seg_words;
     const uint32_t n_j = static_cast<uint32_t>(n_words - w_base < seg_words ? n_words - w_base : seg_words);
     uint64_t mine = 0;
@@ -230,6 +256,12 @@ __global__ void __launch_bounds__(kWideThreads)
     cnt += __popcll(mine);
   }
   block_count_add(static_cast<int64_t>(wave_sum(cnt)), &s_cnt, count);
+}
+
+__global__ void __launch_bounds__(kWideThreads)
+    k_local(PredSet ps, uint64_t n_rows, uint64_t *__restrict__ bitmap,
+            unsigned long long *count, uint32_t seg_words) {
+  local_body(ps, n_rows, bitmap, count, seg_words, whole_grid());
 }
 
 // ------------------------------------------------------------------ probe
@@ -272,31 +304,57 @@ constexpr int probe_group_words() {
 }
 
 // 32-bit words of one wave's LDS slice: compacted survivors (word-and-lane
-// tag, remaining keys) plus one 64-bit failure mask per word of the group.
+// tag, the keys of every slot) plus one 64-bit failure mask per word of the
+// group.
 template <bool ANY64>
 constexpr int probe_slice_words() {
-  return kWave * (1 + (kMaxProbe - 1) * (ANY64 ? 2 : 1)) + 2 * probe_group_words<ANY64>();
+  return kWave * (1 + kMaxProbe * (ANY64 ? 2 : 1)) + 2 * probe_group_words<ANY64>();
 }
 
-template <int B, int K, bool ANY64, bool STAGED>
+// Stores the key of appended column c for a surviving row at region slot
+// pos: from the probe's registers (klo/khi of slot app_slot[c]) or, for a
+// column the probe did not read, from the table.
+template <bool ANY64>
+__device__ __forceinline__ void append_key(const AppendSet &app, int c, int slot, const uint32_t (&klo)[kMaxProbe],
+                                           const uint32_t (&khi)[kMaxProbe], uint64_t row, uint64_t at) {
+  uint32_t lo = 0, hi = 0;
+  bool have = false;
+#pragma unroll
+  for (int q = 0; q < kMaxProbe; q++)
+    if (slot == q) {
+      lo = klo[q];
+      hi = ANY64 ? khi[q] : 0;
+      have = true;
+    }
+  if (app.key64[c]) {
+    static_cast<uint64_t *>(app.dst[c])[at] =
+        have ? ((static_cast<uint64_t>(hi) << 32) | lo) : static_cast<const uint64_t *>(app.src[c])[row];
+  } else {
+    static_cast<uint32_t *>(app.dst[c])[at] = have ? lo : static_cast<const uint32_t *>(app.src[c])[row];
+  }
+}
+
+template <int B, int K, bool ANY64, bool STAGED, bool APPEND>
 __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe],
                                               const uint32_t (&lds_off)[kMaxProbe], uint32_t n_f,
                                               uint32_t k, uint64_t n_rows, uint64_t *bitmap,
                                               uint32_t input_all, const uint32_t *lds_filters,
-                                              uint32_t *slice) {
+                                              uint32_t *slice, const AppendSet &app,
+                                              const int (&app_slot)[kMaxAppend], const VGrid &vg) {
   constexpr int U = probe_group_words<ANY64>();
-  constexpr int kRest = kMaxProbe - 1;
   uint32_t *q_tag = slice;                                          // [kWave]
-  uint32_t *q_lo = slice + kWave;                                   // [kRest][kWave]
-  uint32_t *q_hi = slice + kWave * (1 + kRest);                     // [kRest][kWave] (int64)
+  uint32_t *q_lo = slice + kWave;                                   // [kMaxProbe][kWave]
+  uint32_t *q_hi = slice + kWave * (1 + kMaxProbe);                 // [kMaxProbe][kWave] (int64)
   unsigned long long *fail_mask = reinterpret_cast<unsigned long long *>(
-      slice + kWave * (1 + kRest * (ANY64 ? 2 : 1)));               // [U]
+      slice + kWave * (1 + kMaxProbe * (ANY64 ? 2 : 1)));           // [U]
   const uint32_t lane = lane_id();
   const uint64_t n_words = (n_rows + 63) / 64;
-  const uint64_t stride = wave_count() * U;
+  const uint64_t stride = wave_count(vg) * U;
   int64_t cnt = 0;
+  uint32_t app_n = 0;  // survivors of this wave's region so far
+  const uint64_t app_base = global_wave(vg) * static_cast<uint64_t>(app.region_cap);
 
-  for (uint64_t w0 = global_wave() * U; w0 < n_words; w0 += stride) {
+  for (uint64_t w0 = global_wave(vg) * U; w0 < n_words; w0 += stride) {
     // The group's U words: lane u loads word w0 + u (one load), then every
     // lane reads them back as scalars.
     uint64_t mine = 0;
@@ -363,6 +421,7 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe],
       total += __popcll(m0[u]);
     }
 
+    bool appended = false;  // the survivors' keys are stored
     if (n_f > 1 && total > kWave) {
       // Many survivors: test the remaining filters on the words themselves.
 #pragma unroll
@@ -379,8 +438,9 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe],
           }
         }
       }
-    } else if (n_f > 1 && total > 0) {
-      // Few survivors: compact them into the LDS slice, one lane each.
+    } else if (total > 0 && total <= kWave && (n_f > 1 || (APPEND && app_n < app.region_cap))) {
+      // Few survivors: compact them into the LDS slice, one lane each, and
+      // test the remaining filters with every lane busy.
       uint32_t pos0 = 0;
 #pragma unroll
       for (int u = 0; u < U; u++) {
@@ -389,10 +449,10 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe],
           const uint32_t pos = pos0 + __popcll(m0[u] & ((1ull << lane) - 1));
           q_tag[pos] = (static_cast<uint32_t>(u) << 6) | lane;
 #pragma unroll
-          for (int s = 1; s < kMaxProbe; s++) {
+          for (int s = APPEND ? 0 : 1; s < kMaxProbe; s++) {
             if (s < static_cast<int>(n_f)) {
-              q_lo[(s - 1) * kWave + pos] = lo[s][u];
-              if (ANY64) q_hi[(s - 1) * kWave + pos] = hi[ANY64 ? s : 0][u];
+              q_lo[s * kWave + pos] = lo[s][u];
+              if (ANY64) q_hi[s * kWave + pos] = hi[ANY64 ? s : 0][u];
             }
           }
         }
@@ -404,24 +464,63 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe],
       const bool act = lane < total;
       const uint32_t idx = act ? lane : 0;
       bool ok = act;
+      uint32_t klo[kMaxProbe] = {}, khi[kMaxProbe] = {};
 #pragma unroll
-      for (int s = 1; s < kMaxProbe; s++) {
+      for (int s = APPEND ? 0 : 1; s < kMaxProbe; s++) {
         if (s < static_cast<int>(n_f)) {
-          const uint32_t klo = q_lo[(s - 1) * kWave + idx];
-          const uint32_t khi = ANY64 ? q_hi[(s - 1) * kWave + idx] : 0;
-          uint32_t h1, h2;
-          hash_parts(klo, khi, ANY64 && sl[s].key64, h1, h2);
-          ok = ok && slot_has<B, K, STAGED>(sl[s], lds_filters + lds_off[s], h1, h2, k);
+          klo[s] = q_lo[s * kWave + idx];
+          khi[s] = ANY64 ? q_hi[s * kWave + idx] : 0;
+          if (s > 0) {
+            uint32_t h1, h2;
+            hash_parts(klo[s], khi[s], ANY64 && sl[s].key64, h1, h2);
+            ok = ok && slot_has<B, K, STAGED>(sl[s], lds_filters + lds_off[s], h1, h2, k);
+          }
         }
       }
-      if (act && !ok) {
-        const uint32_t tag = q_tag[idx];
-        atomicOr(&fail_mask[tag >> 6], 1ull << (tag & 63));
+      const uint32_t tag = q_tag[idx];
+      if (act && !ok) atomicOr(&fail_mask[tag >> 6], 1ull << (tag & 63));
+      if (APPEND) {
+        // The final survivors append their keys: one store per column.
+        const uint64_t fin = __ballot(ok);
+        const uint32_t pos = app_n + static_cast<uint32_t>(__popcll(fin & ((1ull << lane) - 1)));
+        if (ok && pos < app.region_cap) {
+          const uint64_t row = base_row + (tag >> 6) * 64 + (tag & 63);
+#pragma unroll
+          for (int c = 0; c < kMaxAppend; c++)
+            if (c < static_cast<int>(app.n_cols)) append_key<ANY64>(app, c, app_slot[c], klo, khi, row, app_base + pos);
+        }
+        app_n += static_cast<uint32_t>(__popcll(fin));
+        appended = true;
       }
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int u = 0; u < U; u++) m0[u] &= ~uniform64(fail_mask[u]);
       __builtin_amdgcn_wave_barrier();
+    }
+
+    if (APPEND && !appended && total > 0) {
+      // Many survivors: append word by word while the region has room (a
+      // full region is walked by the builds; only its count matters).
+      const uint64_t below = (1ull << lane) - 1;
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        if (app_n < app.region_cap) {
+          const uint32_t pos = app_n + static_cast<uint32_t>(__popcll(m0[u] & below));
+          if (((m0[u] >> lane) & 1) && pos < app.region_cap) {
+            uint32_t klo[kMaxProbe], khi[kMaxProbe];
+#pragma unroll
+            for (int q = 0; q < kMaxProbe; q++) {
+              klo[q] = lo[q][u];
+              khi[q] = ANY64 ? hi[ANY64 ? q : 0][u] : 0;
+            }
+            const uint64_t row = base_row + static_cast<uint64_t>(u) * 64 + lane;
+#pragma unroll
+            for (int c = 0; c < kMaxAppend; c++)
+              if (c < static_cast<int>(app.n_cols)) append_key<ANY64>(app, c, app_slot[c], klo, khi, row, app_base + pos);
+          }
+        }
+        app_n += static_cast<uint32_t>(__popcll(m0[u]));
+      }
     }
 
 #pragma unroll
@@ -431,13 +530,15 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe],
       cnt += __popcll(m0[u]);
     }
   }
+  if (APPEND && lane == 0) app.counts[global_wave(vg)] = app_n;
   return cnt;
 }
 
-template <int B, int K, bool ANY64>
-__global__ void __launch_bounds__(kProbeThreads)
-    k_probe(FilterSet fs, uint32_t k, uint64_t n_rows, uint64_t *__restrict__ bitmap,
-            unsigned long long *count, uint32_t lds_filter_words, uint32_t input_all) {
+template <int B, int K, bool ANY64, bool APPEND>
+__device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint64_t n_rows,
+                                           uint64_t *__restrict__ bitmap, unsigned long long *count,
+                                           uint32_t lds_filter_words, uint32_t input_all,
+                                           const AppendSet &app, const VGrid &vg) {
   extern __shared__ __align__(16) uint32_t lds[];
   constexpr int W = BlockShape<B>::kWords;
   constexpr int kSliceWords = probe_slice_words<ANY64>();
@@ -521,16 +622,51 @@ __global__ void __launch_bounds__(kProbeThreads)
     sl[j].key64 = f.key64;
     off[j] = __builtin_amdgcn_readfirstlane(s_off[jj]);
   }
+  // Appended column c comes from slot app_slot[c]'s registers (-1: loaded).
+  int app_slot[kMaxAppend];
+#pragma unroll
+  for (int c = 0; c < kMaxAppend; c++) {
+    app_slot[c] = -1;
+#pragma unroll
+    for (int j = kMaxProbe - 1; j >= 0; j--)
+      if (j < static_cast<int>(n_f) && c < static_cast<int>(app.n_cols) && sl[j].keys == app.src[c] &&
+          sl[j].key64 == app.key64[c])
+        app_slot[c] = j;
+  }
   // The per-wave slices follow the filters; lds_filter_words is even, so
   // each slice's 64-bit failure masks stay 8-byte aligned.
   uint32_t *slice =
       lds + lds_filter_words + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) * kSliceWords;
   int64_t cnt;
   if (staged)
-    cnt = probe_loop<B, K, ANY64, true>(sl, off, n_f, k, n_rows, bitmap, input_all, lds, slice);
+    cnt = probe_loop<B, K, ANY64, true, APPEND>(sl, off, n_f, k, n_rows, bitmap, input_all, lds, slice,
+                                                app, app_slot, vg);
   else
-    cnt = probe_loop<B, K, ANY64, false>(sl, off, n_f, k, n_rows, bitmap, input_all, lds, slice);
+    cnt = probe_loop<B, K, ANY64, false, APPEND>(sl, off, n_f, k, n_rows, bitmap, input_all, lds, slice,
+                                                 app, app_slot, vg);
   block_count_add(cnt, &s_cnt, count);
+}
+
+template <int B, int K, bool ANY64, bool APPEND>
+__global__ void __launch_bounds__(kProbeThreads)
+    k_probe(FilterSet fs, uint32_t k, uint64_t n_rows, uint64_t *__restrict__ bitmap,
+            unsigned long long *count, uint32_t lds_filter_words, uint32_t input_all, AppendSet app) {
+  probe_body<B, K, ANY64, APPEND>(fs, k, n_rows, bitmap, count, lds_filter_words, input_all, app,
+                                  whole_grid());
+}
+
+// Many probes in one launch (one task each, see VGrid).
+template <int B, int K, bool ANY64>
+__global__ void __launch_bounds__(kProbeThreads)
+    k_probe_batch(const ProbeTask *__restrict__ tasks, const uint32_t *__restrict__ first,
+                  uint32_t n_tasks, uint32_t k, uint32_t lds_filter_words) {
+  VGrid vg;
+  const uint32_t t = task_of(first, n_tasks, vg);
+  const ProbeTask &task = tasks[t];
+  const AppendSet none{};
+  probe_body<B, K, ANY64, false>(task.fs, k, task.n_rows, task.bitmap,
+                                 reinterpret_cast<unsigned long long *>(task.count), lds_filter_words,
+                                 task.input_all, none, vg);
 }
 
 // --------------------------------------------------------- size and zero
@@ -625,16 +761,17 @@ __global__ void __launch_bounds__(kThreads)
 // word by word into the filters. Larger filters are built in place with
 // global atomic OR, skipped when a read already shows the bit set.
 
-// Calls f(rows, ok) for the selected rows, spread over the grid's waves,
-// U rows per lane at a time: rows[u] is valid where bit u of ok is set. A
-// batch of U rows lets the caller issue U key loads before it waits.
+// Calls f(rows, ok) for the selected rows of segments seg_first,
+// seg_first + seg_step, ... (seg_words words each), U rows per lane at a
+// time: rows[u] is valid where bit u of ok is set. A batch of U rows lets
+// the caller issue U key loads before it waits.
 template <int U, typename F>
-__device__ __forceinline__ void walk_rows(uint64_t n_rows, const uint64_t *bitmap,
-                                          uint32_t seg_words, F &&f) {
+__device__ __forceinline__ void walk_rows(uint64_t seg_first, uint64_t seg_step, uint32_t seg_words,
+                                          uint64_t n_rows, const uint64_t *bitmap, F &&f) {
   const uint32_t lane = lane_id();
   const uint64_t n_words = (n_rows + 63) / 64;
   // lane l holds word l of a segment of seg_words (1..64) words
-  for (uint64_t seg = global_wave(); seg * seg_words < n_words; seg += wave_count()) {
+  for (uint64_t seg = seg_first; seg * seg_words < n_words; seg += seg_step) {
     const uint64_t w = seg * seg_words + lane;
     uint64_t word = lane < seg_words ? tail_mask(w, n_words, n_rows) : 0;
     if (bitmap && lane < seg_words && w < n_words) word &= bitmap[w];
@@ -704,13 +841,48 @@ __device__ __forceinline__ void hash_rows(const FilterRef &f, const uint64_t (&r
 
 constexpr int kWalkBatch = 8;
 
+// Filter hashes of up to U appended keys (those set in ok): slots
+// base + idx[u] of appended column c.
+template <int U>
+__device__ __forceinline__ void hash_appended(const AppendSet &app, uint32_t c, uint64_t base,
+                                              const uint32_t (&idx)[U], uint32_t ok, uint32_t (&h1)[U],
+                                              uint32_t (&h2)[U]) {
+  const void *col = app.dst[0];
+  uint32_t key64 = app.key64[0];
+#pragma unroll
+  for (int j = 1; j < kMaxAppend; j++)
+    if (c == static_cast<uint32_t>(j)) {
+      col = app.dst[j];
+      key64 = app.key64[j];
+    }
+  if (key64) {
+    const uint64_t *p = static_cast<const uint64_t *>(col) + base;
+    uint64_t x[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) x[u] = (ok >> u) & 1 ? p[idx[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < U; u++) hash_key(x[u], h1[u], h2[u]);
+  } else {
+    const uint32_t *p = static_cast<const uint32_t *>(col) + base;
+    uint32_t x[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) x[u] = (ok >> u) & 1 ? p[idx[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < U; u++) hash_key32(x[u], h1[u], h2[u]);
+  }
+}
+
 // Calls g(i, h1, h2) for every selected row and every filter i of fs, with
-// the hashes of the row's key in filter i's key column.
+// the hashes of the row's key in filter i's key column. Without appended
+// keys the grid's waves walk the bitmap; with them each wave takes whole
+// regions, reading their appended keys (contiguous) or, for a region that
+// overflowed, walking the bitmap words of the probe groups it covers.
 template <typename G>
-__device__ __forceinline__ void for_each_key(const FilterSet &fs, uint64_t n_rows, const uint64_t *bitmap,
-                                             uint32_t seg_words, G &&g) {
+__device__ __forceinline__ void for_each_key(const FilterSet &fs, const AppendSet &app, uint64_t n_rows,
+                                             const uint64_t *bitmap, uint32_t seg_words, const VGrid &vg,
+                                             G &&g) {
   constexpr int U = kWalkBatch;
-  walk_rows<U>(n_rows, bitmap, seg_words, [&](const uint64_t (&row)[U], uint32_t ok) {
+  auto from_rows = [&](const uint64_t (&row)[U], uint32_t ok) {
 #pragma unroll
     for (int i = 0; i < kMaxFilters; i++) {
       if (i < static_cast<int>(fs.n)) {
@@ -721,7 +893,39 @@ __device__ __forceinline__ void for_each_key(const FilterSet &fs, uint64_t n_row
           if ((ok >> u) & 1) g(i, h1[u], h2[u]);
       }
     }
-  });
+  };
+  if (app.n_cols == 0) {
+    walk_rows<U>(global_wave(vg), wave_count(vg), seg_words, n_rows, bitmap, from_rows);
+    return;
+  }
+  const uint32_t lane = lane_id();
+  for (uint64_t r = global_wave(vg); r < app.n_regions; r += wave_count(vg)) {
+    const uint32_t n = __builtin_amdgcn_readfirstlane(app.counts[r]);
+    if (n > app.region_cap) {
+      walk_rows<U>(r, app.n_regions, app.group_words, n_rows, bitmap, from_rows);
+      continue;
+    }
+    const uint64_t base = r * app.region_cap;
+    for (uint32_t j0 = 0; j0 < n; j0 += U * kWave) {
+      uint32_t idx[U];
+      uint32_t ok = 0;
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        idx[u] = j0 + u * kWave + lane;
+        if (idx[u] < n) ok |= 1u << u;
+      }
+#pragma unroll
+      for (int i = 0; i < kMaxFilters; i++) {
+        if (i < static_cast<int>(fs.n)) {
+          uint32_t h1[U], h2[U];
+          hash_appended<U>(app, fs.f[i].app - 1, base, idx, ok, h1, h2);
+#pragma unroll
+          for (int u = 0; u < U; u++)
+            if ((ok >> u) & 1) g(i, h1[u], h2[u]);
+        }
+      }
+    }
+  }
 }
 
 // Sets the k bits of (h1, h2) in a filter held in LDS.
@@ -744,7 +948,7 @@ __device__ __forceinline__ void insert_lds(uint32_t *filter, uint32_t nb, uint32
 
 template <int B, int K>
 __global__ void __launch_bounds__(kThreads)
-    k_build(FilterSet fs, uint32_t k, uint64_t n_rows, const uint64_t *__restrict__ bitmap,
+    k_build(FilterSet fs, AppendSet app, uint32_t k, uint64_t n_rows, const uint64_t *__restrict__ bitmap,
             uint32_t seg_words) {
   uint32_t nb[kMaxFilters];
 #pragma unroll
@@ -752,7 +956,7 @@ __global__ void __launch_bounds__(kThreads)
     nb[i] = i < static_cast<int>(fs.n)
                 ? clamp_blocks(*fs.f[i].nb, fs.f[i].cap_words / BlockShape<B>::kWords)
                 : 1;
-  for_each_key(fs, n_rows, bitmap, seg_words, [&](int i, uint32_t h1, uint32_t h2) {
+  for_each_key(fs, app, n_rows, bitmap, seg_words, whole_grid(), [&](int i, uint32_t h1, uint32_t h2) {
     insert_bits<B, K>(fs.f[i].words, nb[i], k, h1, h2);
   });
 }
@@ -787,20 +991,20 @@ __device__ __forceinline__ LdsPlan lds_plan(const FilterSet &fs, uint32_t lds_wo
 
 template <int B, int K>
 __global__ void __launch_bounds__(kWideThreads)
-    k_build_lds(FilterSet fs, uint32_t k, uint64_t n_rows, const uint64_t *__restrict__ bitmap,
+    k_build_lds(FilterSet fs, AppendSet app, uint32_t k, uint64_t n_rows, const uint64_t *__restrict__ bitmap,
                 uint32_t seg_words, uint32_t *__restrict__ partials, uint32_t lds_words) {
   extern __shared__ __align__(16) uint32_t lds[];
   const LdsPlan pl = lds_plan<B>(fs, lds_words);
   if (!pl.fits) {
     // Too large for LDS: insert in place with global atomics.
-    for_each_key(fs, n_rows, bitmap, seg_words, [&](int i, uint32_t h1, uint32_t h2) {
+    for_each_key(fs, app, n_rows, bitmap, seg_words, whole_grid(), [&](int i, uint32_t h1, uint32_t h2) {
       insert_bits<B, K>(fs.f[i].words, pl.nb[i], k, h1, h2);
     });
     return;
   }
   for (uint32_t j = threadIdx.x; j < pl.total; j += blockDim.x) lds[j] = 0;
   __syncthreads();
-  for_each_key(fs, n_rows, bitmap, seg_words, [&](int i, uint32_t h1, uint32_t h2) {
+  for_each_key(fs, app, n_rows, bitmap, seg_words, whole_grid(), [&](int i, uint32_t h1, uint32_t h2) {
     insert_lds<B, K>(lds + pl.off[i], pl.nb[i], k, h1, h2);
   });
   __syncthreads();
@@ -870,6 +1074,24 @@ __global__ void __launch_bounds__(kWideThreads)
 //            written exactly once).
 // No step needs a global atomic.
 
+// An entry is 32 bits: the block within its tile above the top 2 log2(B)
+// bits of H2, the only bits of H2 the bit positions use. Tiles hold at most
+// 64 KB, so the block index fits (14 bits for B = 32, 9 for B = 1024).
+template <int B>
+__device__ __forceinline__ uint32_t pack_entry(uint32_t blk_in_tile, uint32_t h2) {
+  constexpr int L2 = 2 * BlockShape<B>::kLog2;
+  return (blk_in_tile << L2) | (h2 >> (32 - L2));
+}
+template <int B>
+__device__ __forceinline__ uint32_t entry_block(uint32_t v) {
+  return v >> (2 * BlockShape<B>::kLog2);
+}
+template <int B>
+__device__ __forceinline__ uint32_t entry_h2(uint32_t v) {
+  constexpr int L2 = 2 * BlockShape<B>::kLog2;
+  return v << (32 - L2);
+}
+
 template <int B>
 __device__ __forceinline__ uint32_t bucket_of(const PartPlan &pl, int f, uint32_t h1, uint32_t &blk) {
   blk = block_of(h1, pl.nb[f]);
@@ -878,7 +1100,7 @@ __device__ __forceinline__ uint32_t bucket_of(const PartPlan &pl, int f, uint32_
 
 template <int B>
 __global__ void __launch_bounds__(kWideThreads)
-    k_part_count(FilterSet fs, uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
+    k_part_count(FilterSet fs, AppendSet app, uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
                  const uint64_t *__restrict__ bitmap, uint32_t seg_words, uint64_t entries_cap,
                  uint32_t *__restrict__ hist) {
   extern __shared__ __align__(16) uint32_t s_hist[];
@@ -887,7 +1109,7 @@ __global__ void __launch_bounds__(kWideThreads)
   const uint32_t buckets = pl.base[kMaxFilters];
   for (uint32_t b = threadIdx.x; b < buckets; b += blockDim.x) s_hist[b] = 0;
   __syncthreads();
-  for_each_key(fs, n_rows, bitmap, seg_words, [&](int i, uint32_t h1, uint32_t h2) {
+  for_each_key(fs, app, n_rows, bitmap, seg_words, whole_grid(), [&](int i, uint32_t h1, uint32_t h2) {
     uint32_t blk;
     atomicAdd(&s_hist[bucket_of<B>(pl, i, h1, blk)], 1u);
   });
@@ -938,16 +1160,16 @@ __global__ void __launch_bounds__(kWideThreads)
 
 template <int B, int K>
 __global__ void __launch_bounds__(kWideThreads)
-    k_part_scatter(FilterSet fs, uint32_t k, uint32_t bits_per_key, const uint64_t *count,
+    k_part_scatter(FilterSet fs, AppendSet app, uint32_t k, uint32_t bits_per_key, const uint64_t *count,
                    uint64_t n_rows, const uint64_t *__restrict__ bitmap, uint32_t seg_words,
                    uint64_t entries_cap, const uint32_t *__restrict__ hist,
-                   const uint64_t *__restrict__ starts, uint64_t *__restrict__ entries) {
+                   const uint64_t *__restrict__ starts, uint32_t *__restrict__ entries) {
   extern __shared__ __align__(16) uint64_t s_cur[];
   const PartPlan pl = part_plan(fs, B, bits_per_key, count, n_rows, entries_cap, false);
   if (!pl.ok) {
     // The plan does not fit: insert in place with global atomics (the size
     // kernel zeroed the filters in this case).
-    for_each_key(fs, n_rows, bitmap, seg_words, [&](int i, uint32_t h1, uint32_t h2) {
+    for_each_key(fs, app, n_rows, bitmap, seg_words, whole_grid(), [&](int i, uint32_t h1, uint32_t h2) {
       insert_bits<B, K>(fs.f[i].words, pl.nb[i], k, h1, h2);
     });
     return;
@@ -957,12 +1179,12 @@ __global__ void __launch_bounds__(kWideThreads)
   // s_cur[b]: the next entry slot of this workgroup in bucket b
   for (uint32_t b = threadIdx.x; b < buckets; b += blockDim.x) s_cur[b] = starts[b] + my[b];
   __syncthreads();
-  for_each_key(fs, n_rows, bitmap, seg_words, [&](int i, uint32_t h1, uint32_t h2) {
+  for_each_key(fs, app, n_rows, bitmap, seg_words, whole_grid(), [&](int i, uint32_t h1, uint32_t h2) {
     uint32_t blk;
     const uint32_t b = bucket_of<B>(pl, i, h1, blk);
     const uint64_t pos = atomicAdd(&s_cur[b], static_cast<uint64_t>(1));
     if (pos < entries_cap)  // always true while *count is the bitmap's popcount
-      entries[pos] = (static_cast<uint64_t>(blk % pl.tile_blocks) << 32) | h2;
+      entries[pos] = pack_entry<B>(blk % pl.tile_blocks, h2);
   });
 }
 
@@ -970,7 +1192,7 @@ template <int B, int K>
 __global__ void __launch_bounds__(kWideThreads)
     k_part_fill(FilterSet fs, uint32_t k, uint32_t bits_per_key, const uint64_t *count,
                 uint64_t n_rows, uint64_t entries_cap, const uint64_t *__restrict__ starts,
-                const uint64_t *__restrict__ entries) {
+                const uint32_t *__restrict__ entries) {
   constexpr int W = BlockShape<B>::kWords;
   extern __shared__ __align__(16) uint32_t tile[];
   const PartPlan pl = part_plan(fs, B, bits_per_key, count, n_rows, entries_cap, false);
@@ -993,10 +1215,10 @@ __global__ void __launch_bounds__(kWideThreads)
     for (uint32_t j = threadIdx.x; j < n_blocks * W; j += blockDim.x) tile[j] = 0;
     __syncthreads();
     for (uint64_t e = starts[b] + threadIdx.x; e < starts[b + 1]; e += blockDim.x) {
-      const uint64_t v = entries[e];
+      const uint32_t v = entries[e];
       // the entry names its block inside the tile; with nb = 1 and h1 = 0,
       // insert_lds sets the key's k bits in the block it is pointed at
-      insert_lds<B, K>(tile + static_cast<uint32_t>(v >> 32) * W, 1, k, 0, static_cast<uint32_t>(v));
+      insert_lds<B, K>(tile + entry_block<B>(v) * W, 1, k, 0, entry_h2<B>(v));
     }
     __syncthreads();
     uint32_t *out = pick(fs, f).words + static_cast<uint64_t>(first) * W;
@@ -1082,6 +1304,79 @@ __global__ void __launch_bounds__(kThreads)
 
 // ------------------------------------------------------------ dispatch
 
+// ---------------------------------------------------------- batched steps
+//
+// The same steps for many tables of many problems at once: each workgroup
+// finds its task (task_of) and runs the step's body on the task's share of
+// the grid.
+
+__global__ void __launch_bounds__(kBatchThreads)
+    k_local_batch(const LocalTask *__restrict__ tasks, const uint32_t *__restrict__ first, uint32_t n) {
+  VGrid vg;
+  const LocalTask &t = tasks[task_of(first, n, vg)];
+  local_body(t.ps, t.n_rows, t.bitmap, reinterpret_cast<unsigned long long *>(t.count), t.seg_words, vg);
+}
+
+__global__ void __launch_bounds__(kBatchThreads)
+    k_size_batch(const SizeTask *__restrict__ tasks, const uint32_t *__restrict__ first, uint32_t n) {
+  VGrid vg;
+  const SizeTask &t = tasks[task_of(first, n, vg)];
+  const uint64_t W = t.block_bits / 32;
+  const uint64_t nb = blocks_needed(t.count ? *t.count : t.n_rows, t.block_bits, t.bits_per_key,
+                                    t.f.cap_words / W);
+  if (vg.block == 0 && threadIdx.x == 0) *t.f.nb = nb;
+  const uint64_t words = nb * W;
+  for (uint64_t i = static_cast<uint64_t>(vg.block) * blockDim.x + threadIdx.x; i < words;
+       i += static_cast<uint64_t>(vg.blocks) * blockDim.x)
+    t.f.words[i] = 0;
+}
+
+// Filters that fit the launch's LDS are built in private copies and merged
+// into the (zeroed) filters: stored when the task has one workgroup, OR-ed
+// with atomics otherwise. Larger ones are built with global atomics.
+template <int B, int K>
+__global__ void __launch_bounds__(kBatchThreads)
+    k_build_batch(const BuildTask *__restrict__ tasks, const uint32_t *__restrict__ first, uint32_t n,
+                  uint32_t k, uint32_t lds_words) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  constexpr int W = BlockShape<B>::kWords;
+  VGrid vg;
+  const BuildTask &t = tasks[task_of(first, n, vg)];
+  const FilterSet &fs = t.fs;
+  const AppendSet none{};
+  const LdsPlan pl = lds_plan<B>(fs, lds_words);
+  if (!pl.fits) {
+    for_each_key(fs, none, t.n_rows, t.bitmap, t.seg_words, vg, [&](int i, uint32_t h1, uint32_t h2) {
+      insert_bits<B, K>(fs.f[i].words, pl.nb[i], k, h1, h2);
+    });
+    return;
+  }
+  for (uint32_t j = threadIdx.x; j < pl.total; j += blockDim.x) lds[j] = 0;
+  __syncthreads();
+  for_each_key(fs, none, t.n_rows, t.bitmap, t.seg_words, vg, [&](int i, uint32_t h1, uint32_t h2) {
+    insert_lds<B, K>(lds + pl.off[i], pl.nb[i], k, h1, h2);
+  });
+  __syncthreads();
+  const bool alone = vg.blocks == 1;
+#pragma unroll
+  for (int i = 0; i < kMaxFilters; i++) {
+    if (i < static_cast<int>(fs.n)) {
+      uint32_t *words = fs.f[i].words;
+      const uint32_t *mine = lds + pl.off[i];
+      for (uint32_t j = threadIdx.x; j < pl.nb[i] * W; j += blockDim.x) {
+        const uint32_t v = mine[j];
+        if (alone) words[j] = v;
+        else if (v) atomicOr(words + j, v);
+      }
+    }
+  }
+}
+
+__global__ void k_copy_pairs(const CopyPair *__restrict__ pairs, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) *pairs[i].dst = *pairs[i].src;
+}
+
 template <typename F>
 hipError_t by_block_bits(uint32_t block_bits, F &&f) {
   switch (block_bits) {
@@ -1156,9 +1451,13 @@ hipError_t launch_local_filter(const PredSet &preds, uint64_t n_rows, uint64_t *
 }
 
 hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,
-                        uint64_t *bitmap, uint64_t *count, bool input_all, hipStream_t s) {
+                        uint64_t *bitmap, uint64_t *count, bool input_all, AppendSet *app,
+                        uint64_t capacity, hipStream_t s) {
   const uint64_t n_words = (n_rows + 63) / 64;
-  if (n_words == 0 || fs.n == 0) return hipSuccess;
+  if (n_words == 0 || fs.n == 0) {
+    if (app) app->n_cols = 0;
+    return hipSuccess;
+  }
   bool any64 = false;
   uint64_t want_words = 0;
   for (uint32_t i = 0; i < fs.n; i++) {
@@ -1178,6 +1477,23 @@ hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, ui
   const uint32_t grid = grid_for((n_words + U - 1) / U, kProbeThreads, per_cu);
   const uint32_t filter_words = static_cast<uint32_t>(filter_bytes / 8) * 2;  // keep slices 8-byte aligned
   auto *cnt = reinterpret_cast<unsigned long long *>(count);
+  // Region geometry of the appended keys: one region per wave of the grid,
+  // capacity / regions slots each (at most the rows a wave can see).
+  AppendSet a{};
+  if (app && app->n_cols > 0 && app->n_cols <= static_cast<uint32_t>(kMaxAppend) && app->counts) {
+    const uint64_t regions = static_cast<uint64_t>(grid) * kProbeWaves;
+    const uint64_t groups = (n_words + U - 1) / U;
+    const uint64_t most = (groups + regions - 1) / regions * U * 64;
+    uint64_t cap = capacity / regions;
+    if (cap > most) cap = most;
+    if (regions <= kMaxRegions && cap >= 64) {
+      a = *app;
+      a.n_regions = static_cast<uint32_t>(regions);
+      a.region_cap = static_cast<uint32_t>(cap);
+      a.group_words = static_cast<uint32_t>(U);
+    }
+  }
+  if (app) *app = a;
   const uint32_t all = input_all ? 1u : 0u;
   return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
     constexpr int B = decltype(bb)::value;
@@ -1185,11 +1501,15 @@ hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, ui
       hipError_t e = allow_lds(reinterpret_cast<const void *>(kern), lds_bytes);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(kern, dim3(grid), dim3(kProbeThreads), lds_bytes, s, fs, k, n_rows,
-                         bitmap, cnt, filter_words, all);
+                         bitmap, cnt, filter_words, all, a);
       return hipGetLastError();
     };
-    if (k == 3) return any64 ? launch(k_probe<B, 3, true>) : launch(k_probe<B, 3, false>);
-    return any64 ? launch(k_probe<B, 0, true>) : launch(k_probe<B, 0, false>);
+    if (a.n_cols) {
+      if (k == 3) return any64 ? launch(k_probe<B, 3, true, true>) : launch(k_probe<B, 3, false, true>);
+      return any64 ? launch(k_probe<B, 0, true, true>) : launch(k_probe<B, 0, false, true>);
+    }
+    if (k == 3) return any64 ? launch(k_probe<B, 3, true, false>) : launch(k_probe<B, 3, false, false>);
+    return any64 ? launch(k_probe<B, 0, true, false>) : launch(k_probe<B, 0, false, false>);
   });
 }
 
@@ -1200,8 +1520,15 @@ uint64_t build_lds_words() {
 
 hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, const FilterSet &fs,
                         uint64_t n_rows, const uint64_t *bitmap, const uint64_t *count,
-                        const BuildScratch *scratch, hipStream_t s) {
+                        const BuildScratch *scratch, const AppendSet *app, hipStream_t s) {
   if (fs.n == 0) return hipSuccess;
+  // Appended keys are used only when every filter names one of them.
+  AppendSet a{};
+  if (app && app->n_cols > 0 && app->n_cols <= static_cast<uint32_t>(kMaxAppend)) {
+    bool all = true;
+    for (uint32_t i = 0; i < fs.n; i++) all = all && fs.f[i].app >= 1 && fs.f[i].app <= app->n_cols;
+    if (all) a = *app;
+  }
   const uint64_t n_words = (n_rows + 63) / 64;
   const uint32_t seg_words = segment_words(n_words ? n_words : 1);
   const uint64_t lds_words = build_lds_words();
@@ -1239,10 +1566,10 @@ hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, 
     return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
       constexpr int B = decltype(bb)::value;
       if (k == 3)
-        hipLaunchKernelGGL((k_build<B, 3>), dim3(grid), dim3(kThreads), 0, s, fs, k, n_rows, bitmap,
+        hipLaunchKernelGGL((k_build<B, 3>), dim3(grid), dim3(kThreads), 0, s, fs, a, k, n_rows, bitmap,
                            seg_words);
       else
-        hipLaunchKernelGGL((k_build<B, 0>), dim3(grid), dim3(kThreads), 0, s, fs, k, n_rows, bitmap,
+        hipLaunchKernelGGL((k_build<B, 0>), dim3(grid), dim3(kThreads), 0, s, fs, a, k, n_rows, bitmap,
                            seg_words);
       return hipGetLastError();
     });
@@ -1262,7 +1589,7 @@ hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, 
       auto kern = k == 3 ? k_build_lds<B, 3> : k_build_lds<B, 0>;
       hipError_t e = allow_lds(reinterpret_cast<const void *>(kern), copy_words * 4);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(kern, dim3(n_parts), dim3(kWideThreads), copy_words * 4, s, fs, k, n_rows,
+      hipLaunchKernelGGL(kern, dim3(n_parts), dim3(kWideThreads), copy_words * 4, s, fs, a, k, n_rows,
                          bitmap, seg_words, scratch->copies, cw);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
@@ -1306,14 +1633,14 @@ hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, 
     if (e == hipSuccess) e = allow_lds(reinterpret_cast<const void *>(scatter_k), cursor_bytes);
     if (e == hipSuccess) e = allow_lds(reinterpret_cast<const void *>(fill_k), tile_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(count_k, dim3(n_groups), dim3(kWideThreads), hist_bytes, s, fs, bits_per_key,
+    hipLaunchKernelGGL(count_k, dim3(n_groups), dim3(kWideThreads), hist_bytes, s, fs, a, bits_per_key,
                        count, n_rows, bitmap, seg_words, entries_cap, scratch->hist);
     hipLaunchKernelGGL(k_part_scan_groups, dim3(scan_grid ? scan_grid : 1), dim3(kWideThreads), 0, s, fs,
                        block_bits, bits_per_key, count, n_rows, entries_cap, scratch->hist, n_groups,
                        scratch->totals);
     hipLaunchKernelGGL(k_part_scan_buckets, dim3(1), dim3(kWideThreads), 0, s, fs, block_bits,
                        bits_per_key, count, n_rows, entries_cap, scratch->totals, scratch->starts);
-    hipLaunchKernelGGL(scatter_k, dim3(n_groups), dim3(kWideThreads), cursor_bytes, s, fs, k, bits_per_key,
+    hipLaunchKernelGGL(scatter_k, dim3(n_groups), dim3(kWideThreads), cursor_bytes, s, fs, a, k, bits_per_key,
                        count, n_rows, bitmap, seg_words, entries_cap, scratch->hist, scratch->starts,
                        scratch->entries);
     hipLaunchKernelGGL(fill_k, dim3(static_cast<uint32_t>(fill_grid ? fill_grid : 1)), dim3(kWideThreads),
@@ -1350,6 +1677,84 @@ hipError_t launch_compact(const uint64_t *bitmap, uint64_t n_rows, uint32_t *idx
   hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, partials, n_parts, count);
   hipLaunchKernelGGL(k_compact_write, dim3(static_cast<uint32_t>(n_parts)), dim3(kThreads), 0, s,
                      bitmap, n_words, n_rows, partials, idx);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- batched launches
+
+hipError_t launch_local_batch(const LocalTask *tasks, const uint32_t *first, uint32_t n, uint32_t grid,
+                              hipStream_t s) {
+  if (n == 0 || grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_local_batch, dim3(grid), dim3(kBatchThreads), 0, s, tasks, first, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_size_batch(const SizeTask *tasks, const uint32_t *first, uint32_t n, uint32_t grid,
+                             hipStream_t s) {
+  if (n == 0 || grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_size_batch, dim3(grid), dim3(kBatchThreads), 0, s, tasks, first, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_batch(uint32_t block_bits, uint32_t k, const BuildTask *tasks, const uint32_t *first,
+                              uint32_t n, uint32_t grid, uint32_t lds_words, hipStream_t s) {
+  if (n == 0 || grid == 0) return hipSuccess;
+  return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
+    constexpr int B = decltype(bb)::value;
+    auto kern = k == 3 ? k_build_batch<B, 3> : k_build_batch<B, 0>;
+    hipError_t e = allow_lds(reinterpret_cast<const void *>(kern), static_cast<uint64_t>(lds_words) * 4);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBatchThreads), static_cast<uint64_t>(lds_words) * 4, s, tasks,
+                       first, n, k, lds_words);
+    return hipGetLastError();
+  });
+}
+
+uint64_t probe_queue_bytes(bool any64) {
+  return static_cast<uint64_t>(kProbeWaves) * 4 *
+         (any64 ? probe_slice_words<true>() : probe_slice_words<false>());
+}
+
+hipError_t launch_probe_batch(uint32_t block_bits, uint32_t k, bool any64, const ProbeTask *tasks,
+                              const uint32_t *first, uint32_t n, uint32_t grid, uint32_t lds_filter_words,
+                              hipStream_t s) {
+  if (n == 0 || grid == 0) return hipSuccess;
+  lds_filter_words &= ~1u;  // keep the slices 8-byte aligned
+  const uint64_t lds_bytes = static_cast<uint64_t>(lds_filter_words) * 4 + probe_queue_bytes(any64);
+  return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
+    constexpr int B = decltype(bb)::value;
+    auto launch = [&](auto kern) -> hipError_t {
+      hipError_t e = allow_lds(reinterpret_cast<const void *>(kern), lds_bytes);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(kProbeThreads), lds_bytes, s, tasks, first, n, k,
+                         lds_filter_words);
+      return hipGetLastError();
+    };
+    if (k == 3) return any64 ? launch(k_probe_batch<B, 3, true>) : launch(k_probe_batch<B, 3, false>);
+    return any64 ? launch(k_probe_batch<B, 0, true>) : launch(k_probe_batch<B, 0, false>);
+  });
+}
+
+hipError_t prepare_batch_kernels(uint32_t block_bits, uint32_t k, bool any64) {
+  const uint64_t lds_max = static_cast<uint64_t>(device_info().max_lds_block) - 1024;
+  return by_block_bits(block_bits, [&](auto bb) -> hipError_t {
+    constexpr int B = decltype(bb)::value;
+    const void *kerns[] = {
+        reinterpret_cast<const void *>(k == 3 ? k_build_batch<B, 3> : k_build_batch<B, 0>),
+        reinterpret_cast<const void *>(
+            k == 3 ? (any64 ? k_probe_batch<B, 3, true> : k_probe_batch<B, 3, false>)
+                   : (any64 ? k_probe_batch<B, 0, true> : k_probe_batch<B, 0, false>))};
+    for (const void *kern : kerns) {
+      hipError_t e = allow_lds(kern, lds_max);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
+}
+
+hipError_t launch_copy_pairs(const CopyPair *pairs, uint32_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_pairs, dim3((n + 255) / 256), dim3(256), 0, s, pairs, n);
   return hipGetLastError();
 }
 

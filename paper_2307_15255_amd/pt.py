@@ -63,6 +63,12 @@ class pt_bloom(C.Structure):
                 ("params", pt_params)]
 
 
+class pt_problem(C.Structure):
+    _fields_ = [("graph", C.POINTER(pt_graph)), ("tables", C.POINTER(pt_table)), ("preds", C.POINTER(pt_pred)),
+                ("n_preds", C.c_uint32), ("reserved", C.c_uint32), ("params", pt_params),
+                ("d_bitmaps", C.POINTER(C.c_void_p)), ("d_counts", C.c_void_p)]
+
+
 class pt_kernel_time(C.Structure):
     _fields_ = [("name", C.c_char * 24), ("table", C.c_uint32), ("pass_", C.c_uint32),
                 ("rows", C.c_uint64), ("bytes", C.c_uint64), ("ms", C.c_float),
@@ -90,6 +96,12 @@ def _load() -> C.CDLL:
                          C.POINTER(pt_params), vp, C.c_size_t, C.POINTER(vp), vp, vp], st),
         "pt_transfer_filter": ([C.POINTER(pt_graph), C.POINTER(pt_table), C.POINTER(pt_params), vp,
                                 u32, u32, C.POINTER(pt_bloom), C.POINTER(u32)], st),
+        "pt_batch_workspace_size": ([u32, C.POINTER(pt_problem), sizep], st),
+        "pt_batch_prepare": ([u32, C.POINTER(pt_problem), vp, C.c_size_t, C.POINTER(vp)], st),
+        "pt_batch_run": ([vp, vp, u32], st),
+        "pt_batch_info": ([vp, C.POINTER(u32), C.POINTER(u64)], st),
+        "pt_batch_free": ([vp], None),
+        "pt_transfer_batch": ([u32, C.POINTER(pt_problem), vp, C.c_size_t, vp], st),
         "pt_profile_enable": ([C.c_int], st),
         "pt_profile_read": ([C.POINTER(pt_kernel_time), u32, C.POINTER(u32)], st),
     }
@@ -103,7 +115,9 @@ def _load() -> C.CDLL:
 _lib = _load()
 EXPORTS = ("pt_version", "pt_last_error", "pt_local_filter", "pt_bloom_capacity", "pt_bloom_build",
            "pt_bloom_probe", "pt_compact_workspace_size", "pt_compact", "pt_transfer_workspace_size",
-           "pt_transfer", "pt_transfer_filter", "pt_profile_enable", "pt_profile_read")
+           "pt_transfer", "pt_transfer_filter", "pt_batch_workspace_size", "pt_batch_prepare", "pt_batch_run",
+           "pt_batch_info", "pt_batch_free", "pt_transfer_batch", "pt_profile_enable", "pt_profile_read")
+PT_BATCH_EAGER = 1
 
 
 def lib() -> C.CDLL:
@@ -131,8 +145,11 @@ def column(t: torch.Tensor) -> pt_column:
     return pt_column(t.data_ptr() if t.numel() else 0, PT_I64 if t.dtype == torch.int64 else PT_I32, 0)
 
 
-def params(block_bits: int = 512, k: int = 3, bits_per_key: int = 10) -> pt_params:
-    return pt_params(block_bits, k, bits_per_key, 0)
+PT_FLAG_NO_APPEND = 1
+
+
+def params(block_bits: int = 512, k: int = 3, bits_per_key: int = 10, flags: int = 0) -> pt_params:
+    return pt_params(block_bits, k, bits_per_key, flags)
 
 
 def bitmap_words(n_rows: int) -> int:
@@ -301,3 +318,51 @@ class Transfer:
         n = nb * (self.params.block_bits // 32)
         words = self.ws[off:off + 4 * n].cpu().numpy().view(np.uint32)
         return words, nb, builder
+
+
+class Batch:
+    """Many problems run together (pt_batch_*): one launch per step and
+    schedule level for all of them, captured once into a HIP graph. Holds
+    the workspace, every problem's bitmaps and counts."""
+
+    def __init__(self, dps: list[DeviceProblem], ps: list[pt_params] | None = None, device="cuda"):
+        self.dps = dps
+        self.params = ps if ps is not None else [params() for _ in dps]
+        self.bitmaps = [[torch.empty(bitmap_words(n), dtype=torch.int64, device=device) for n in dp.n_rows]
+                        for dp in dps]
+        self.counts = [torch.zeros(dp.n_tables, dtype=torch.int64, device=device) for dp in dps]
+        self._bm = [(C.c_void_p * max(1, dp.n_tables))(*[b.data_ptr() if b.numel() else 0 for b in bms])
+                    for dp, bms in zip(dps, self.bitmaps)]
+        self._probs = (pt_problem * max(1, len(dps)))()
+        for i, dp in enumerate(dps):
+            self._probs[i] = pt_problem(C.pointer(dp.graph), dp.tables, dp.preds, dp.n_preds, 0, self.params[i],
+                                        self._bm[i], self.counts[i].data_ptr())
+        size = C.c_size_t()
+        _check(_lib.pt_batch_workspace_size(len(dps), self._probs, C.byref(size)))
+        self.ws = torch.empty(size.value, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        _check(_lib.pt_batch_prepare(len(dps), self._probs, _ptr(self.ws), self.ws.numel(), C.byref(h)))
+        self._h = h
+
+    def run(self, stream=None, eager: bool = False) -> None:
+        _check(_lib.pt_batch_run(self._h, _stream(stream), PT_BATCH_EAGER if eager else 0))
+
+    def info(self) -> tuple[int, int]:
+        """(kernel launches per run, rows probed per run)."""
+        n, rows = C.c_uint32(), C.c_uint64()
+        _check(_lib.pt_batch_info(self._h, C.byref(n), C.byref(rows)))
+        return n.value, rows.value
+
+    def bitmap(self, i: int, t: int) -> np.ndarray:
+        return self.bitmaps[i][t].cpu().numpy().view(np.uint64)
+
+    def close(self) -> None:
+        if self._h:
+            _lib.pt_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

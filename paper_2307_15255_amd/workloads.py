@@ -301,3 +301,28 @@ def zipf_ranks(rng: np.random.Generator, n: int, s: float, size: int) -> np.ndar
 
 def log_uniform_int(rng: np.random.Generator, lo: int, hi: int) -> int:
     return int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+
+
+# ------------------------------------------------------------------- batches
+
+def batch(seed: int = 1, n_problems: int = 256, lo: int = 10_000, hi: int = 5_000_000) -> list[Problem]:
+    """Independent transfer problems of uneven sizes: alternately a chain
+    R - S - T (key domain twice the smaller end table, R keeps U[1 %, 50 %])
+    and a star with 2 to 4 dimensions (two of them with a predicate keeping
+    U[1 %, 50 %]). Every table has a row count log-uniform on [lo, hi];
+    keys are int32 uniform."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    out = []
+    for i in range(n_problems):
+        sub = int(rng.integers(1, 1 << 31))
+        if i % 2 == 0:
+            n_r, n_s, n_t = (log_uniform_int(rng, lo, hi) for _ in range(3))
+            keep = float(rng.uniform(0.01, 0.50))
+            out.append(chain(sub, n_r, n_s, n_t, domain=2 * min(n_r, n_t), keep=keep))
+        else:
+            nd = int(rng.integers(2, 5))
+            n_fact = log_uniform_int(rng, lo, hi)
+            dims = tuple(log_uniform_int(rng, lo, hi) for _ in range(nd))
+            keeps = (float(rng.uniform(0.01, 0.50)), float(rng.uniform(0.01, 0.50))) + (None,) * (nd - 2)
+            out.append(star(sub, n_fact, dims, keeps, payload=0))
+    return out

@@ -1,0 +1,122 @@
+"""GPU parity of the batched transfer (pt_batch_*): every problem of a batch
+ends with the bitmaps and counts the oracle computes for it alone, whether
+the batch runs eagerly or as its captured graph, replayed several times with
+other GPU work in between."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import assert_bitmaps_equal, say
+from paper_2307_15255_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = ["chain", "star", "tree", "cycle", "parallel", "forest"]
+
+
+@pytest.fixture(scope="module")
+def pt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_15255_amd import pt as ptmod
+    return ptmod
+
+
+def check_against_oracle(pt, bt, probs, params, which=None):
+    counts = [c.cpu().numpy() for c in bt.counts]
+    for i in (range(len(probs)) if which is None else which):
+        p = params[i]
+        ref = oracle.transfer(probs[i], p.block_bits, p.k, p.bits_per_key)
+        for t in range(probs[i].n_tables):
+            assert_bitmaps_equal(bt.bitmap(i, t), ref.bitmaps[t], f"problem {i} ({probs[i].label}) table {t}")
+            assert counts[i][t] == ref.counts[t], (i, t)
+
+
+def mixed_params(pt, n, rng):
+    choices = [(512, 3, 10), (256, 3, 8), (512, 4, 12), (1024, 2, 16), (64, 3, 10)]
+    return [pt.params(*choices[int(rng.integers(len(choices)))]) for _ in range(n)]
+
+
+def test_tiny_graphs_every_shape(pt):
+    """Thirty random graphs of every shape (cycles, forests, parallel edges)
+    with mixed parameters, in one batch."""
+    rng = np.random.default_rng(31)
+    probs = [W.tiny_random(np.random.default_rng(70_000 + s), SHAPES[s % 6]) for s in range(30)]
+    ps = mixed_params(pt, len(probs), rng)
+    bt = pt.Batch([pt.DeviceProblem(p) for p in probs], ps)
+    say("batch tiny eager")
+    bt.run(eager=True)
+    torch.cuda.synchronize()
+    check_against_oracle(pt, bt, probs, ps)
+
+
+def test_graph_replays_match_eager(pt):
+    """A batch of chains and stars of 1 k to 200 k rows: the eager run and
+    three replays of the captured graph (with unrelated GPU work and a
+    synchronisation between them) all give the oracle's bits."""
+    probs = W.batch(seed=5, n_problems=24, lo=1_000, hi=200_000)
+    rng = np.random.default_rng(5)
+    ps = mixed_params(pt, len(probs), rng)
+    bt = pt.Batch([pt.DeviceProblem(p) for p in probs], ps)
+    n_launch, rows = bt.info()
+    say("batch small: launches", n_launch, "rows probed", rows)
+    bt.run(eager=True)
+    torch.cuda.synchronize()
+    check_against_oracle(pt, bt, probs, ps)
+    eager = [[b.clone() for b in bms] for bms in bt.bitmaps]
+    noise = torch.ones(1 << 20, device="cuda")
+    for r in range(3):
+        for bms in bt.bitmaps:
+            for b in bms:
+                b.fill_(-1)
+        bt.run()
+        torch.cuda.synchronize()
+        noise.mul_(1.5).add_(r)  # other work between replays
+        torch.cuda.synchronize()
+        for i, bms in enumerate(bt.bitmaps):
+            for t, b in enumerate(bms):
+                assert torch.equal(b, eager[i][t]), (r, i, t)
+
+
+def test_batch_equals_single_transfers(pt):
+    """Each problem of a batch gets the bits pt_transfer gives it alone."""
+    probs = W.batch(seed=9, n_problems=16, lo=10_000, hi=400_000)
+    dps = [pt.DeviceProblem(p) for p in probs]
+    bt = pt.Batch(dps)
+    bt.run()
+    torch.cuda.synchronize()
+    for i, dp in enumerate(dps):
+        tr = pt.Transfer(dp)
+        tr.run()
+        torch.cuda.synchronize()
+        for t in range(dp.n_tables):
+            assert torch.equal(bt.bitmaps[i][t], tr.bitmaps[t]), (i, t)
+        assert torch.equal(bt.counts[i], tr.counts), i
+
+
+@pytest.mark.timeout(400)
+def test_full_batch_sampled(pt):
+    """256 problems with tables of 10 k to 5 M rows (677 M rows in all), as
+    one graph launch: eight problems checked against the oracle, every
+    problem's counts against pt_transfer on its own."""
+    t0 = time.time()
+    probs = W.batch(seed=1)
+    say("full batch generated", round(time.time() - t0, 1), "s")
+    dps = [pt.DeviceProblem(p) for p in probs]
+    bt = pt.Batch(dps)
+    bt.run()
+    torch.cuda.synchronize()
+    say("full batch ran", round(time.time() - t0, 1), "s")
+    sample = [0, 1, 2, 3, 101, 130, 254, 255]
+    check_against_oracle(pt, bt, probs, bt.params, which=sample)
+    say("full batch oracle sample ok", round(time.time() - t0, 1), "s")
+    for i, dp in enumerate(dps):
+        tr = pt.Transfer(dp)
+        tr.run()
+        torch.cuda.synchronize()
+        assert torch.equal(bt.counts[i], tr.counts), i
+        del tr
+    say("full batch counts ok", round(time.time() - t0, 1), "s")

@@ -27,9 +27,9 @@ def pt():
     return ptmod
 
 
-def check_transfer(pt, prob, B=512, k=3, bpk=10, filters=True, runs=1):
+def check_transfer(pt, prob, B=512, k=3, bpk=10, filters=True, runs=1, flags=0):
     dp = pt.DeviceProblem(prob)
-    tr = pt.Transfer(dp, pt.params(B, k, bpk))
+    tr = pt.Transfer(dp, pt.params(B, k, bpk, flags))
     for _ in range(runs):
         tr.run()
     torch.cuda.synchronize()
@@ -134,6 +134,23 @@ def test_snowflake_full_size(pt):
     say("snowflake full: generated", round(time.time() - t0, 1), "s")
     tr, ref = check_transfer(pt, prob, 512, 3, 12, filters=False)
     say("snowflake full: counts", ref.counts, "after", round(time.time() - t0, 1), "s")
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("n_fact", [20_000, 3_000_000])
+def test_append_and_rescan_agree(pt, flags, n_fact):
+    """Builds from keys appended during the probe (the default) and builds
+    that scan the selected rows again (PT_FLAG_NO_APPEND) write the same
+    filters; at 3 M fact rows the dense dimension probes overflow some
+    append regions, which are then walked."""
+    key64 = (True, False, False, True) if n_fact < 100_000 else ()
+    prob = W.star(seed=11, n_fact=n_fact, dims=(n_fact // 3, n_fact // 20, 500, 25), keeps=(0.3, 0.9, None, None),
+                  payload=0, key64=key64)
+    say("append", flags, n_fact)
+    check_transfer(pt, prob, flags=flags)
+    for s in range(3):
+        say("append tiny", flags, s)
+        check_transfer(pt, W.tiny_random(np.random.default_rng(9100 + s), SHAPES[s]), flags=flags)
 
 
 @pytest.mark.parametrize("path,max_entries", [("atomic", None), ("part", None), ("part", "1000")])
