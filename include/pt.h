@@ -281,6 +281,12 @@ pt_status pt_batch_workspace_size(uint32_t n_problems, const pt_problem *problem
 pt_status pt_batch_prepare(uint32_t n_problems, const pt_problem *problems, void *d_ws,
                            size_t ws_bytes, pt_batch **out);
 
+/* As pt_batch_prepare, but the task tables are copied asynchronously on
+ * `stream` (from a host buffer the handle keeps); runs must be ordered after
+ * that copy (same stream, or synchronized with it). */
+pt_status pt_batch_prepare_async(uint32_t n_problems, const pt_problem *problems, void *d_ws,
+                                 size_t ws_bytes, pt_stream stream, pt_batch **out);
+
 /* Runs the batch on `stream`: every problem's bitmaps and counts are
  * written as pt_transfer would write them. flags = 0 launches the captured
  * graph (captured on the first run); PT_BATCH_EAGER enqueues the kernels one

@@ -865,7 +865,20 @@ std::vector<uint32_t> levels(const Plan &pl, uint32_t p) {
   return lvl;
 }
 
-enum LaunchKind : uint32_t { kZero, kLocal, kSize, kBuild, kProbe, kCopy };
+enum LaunchKind : uint32_t { kZero, kLocal, kSize, kBuild, kProbe, kCopy, kSoloBuild };
+
+// A table of at least this many rows whose outgoing filters cannot fit in
+// LDS even at their smallest is built on its own with the partitioned build
+// (inside the batch's sequence), not by a batched build.
+constexpr uint64_t kSoloBuildRows = 8ull << 20;
+
+// Bitmap words (64 rows each) one workgroup of a batched local filter,
+// probe or build takes: enough rows that its fixed cost (finding its task,
+// staging filters) is small beside its scan.
+constexpr uint64_t kBatchWordsPerBlock = 1024;
+
+// LDS a batched probe may stage filters in: two workgroups per CU.
+constexpr uint64_t kBatchProbeLdsBytes = 64 * 1024;
 
 struct BatchLaunch {
   LaunchKind kind;
@@ -875,6 +888,10 @@ struct BatchLaunch {
   uint32_t n = 0, grid = 0, lds_words = 0;
   uint32_t pass = 0;                      // 1 forward, 2 backward (probes, builds)
   uint64_t rows = 0, bytes = 0;           // rows scanned, algorithmic bytes (probes)
+  // kSoloBuild: one table's filters, built by launch_build
+  FilterSet fs{};
+  const uint64_t *bitmap = nullptr, *count = nullptr;
+  uint32_t bits_per_key = 0;
 };
 
 // Task lists of one launch before they are laid out.
@@ -896,6 +913,9 @@ uint32_t clamp_u32(uint64_t v, uint64_t lo, uint64_t hi) {
 
 struct BatchPlan {
   std::vector<Plan> plans;
+  // scratch of the solo builds (partitioned), shared: they run one by one
+  uint64_t off_hist = 0, off_totals = 0, off_starts = 0, off_entries = 0, entries_cap = 0;
+  uint32_t hist_groups = 0;
   std::vector<uint64_t> off_problem;  // per problem: its nb and filter region
   uint64_t off_counts = 0, n_counts = 0;
   uint64_t data_end = 0, total = 0;
@@ -921,10 +941,12 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
     st = check_preds(pl, pr.tables, pr.preds, pr.n_preds);
     if (st != PT_OK) return fail(st, "problem %u: %s", i, g_error.c_str());
     if (pr.reserved != 0) return fail(PT_EINVAL, "problem %u: reserved field is not 0", i);
-    if (pl.n_t > 0 && !pr.d_bitmaps) return fail(PT_EINVAL, "problem %u: d_bitmaps is NULL", i);
-    for (uint32_t t = 0; t < pl.n_t; t++)
-      if (pr.tables[t].n_rows > 0 && !pr.d_bitmaps[t])
-        return fail(PT_EINVAL, "problem %u: d_bitmaps[%u] is NULL", i, t);
+    if (ws) {  // the size query needs no output buffers
+      if (pl.n_t > 0 && !pr.d_bitmaps) return fail(PT_EINVAL, "problem %u: d_bitmaps is NULL", i);
+      for (uint32_t t = 0; t < pl.n_t; t++)
+        if (pr.tables[t].n_rows > 0 && !pr.d_bitmaps[t])
+          return fail(PT_EINVAL, "problem %u: d_bitmaps[%u] is NULL", i, t);
+    }
     n_counts += 3ull * pl.n_t;
   }
   bp.off_counts = off;
@@ -995,11 +1017,11 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
           lt.ps.p[lt.ps.n++] = PredRef{c.data, c.dtype == PT_I64 ? 1u : 0u, q->op, q->lo, q->hi};
         }
         lt.n_rows = tb.n_rows;
-        lt.bitmap = pr.d_bitmaps[t];
+        lt.bitmap = ws ? pr.d_bitmaps[t] : nullptr;
         lt.count = count_ptr(i, 0, t);
         lt.seg_words = 16;
         const uint64_t n_words = (tb.n_rows + 63) / 64;
-        d.add(lt, clamp_u32((n_words + 16 * 16 * 4 - 1) / (16 * 16 * 4), 1, 512));
+        d.add(lt, clamp_u32((n_words + kBatchWordsPerBlock - 1) / kBatchWordsPerBlock, 1, 4096));
       }
     }
     d.l.n = static_cast<uint32_t>(d.first.size() - 1);
@@ -1051,10 +1073,9 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
             }
             const bool last = c0 + kMaxProbe >= in.size();
             pt.n_rows = pr.tables[v].n_rows;
-            pt.bitmap = pr.d_bitmaps[v];
+            pt.bitmap = ws ? pr.d_bitmaps[v] : nullptr;
             pt.count = last ? count_ptr(i, p + 1, v) : nullptr;
             pt.input_all = 0;
-            const uint32_t U = any64 ? 4 : 8;
             const uint64_t n_words = (pt.n_rows + 63) / 64;
             const Key key{pr.params.block_bits, pr.params.k, any64};
             LaunchDraft &d = probes[{key, chunk}];
@@ -1062,7 +1083,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
             d.l.block_bits = pr.params.block_bits;
             d.l.k = pr.params.k;
             d.l.any64 = any64;
-            d.add(pt, clamp_u32((n_words + 16ull * U * 4 - 1) / (16ull * U * 4), 1, 1024));
+            d.add(pt, clamp_u32((n_words + kBatchWordsPerBlock - 1) / kBatchWordsPerBlock, 1, 4096));
             d.l.pass = p + 1;
             d.l.rows += pt.n_rows;
             d.l.bytes += 2 * n_words * 8;  // bitmap read and written
@@ -1082,7 +1103,8 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
           any = true;
           LaunchDraft d = std::move(kv.second);
           const bool any64 = std::get<2>(kv.first.first);
-          const uint64_t room = lds_max > probe_queue_bytes(any64) ? (lds_max - probe_queue_bytes(any64)) / 4 : 0;
+          const uint64_t lds_cap = std::min<uint64_t>(lds_max, kBatchProbeLdsBytes);
+          const uint64_t room = lds_cap > probe_queue_bytes(any64) ? (lds_cap - probe_queue_bytes(any64)) / 4 : 0;
           d.l.lds_words = static_cast<uint32_t>(std::min<uint64_t>(room, probe_need[kv.first]));
           d.l.n = static_cast<uint32_t>(d.first.size() - 1);
           bp.drafts.push_back(std::move(d));
@@ -1092,6 +1114,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
       // Sizes and builds of the filters sent by this level's tables.
       LaunchDraft size;
       size.l.kind = kSize;
+      std::vector<LaunchDraft> solos;
       std::map<std::pair<uint32_t, uint32_t>, LaunchDraft> builds;
       std::map<std::pair<uint32_t, uint32_t>, uint64_t> build_need;
       for (uint32_t i = 0; i < n_problems; i++) {
@@ -1105,6 +1128,26 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
           if (out.empty()) continue;
           const uint64_t n_rows = pr.tables[v].n_rows;
           const uint64_t *cnt = count_ptr(i, cur[i][v], v);
+          uint64_t cap_all = 0;
+          for (uint32_t e : out) cap_all += pl.cap_words[p * pl.n_e + e];
+          if (n_rows >= kSoloBuildRows && cap_all > build_lds_words()) {
+            for (uint32_t c0 = 0; c0 < out.size(); c0 += kMaxFilters) {
+              LaunchDraft d;
+              d.l.kind = kSoloBuild;
+              d.l.block_bits = pr.params.block_bits;
+              d.l.k = pr.params.k;
+              d.l.bits_per_key = pr.params.bits_per_key;
+              d.l.pass = p + 1;
+              d.l.rows = n_rows;
+              d.l.bitmap = ws ? pr.d_bitmaps[v] : nullptr;
+              d.l.count = cnt;
+              for (uint32_t j = c0; j < out.size() && d.l.fs.n < static_cast<uint32_t>(kMaxFilters); j++)
+                d.l.fs.f[d.l.fs.n++] = filter_ref(i, p, out[j], v);
+              bp.entries_cap = std::max<uint64_t>(bp.entries_cap, d.l.fs.n * n_rows);
+              solos.push_back(std::move(d));
+            }
+            continue;
+          }
           for (uint32_t c0 = 0; c0 < out.size(); c0 += kMaxProbe) {
             BuildTask bt{};
             uint64_t need = 0;
@@ -1121,7 +1164,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
               bt.fs.f[bt.fs.n++] = r;
             }
             bt.n_rows = n_rows;
-            bt.bitmap = n_rows ? pr.d_bitmaps[v] : nullptr;
+            bt.bitmap = (ws && n_rows) ? pr.d_bitmaps[v] : nullptr;
             bt.seg_words = 16;
             const uint64_t n_words = (n_rows + 63) / 64;
             const std::pair<uint32_t, uint32_t> key{pr.params.block_bits, pr.params.k};
@@ -1129,7 +1172,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
             d.l.kind = kBuild;
             d.l.block_bits = pr.params.block_bits;
             d.l.k = pr.params.k;
-            d.add(bt, clamp_u32((n_words + 16 * 16 * 4 - 1) / (16 * 16 * 4), 1, 64));
+            d.add(bt, clamp_u32((n_words + kBatchWordsPerBlock - 1) / kBatchWordsPerBlock, 1, 1024));
             uint64_t &mx = build_need[key];
             mx = std::max(mx, need);
           }
@@ -1145,6 +1188,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
         d.l.n = static_cast<uint32_t>(d.first.size() - 1);
         bp.drafts.push_back(std::move(d));
       }
+      for (LaunchDraft &d : solos) bp.drafts.push_back(std::move(d));
     }
   }
   // 4. Final counts to the callers' arrays.
@@ -1152,7 +1196,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
     LaunchDraft d;
     d.l.kind = kCopy;
     for (uint32_t i = 0; i < n_problems; i++) {
-      if (!probs[i].d_counts) continue;
+      if (ws && !probs[i].d_counts) continue;  // sizes assume every problem wants its counts
       for (uint32_t t = 0; t < bp.plans[i].n_t; t++) {
         CopyPair cp{count_ptr(i, cur[i][t], t), probs[i].d_counts + t};
         const char *b = reinterpret_cast<const char *>(&cp);
@@ -1162,16 +1206,34 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
     d.l.n = static_cast<uint32_t>(d.tasks.size() / sizeof(CopyPair));
     bp.drafts.push_back(std::move(d));
   }
-  // Task tables after the data.
+  // Scratch of the solo builds, then the task tables, after the data.
   off = bp.data_end;
+  if (bp.entries_cap > 0) {
+    bp.entries_cap = std::min<uint64_t>(bp.entries_cap, kMaxEntries);
+    bp.hist_groups = static_cast<uint32_t>(device_info().n_cu);
+    bp.off_hist = off;
+    off = align256(off + static_cast<uint64_t>(bp.hist_groups) * kMaxBuckets * 4);
+    bp.off_totals = off;
+    off = align256(off + static_cast<uint64_t>(kMaxBuckets) * 8);
+    bp.off_starts = off;
+    off = align256(off + (static_cast<uint64_t>(kMaxBuckets) + 1) * 8);
+    bp.off_entries = off;
+    off = align256(off + bp.entries_cap * 4);
+  }
+  const uint64_t tables_begin = off;
   for (LaunchDraft &d : bp.drafts) {
     d.l.tasks_off = off;
     off = align256(off + d.tasks.size());
+    d.l.grid = d.first.back();
+    // the per-workgroup task map follows the task starts
+    const size_t n_first = d.first.size();
+    for (uint32_t t = 0; t + 1 < n_first; t++)
+      for (uint32_t b = d.first[t]; b < d.first[t + 1]; b++) d.first.push_back(t);
     d.l.first_off = off;
     off = align256(off + d.first.size() * 4);
-    d.l.grid = d.first.back();
   }
   bp.total = off;
+  bp.data_end = tables_begin;  // the task tables start here
   return PT_OK;
 }
 
@@ -1180,6 +1242,8 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
 struct pt_batch {
   int device = 0;
   char *ws = nullptr;
+  BuildScratch scratch;  // offsets resolved into ws (solo builds)
+  std::vector<char> staging;  // host copy of the task tables
   std::vector<BatchLaunch> launches;
   uint64_t off_counts = 0, n_counts = 0, rows_probed = 0;
   hipStream_t capture = nullptr;
@@ -1217,6 +1281,10 @@ static pt_status enqueue_batch(const pt_batch &b, hipStream_t s, bool timed) {
       case kCopy:
         e = launch_copy_pairs(reinterpret_cast<const CopyPair *>(tasks), l.n, s);
         break;
+      case kSoloBuild:
+        e = launch_build(l.block_bits, l.k, l.bits_per_key, l.fs, l.rows, l.bitmap, l.count, &b.scratch,
+                         nullptr, s);
+        break;
     }
     pt_status st = check_hip(e, "batch launch");
     if (st != PT_OK) return st;
@@ -1237,6 +1305,18 @@ pt_status pt_batch_workspace_size(uint32_t n_problems, const pt_problem *problem
 
 pt_status pt_batch_prepare(uint32_t n_problems, const pt_problem *problems, void *d_ws, size_t ws_bytes,
                            pt_batch **out) {
+  pt_status st = pt_batch_prepare_async(n_problems, problems, d_ws, ws_bytes, nullptr, out);
+  if (st != PT_OK) return st;
+  st = check_hip(hipDeviceSynchronize(), "task table copy");
+  if (st != PT_OK) {
+    pt_batch_free(*out);
+    *out = nullptr;
+  }
+  return st;
+}
+
+pt_status pt_batch_prepare_async(uint32_t n_problems, const pt_problem *problems, void *d_ws, size_t ws_bytes,
+                                 pt_stream stream, pt_batch **out) {
   if (!out) return fail(PT_EINVAL, "out is NULL");
   *out = nullptr;
   if (!d_ws) return fail(PT_EINVAL, "d_ws is NULL");
@@ -1253,19 +1333,34 @@ pt_status pt_batch_prepare(uint32_t n_problems, const pt_problem *problems, void
     if (st != PT_OK) return st;
   }
   char *ws = static_cast<char *>(d_ws);
-  for (const LaunchDraft &d : bp.drafts) {
-    if (!d.tasks.empty()) {
-      st = check_hip(hipMemcpy(ws + d.l.tasks_off, d.tasks.data(), d.tasks.size(), hipMemcpyHostToDevice),
-                     "task table copy");
-      if (st != PT_OK) return st;
-    }
-    st = check_hip(hipMemcpy(ws + d.l.first_off, d.first.data(), d.first.size() * 4, hipMemcpyHostToDevice),
-                   "task table copy");
-    if (st != PT_OK) return st;
-  }
+  // The task tables go to the workspace in one asynchronous copy on
+  // `stream`, from a host buffer the handle keeps until it is freed.
   auto *b = new pt_batch();
+  const uint64_t table_bytes = bp.total - bp.data_end;
+  b->staging.assign(table_bytes, 0);
+  for (const LaunchDraft &d : bp.drafts) {
+    std::memcpy(b->staging.data() + (d.l.tasks_off - bp.data_end), d.tasks.data(), d.tasks.size());
+    std::memcpy(b->staging.data() + (d.l.first_off - bp.data_end), d.first.data(), d.first.size() * 4);
+  }
+  if (table_bytes) {
+    st = check_hip(hipMemcpyAsync(ws + bp.data_end, b->staging.data(), table_bytes, hipMemcpyHostToDevice,
+                                  reinterpret_cast<hipStream_t>(stream)),
+                   "task table copy");
+    if (st != PT_OK) {
+      pt_batch_free(b);
+      return st;
+    }
+  }
   if (hipGetDevice(&b->device) != hipSuccess) b->device = 0;
   b->ws = ws;
+  if (bp.entries_cap > 0) {
+    b->scratch.hist = reinterpret_cast<uint32_t *>(ws + bp.off_hist);
+    b->scratch.hist_groups = bp.hist_groups;
+    b->scratch.totals = reinterpret_cast<uint64_t *>(ws + bp.off_totals);
+    b->scratch.starts = reinterpret_cast<uint64_t *>(ws + bp.off_starts);
+    b->scratch.entries = reinterpret_cast<uint32_t *>(ws + bp.off_entries);
+    b->scratch.entries_cap = bp.entries_cap;
+  }
   b->off_counts = bp.off_counts;
   b->n_counts = bp.n_counts;
   b->rows_probed = bp.rows_probed;

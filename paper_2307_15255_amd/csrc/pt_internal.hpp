@@ -120,7 +120,8 @@ uint64_t compact_partials(uint64_t n_rows);
 //
 // A batched launch runs the same step for many tables of many problems. Its
 // tasks live in device memory; task i owns workgroups [first[i], first[i+1])
-// of the launch (first has n + 1 entries, first[n] = the grid size).
+// of the launch (first has n + 1 entries, first[n] = the grid size, then
+// one entry per workgroup: the task it belongs to).
 
 // Local predicates of one table (no predicates: every row).
 struct LocalTask {

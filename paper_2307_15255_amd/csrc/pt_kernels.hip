@@ -48,19 +48,15 @@ __device__ __forceinline__ uint64_t wave_count(const VGrid &g) {
 }
 
 
-// The task of this workgroup: first[t] <= blockIdx.x < first[t + 1]
-// (binary search over the n + 1 prefix entries; uniform).
+// The task of this workgroup. `first` holds the n + 1 first workgroups of
+// the tasks (first[t] <= blockIdx.x < first[t + 1]) followed by the task of
+// every workgroup of the grid, so the lookup is one load and one pair.
 __device__ __forceinline__ uint32_t task_of(const uint32_t *first, uint32_t n, VGrid &g) {
-  uint32_t lo = 0, hi = n;  // first[lo] <= blockIdx.x < first[hi]
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) / 2;
-    if (first[mid] <= blockIdx.x) lo = mid;
-    else hi = mid;
-  }
-  const uint32_t a = __builtin_amdgcn_readfirstlane(first[lo]);
-  const uint32_t b = __builtin_amdgcn_readfirstlane(first[lo + 1]);
+  const uint32_t t = __builtin_amdgcn_readfirstlane(first[n + 1 + blockIdx.x]);
+  const uint32_t a = __builtin_amdgcn_readfirstlane(first[t]);
+  const uint32_t b = __builtin_amdgcn_readfirstlane(first[t + 1]);
   g = VGrid{blockIdx.x - a, b - a};
-  return __builtin_amdgcn_readfirstlane(lo);
+  return t;
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -170,6 +166,23 @@ __device__ __forceinline__ void insert_bits(uint32_t *words, uint32_t nb, uint32
     uint32_t *w = blk + (p >> 5);
     if ((__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit) == 0)
       atomicOr(w, bit);
+    pos += g2;
+  }
+}
+
+// Set the k bits of a key with atomic OR alone (no read first).
+template <int B, int K>
+__device__ __forceinline__ void or_bits(uint32_t *words, uint32_t nb, uint32_t k, uint32_t h1, uint32_t h2) {
+  using S = BlockShape<B>;
+  uint32_t *blk = words + static_cast<uint64_t>(block_of(h1, nb)) * S::kWords;
+  const uint32_t g1 = h2 >> (32 - S::kLog2);
+  const uint32_t g2 = ((h2 >> (32 - 2 * S::kLog2)) & (B - 1)) | 1u;
+  uint32_t pos = g1;
+  const uint32_t kk = K > 0 ? static_cast<uint32_t>(K) : k;
+#pragma unroll
+  for (uint32_t i = 0; i < kk; i++) {
+    const uint32_t p = pos & (B - 1);
+    atomicOr(blk + (p >> 5), 1u << (p & 31));
     pos += g2;
   }
 }
@@ -1346,8 +1359,10 @@ __global__ void __launch_bounds__(kBatchThreads)
   const AppendSet none{};
   const LdsPlan pl = lds_plan<B>(fs, lds_words);
   if (!pl.fits) {
+    // atomic OR without a prior read: nothing waits on the result, so a
+    // wave's inserts overlap
     for_each_key(fs, none, t.n_rows, t.bitmap, t.seg_words, vg, [&](int i, uint32_t h1, uint32_t h2) {
-      insert_bits<B, K>(fs.f[i].words, pl.nb[i], k, h1, h2);
+      or_bits<B, K>(fs.f[i].words, pl.nb[i], k, h1, h2);
     });
     return;
   }

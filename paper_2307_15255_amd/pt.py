@@ -98,6 +98,7 @@ def _load() -> C.CDLL:
                                 u32, u32, C.POINTER(pt_bloom), C.POINTER(u32)], st),
         "pt_batch_workspace_size": ([u32, C.POINTER(pt_problem), sizep], st),
         "pt_batch_prepare": ([u32, C.POINTER(pt_problem), vp, C.c_size_t, C.POINTER(vp)], st),
+        "pt_batch_prepare_async": ([u32, C.POINTER(pt_problem), vp, C.c_size_t, vp, C.POINTER(vp)], st),
         "pt_batch_run": ([vp, vp, u32], st),
         "pt_batch_info": ([vp, C.POINTER(u32), C.POINTER(u64)], st),
         "pt_batch_free": ([vp], None),
@@ -115,7 +116,8 @@ def _load() -> C.CDLL:
 _lib = _load()
 EXPORTS = ("pt_version", "pt_last_error", "pt_local_filter", "pt_bloom_capacity", "pt_bloom_build",
            "pt_bloom_probe", "pt_compact_workspace_size", "pt_compact", "pt_transfer_workspace_size",
-           "pt_transfer", "pt_transfer_filter", "pt_batch_workspace_size", "pt_batch_prepare", "pt_batch_run",
+           "pt_transfer", "pt_transfer_filter", "pt_batch_workspace_size", "pt_batch_prepare",
+           "pt_batch_prepare_async", "pt_batch_run",
            "pt_batch_info", "pt_batch_free", "pt_transfer_batch", "pt_profile_enable", "pt_profile_read")
 PT_BATCH_EAGER = 1
 
@@ -294,11 +296,17 @@ class Transfer:
     """Holds the workspace, bitmaps and counts of one problem and runs the
     transfer phase on it (all allocation happens here, once)."""
 
-    def __init__(self, dp: DeviceProblem, p: pt_params | None = None, device="cuda"):
+    def __init__(self, dp: DeviceProblem, p: pt_params | None = None, device="cuda",
+                 ws: torch.Tensor | None = None):
         self.dp = dp
         self.params = p if p is not None else params()
         self.ws_bytes = pt_transfer_workspace_size(dp, self.params)
-        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        if ws is not None:
+            if ws.numel() < self.ws_bytes:
+                raise ValueError(f"workspace of {ws.numel()} bytes, {self.ws_bytes} needed")
+            self.ws = ws
+        else:
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.bitmaps = [torch.empty(bitmap_words(n), dtype=torch.int64, device=device) for n in dp.n_rows]
         self.counts = torch.zeros(dp.n_tables, dtype=torch.int64, device=device)
 
@@ -320,12 +328,25 @@ class Transfer:
         return words, nb, builder
 
 
+def pt_batch_workspace_size(dps: list[DeviceProblem], ps: list[pt_params]) -> int:
+    probs = (pt_problem * max(1, len(dps)))()
+    for i, dp in enumerate(dps):
+        probs[i] = pt_problem(C.pointer(dp.graph), dp.tables, dp.preds, dp.n_preds, 0, ps[i], None, None)
+    size = C.c_size_t()
+    _check(_lib.pt_batch_workspace_size(len(dps), probs, C.byref(size)))
+    return size.value
+
+
 class Batch:
     """Many problems run together (pt_batch_*): one launch per step and
     schedule level for all of them, captured once into a HIP graph. Holds
     the workspace, every problem's bitmaps and counts."""
 
-    def __init__(self, dps: list[DeviceProblem], ps: list[pt_params] | None = None, device="cuda"):
+    def __init__(self, dps: list[DeviceProblem], ps: list[pt_params] | None = None, device="cuda",
+                 stream=None, ws: torch.Tensor | None = None):
+        """stream: prepare asynchronously on this stream (runs must follow on
+        it); ws: a uint8 device buffer to use as the workspace (at least
+        pt_batch_workspace_size bytes, 256-byte aligned) instead of a new one."""
         self.dps = dps
         self.params = ps if ps is not None else [params() for _ in dps]
         self.bitmaps = [[torch.empty(bitmap_words(n), dtype=torch.int64, device=device) for n in dp.n_rows]
@@ -339,9 +360,18 @@ class Batch:
                                         self._bm[i], self.counts[i].data_ptr())
         size = C.c_size_t()
         _check(_lib.pt_batch_workspace_size(len(dps), self._probs, C.byref(size)))
-        self.ws = torch.empty(size.value, dtype=torch.uint8, device=device)
+        if ws is not None:
+            if ws.numel() < size.value:
+                raise ValueError(f"workspace of {ws.numel()} bytes, {size.value} needed")
+            self.ws = ws
+        else:
+            self.ws = torch.empty(size.value, dtype=torch.uint8, device=device)
         h = C.c_void_p()
-        _check(_lib.pt_batch_prepare(len(dps), self._probs, _ptr(self.ws), self.ws.numel(), C.byref(h)))
+        if stream is None:
+            _check(_lib.pt_batch_prepare(len(dps), self._probs, _ptr(self.ws), self.ws.numel(), C.byref(h)))
+        else:
+            _check(_lib.pt_batch_prepare_async(len(dps), self._probs, _ptr(self.ws), self.ws.numel(),
+                                               _stream(stream), C.byref(h)))
         self._h = h
 
     def run(self, stream=None, eager: bool = False) -> None:

@@ -1,0 +1,270 @@
+"""Serving transfer queries over tables resident in HBM.
+
+A query asks for the transfer phase over a subgraph of a resident star
+schema (the fact table and one to four dimensions, each edge on its int32 or
+int64 key columns, one or two range predicates). The server keeps the tables
+on the GPU and runs a request loop:
+
+  admission   queries wait in arrival order; the head is admitted when the
+              memory its filters, bitmaps and task tables need fits in what
+              the in-flight batches leave of the budget (a ledger of bytes);
+  batching    every admitted query that is waiting when a launch slot is
+              free goes into one batch (pt_batch: one launch per step and
+              schedule level for all of its queries);
+  overlap     up to `slots` batches are in flight at once, each on its own
+              stream: queries that arrive while others run are admitted and
+              launched as soon as a slot and memory free up.
+
+The loop is written against a small executor interface (mem_need, launch,
+done, finish) so its admission and batching logic also runs, with a host
+executor, where there is no GPU. The paper evaluates one query at a time;
+serving is an addition.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import workloads as W
+
+
+@dataclass
+class Query:
+    qid: int
+    dims: list[int]                 # dimensions joined to the fact table
+    wide: list[bool]                # per joined dimension: int64 key columns
+    preds: list[tuple[int, int]]    # (dimension, threshold): attr < threshold
+    arrival: float = 0.0            # seconds after the start of the stream
+
+
+def random_query(rng: np.random.Generator, qid: int, n_dims: int = 4, wide_dims: tuple[int, ...] = (0, 1),
+                 sel_lo: float = 0.001, sel_hi: float = 0.5) -> Query:
+    """A fact table plus 1-4 distinct dimensions (2-5 tables); the int64 key
+    variant on each edge that has one with probability 1/2; one or two
+    predicates on joined dimensions with selectivity log-uniform on
+    [sel_lo, sel_hi]."""
+    k = int(rng.integers(1, n_dims + 1))
+    dims = sorted(int(d) for d in rng.choice(n_dims, size=k, replace=False))
+    wide = [d in wide_dims and bool(rng.integers(2)) for d in dims]
+    n_pred = min(len(dims), int(rng.integers(1, 3)))
+    preds = []
+    for d in rng.choice(dims, size=n_pred, replace=False):
+        sel = math.exp(rng.uniform(math.log(sel_lo), math.log(sel_hi)))
+        preds.append((int(d), max(1, int(round(sel * 1_000_000)))))
+    return Query(qid, dims, wide, sorted(preds))
+
+
+def poisson_arrivals(rng: np.random.Generator, n: int, qps: float) -> np.ndarray:
+    return np.cumsum(rng.exponential(1.0 / qps, size=n))
+
+
+class ResidentStar:
+    """The star schema (fact with int32 foreign keys k0..k3, dimensions with
+    primary key pk and attribute attr uniform on [0, 10^6)) plus int64 twins
+    of the keys of the edges in `wide_dims`, on the host and in HBM."""
+
+    def __init__(self, seed: int = 1, n_fact: int = 100_000_000, dims: tuple[int, ...] = W.STAR_DIMS,
+                 wide_dims: tuple[int, ...] = (0, 1), device: str | None = "cuda"):
+        base = W.star(seed=seed, n_fact=n_fact, dims=dims, keeps=(None,) * len(dims), payload=0)
+        self.dims = dims
+        self.wide_dims = wide_dims
+        self.host = [dict(c) for c in base.columns]
+        for d in wide_dims:
+            self.host[0][f"k{d}_64"] = self.host[0][f"k{d}"].astype(np.int64)
+            self.host[d + 1]["pk64"] = self.host[d + 1]["pk"].astype(np.int64)
+        self.dev = None
+        if device is not None:
+            import torch
+            self.dev = [{c: torch.from_numpy(np.ascontiguousarray(a)).to(device) for c, a in cols.items()}
+                        for cols in self.host]
+
+    def problem(self, q: Query) -> tuple[W.Problem, list | None]:
+        """The query as a join problem, with the device columns in the same
+        order (None without a device)."""
+        names, cols, dev, edges, preds = ["F"], [{}], [{}], [], []
+        for i, (d, wide) in enumerate(zip(q.dims, q.wide)):
+            fk, pk = (f"k{d}_64", "pk64") if wide else (f"k{d}", "pk")
+            cols[0][fk] = self.host[0][fk]
+            names.append(f"D{d}")
+            cols.append({pk: self.host[d + 1][pk], "attr": self.host[d + 1]["attr"]})
+            if self.dev is not None:
+                dev[0][fk] = self.dev[0][fk]
+                dev.append({pk: self.dev[d + 1][pk], "attr": self.dev[d + 1]["attr"]})
+            edges.append((0, fk, i + 1, pk))
+        for d, thr in q.preds:
+            preds.append((q.dims.index(d) + 1, "attr", "lt", thr, 0))
+        label = f"query {q.qid}: F + {['D%d%s' % (d, '/64' if w else '') for d, w in zip(q.dims, q.wide)]}"
+        return W.Problem(names, cols, edges, preds, label=label), (dev if self.dev is not None else None)
+
+
+@dataclass
+class Report:
+    latency: dict = field(default_factory=dict)    # qid -> seconds from arrival to results ready
+    service: dict = field(default_factory=dict)    # qid -> seconds from launch to results ready (alone)
+    finish: dict = field(default_factory=dict)     # qid -> seconds after start
+    batches: list = field(default_factory=list)    # (launch time, [qid], bytes)
+    peak_bytes: int = 0
+    wall: float = 0.0
+
+    def percentile(self, p: float) -> float:
+        return float(np.percentile(np.array(list(self.latency.values())), p))
+
+
+def serve(queries: list[Query], executor, budget_bytes: int, slots: int = 2, max_batch: int = 64,
+          batch_bytes: int | None = None, clock=time.perf_counter, idle=lambda: time.sleep(50e-6)) -> Report:
+    """Runs the request loop over `queries` (sorted by arrival) on
+    `executor` and reports every query's latency. budget_bytes bounds the
+    memory of all batches in flight, batch_bytes (default: the budget) that
+    of one batch. A query needing more than either is rejected with
+    ValueError before the loop starts."""
+    rep = Report()
+    cap = budget_bytes if batch_bytes is None else min(batch_bytes, budget_bytes)
+    need = {q.qid: executor.mem_need(q) for q in queries}
+    for q in queries:
+        if need[q.qid] > cap:
+            raise ValueError(f"query {q.qid} needs {need[q.qid]} bytes, over the limit of {cap}")
+    pending = collections.deque(sorted(queries, key=lambda q: q.arrival))
+    waiting: collections.deque[Query] = collections.deque()
+    inflight = []  # (handle, queries, bytes, slot)
+    free_slots = list(range(slots))
+    used = 0
+    t0 = clock()
+    while pending or waiting or inflight:
+        now = clock() - t0
+        while pending and pending[0].arrival <= now:
+            waiting.append(pending.popleft())
+        progressed = False
+        for item in list(inflight):
+            handle, qs, nbytes, slot = item
+            if executor.done(handle):
+                t = clock() - t0
+                executor.finish(handle)
+                for q in qs:
+                    rep.finish[q.qid] = t
+                    rep.latency[q.qid] = t - q.arrival
+                used -= nbytes
+                free_slots.append(slot)
+                inflight.remove(item)
+                progressed = True
+        if waiting and free_slots:
+            take, nbytes = [], 0
+            while (waiting and len(take) < max_batch and used + nbytes + need[waiting[0].qid] <= budget_bytes
+                   and nbytes + need[waiting[0].qid] <= cap):
+                q = waiting.popleft()
+                take.append(q)
+                nbytes += need[q.qid]
+            if take:
+                slot = free_slots.pop(0)
+                used += nbytes
+                rep.peak_bytes = max(rep.peak_bytes, used)
+                rep.batches.append((clock() - t0, [q.qid for q in take], nbytes))
+                inflight.append((executor.launch(take, slot), take, nbytes, slot))
+                progressed = True
+        if not progressed:
+            idle()
+    rep.wall = clock() - t0
+    return rep
+
+
+def one_at_a_time(queries: list[Query], executor, clock=time.perf_counter,
+                  idle=lambda: time.sleep(50e-6)) -> Report:
+    """The baseline: queries in arrival order, each run alone once the
+    previous one has finished."""
+    rep = Report()
+    t0 = clock()
+    for q in sorted(queries, key=lambda q: q.arrival):
+        while clock() - t0 < q.arrival:
+            idle()
+        start = clock() - t0
+        h = executor.launch_single(q)
+        while not executor.done(h):
+            idle()
+        t = clock() - t0
+        executor.finish(h)
+        rep.finish[q.qid] = t
+        rep.latency[q.qid] = t - q.arrival
+        rep.service[q.qid] = t - start
+    rep.wall = clock() - t0
+    return rep
+
+
+class GpuExecutor:
+    """Runs batches with pt_batch on `slots` streams and single queries with
+    pt_transfer. Each slot owns a workspace arena of `arena_bytes` allocated
+    once (a batch's workspace is a prefix of its slot's arena; serve with
+    batch_bytes <= arena_bytes), and single queries share one more arena, so
+    the loop itself allocates nothing but the queries' bitmaps. Keeps every
+    query's bitmaps and counts when `keep`."""
+
+    def __init__(self, resident: ResidentStar, params=None, slots: int = 2, keep: bool = False,
+                 arena_bytes: int = 1 << 30, single_arena_bytes: int = 0):
+        import torch
+        from . import pt
+        self.torch, self.pt = torch, pt
+        self.resident = resident
+        self.params = params if params is not None else pt.params()
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.single_stream = torch.cuda.Stream()
+        self.arenas = [torch.empty(arena_bytes, dtype=torch.uint8, device="cuda") for _ in range(slots)]
+        self.single_arena = (torch.empty(single_arena_bytes, dtype=torch.uint8, device="cuda")
+                             if single_arena_bytes else None)
+        self.keep = keep
+        self.results: dict[int, tuple[list, object]] = {}
+        self._dp_cache: dict[int, object] = {}
+
+    def device_problem(self, q: Query):
+        dp = self._dp_cache.get(q.qid)
+        if dp is None:
+            prob, dev = self.resident.problem(q)
+            dp = self.pt.DeviceProblem(prob, columns=dev)
+            self._dp_cache[q.qid] = dp
+        return dp
+
+    def single_need(self, q: Query) -> int:
+        """Workspace pt_transfer needs for the query alone."""
+        return self.pt.pt_transfer_workspace_size(self.device_problem(q), self.params)
+
+    def mem_need(self, q: Query) -> int:
+        dp = self.device_problem(q)
+        ws = self.pt.pt_batch_workspace_size([dp], [self.params])
+        bitmaps = sum(8 * self.pt.bitmap_words(n) for n in dp.n_rows) + 8 * dp.n_tables
+        return ws + bitmaps
+
+    def launch(self, qs: list[Query], slot: int):
+        torch = self.torch
+        s = self.streams[slot]
+        dps = [self.device_problem(q) for q in qs]
+        with torch.cuda.stream(s):
+            bt = self.pt.Batch(dps, [self.params] * len(dps), stream=s, ws=self.arenas[slot])
+            bt.run(stream=s, eager=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return ("batch", bt, ev, qs)
+
+    def launch_single(self, q: Query):
+        torch = self.torch
+        s = self.single_stream
+        with torch.cuda.stream(s):
+            tr = self.pt.Transfer(self.device_problem(q), self.params, ws=self.single_arena)
+            tr.run(stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return ("single", tr, ev, [q])
+
+    def done(self, h) -> bool:
+        return h[2].query()
+
+    def finish(self, h) -> None:
+        kind, obj, _, qs = h
+        if self.keep:
+            if kind == "batch":
+                for i, q in enumerate(qs):
+                    self.results[q.qid] = ([b.clone() for b in obj.bitmaps[i]], obj.counts[i].clone())
+            else:
+                self.results[qs[0].qid] = ([b.clone() for b in obj.bitmaps], obj.counts.clone())
+        if kind == "batch":
+            obj.close()
