@@ -55,8 +55,10 @@ const DeviceInfo &device_info();
 // transformation scans the table once). Region r belongs to wave r of the
 // probe grid and holds, in its first counts[r] slots, the keys of the rows
 // that survived in that wave's word groups (groups r, r + n_regions, ... of
-// group_words words). A region whose survivors exceed region_cap keeps only
-// its count; builds walk that region's bitmap words instead.
+// group_words words). A region whose survivors exceed region_cap, or with a
+// word group of more than 64 survivors of the probe's first filter, is
+// marked by a count above region_cap; builds walk that region's bitmap words
+// instead.
 constexpr int kMaxAppend = 4;
 struct AppendSet {
   uint32_t n_cols = 0;         // 0: nothing appended

@@ -512,28 +512,10 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe],
     }
 
     if (APPEND && !appended && total > 0) {
-      // Many survivors: append word by word while the region has room (a
-      // full region is walked by the builds; only its count matters).
-      const uint64_t below = (1ull << lane) - 1;
-#pragma unroll
-      for (int u = 0; u < U; u++) {
-        if (app_n < app.region_cap) {
-          const uint32_t pos = app_n + static_cast<uint32_t>(__popcll(m0[u] & below));
-          if (((m0[u] >> lane) & 1) && pos < app.region_cap) {
-            uint32_t klo[kMaxProbe], khi[kMaxProbe];
-#pragma unroll
-            for (int q = 0; q < kMaxProbe; q++) {
-              klo[q] = lo[q][u];
-              khi[q] = ANY64 ? hi[ANY64 ? q : 0][u] : 0;
-            }
-            const uint64_t row = base_row + static_cast<uint64_t>(u) * 64 + lane;
-#pragma unroll
-            for (int c = 0; c < kMaxAppend; c++)
-              if (c < static_cast<int>(app.n_cols)) append_key<ANY64>(app, c, app_slot[c], klo, khi, row, app_base + pos);
-          }
-        }
-        app_n += static_cast<uint32_t>(__popcll(m0[u]));
-      }
+      // Too many first-filter survivors to compact (or a full region): the
+      // region is marked as overflowed, and builds walk its bitmap words
+      // (dense survivors read coalesced anyway).
+      app_n = app.region_cap + 1;
     }
 
 #pragma unroll
