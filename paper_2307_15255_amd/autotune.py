@@ -14,7 +14,6 @@ from __future__ import annotations
 
 import json
 import math
-import time
 from dataclasses import dataclass, field
 
 import torch
@@ -42,24 +41,25 @@ def blocked_fpr(block_bits: int, k: int, bits_per_key: float) -> float:
     return total
 
 
+SIZE_CLASSES = (20_000, 400_000, 4_000_000)  # filter keys the costs are measured at
+
+
 @dataclass
 class CostTable:
-    """Measured nanoseconds per probed row and per inserted key, by (B, k)
-    and by where the probe's filters live (LDS or global memory)."""
-    probe_lds: dict = field(default_factory=dict)
-    probe_global: dict = field(default_factory=dict)
-    build: dict = field(default_factory=dict)
+    """Measured nanoseconds per probed row and per inserted key, by filter
+    size class (keys) and setting (B, k, bits per key)."""
+    probe: dict = field(default_factory=dict)   # (size, B, k, bpk) -> ns per probed row
+    build: dict = field(default_factory=dict)   # (size, B, k, bpk) -> ns per inserted key
 
     def to_json(self) -> str:
-        enc = lambda d: {f"{b},{k}": v for (b, k), v in d.items()}
-        return json.dumps({"probe_lds": enc(self.probe_lds), "probe_global": enc(self.probe_global),
-                           "build": enc(self.build)})
+        enc = lambda d: {",".join(map(str, key)): v for key, v in d.items()}
+        return json.dumps({"probe": enc(self.probe), "build": enc(self.build)})
 
     @staticmethod
     def from_json(text: str) -> "CostTable":
         raw = json.loads(text)
         dec = lambda d: {tuple(int(x) for x in key.split(",")): v for key, v in d.items()}
-        return CostTable(dec(raw["probe_lds"]), dec(raw["probe_global"]), dec(raw["build"]))
+        return CostTable(dec(raw["probe"]), dec(raw["build"]))
 
 
 def _time_ms(fn, reps: int = 5) -> float:
@@ -76,77 +76,96 @@ def _time_ms(fn, reps: int = 5) -> float:
     return best
 
 
-def measure(n_rows: int = 1 << 24, small_keys: int = 20_000, large_keys: int = 2_000_000,
+def candidates(fpr_cap: float) -> list[tuple[int, int, int]]:
+    """For every (B, k): the fewest bits per key whose false-positive rate
+    is within the cap (more bits only make the filter larger)."""
+    out = []
+    for B in BLOCK_BITS:
+        for k in HASHES:
+            for bpk in BITS_PER_KEY:
+                if blocked_fpr(B, k, bpk) <= fpr_cap:
+                    out.append((B, k, bpk))
+                    break
+    return out
+
+
+def measure(fpr_cap: float = 0.02, sizes: tuple[int, ...] = SIZE_CLASSES, n_rows: int = 1 << 24,
             device: str = "cuda") -> CostTable:
-    """Times pt_bloom_build and pt_bloom_probe for every (B, k): a probe of
-    n_rows int32 keys against a filter of small_keys keys (held in LDS) and
-    one of large_keys keys (read from L2 / HBM), and a build of large_keys
-    keys."""
+    """Times pt_bloom_probe (n_rows int32 keys) and pt_bloom_build for every
+    candidate setting with filters of each size class: the filter's size
+    decides whether it is read from LDS, L2 or beyond, so each size is
+    measured."""
     from . import pt
     g = torch.Generator(device=device).manual_seed(7)
     probe_keys = torch.randint(0, 1 << 30, (n_rows,), dtype=torch.int32, device=device, generator=g)
     bitmap = torch.empty(pt.bitmap_words(n_rows), dtype=torch.int64, device=device)
     count = torch.zeros(1, dtype=torch.int64, device=device)
     out = CostTable()
-    for B in BLOCK_BITS:
-        for k in HASHES:
-            p = pt.params(B, k, 10)
-            for keys_n, table in ((small_keys, out.probe_lds), (large_keys, out.probe_global)):
-                keys = probe_keys[:keys_n].contiguous()
-                f = pt.Bloom(keys_n, p, device)
-                pt.pt_bloom_build([keys], [f], keys_n)
+    fill = _time_ms(lambda: bitmap.fill_(-1))
+    for size in sizes:
+        keys = probe_keys[:size].contiguous()
+        for B, k, bpk in candidates(fpr_cap):
+            f = pt.Bloom(size, pt.params(B, k, bpk), device)
+            pt.pt_bloom_build([keys], [f], size)
 
-                def probe():
-                    bitmap.fill_(-1)
-                    pt.pt_bloom_probe([probe_keys], [f], n_rows, bitmap, count)
-                fill = _time_ms(lambda: bitmap.fill_(-1))
-                table[(B, k)] = max(0.0, _time_ms(probe) - fill) * 1e6 / n_rows
-            keys = probe_keys[:large_keys].contiguous()
-            f = pt.Bloom(large_keys, p, device)
-            out.build[(B, k)] = _time_ms(lambda: pt.pt_bloom_build([keys], [f], large_keys)) * 1e6 / large_keys
+            def probe():
+                bitmap.fill_(-1)
+                pt.pt_bloom_probe([probe_keys], [f], n_rows, bitmap, count)
+            out.probe[(size, B, k, bpk)] = max(0.0, _time_ms(probe) - fill) * 1e6 / n_rows
+            out.build[(size, B, k, bpk)] = _time_ms(lambda: pt.pt_bloom_build([keys], [f], size)) * 1e6 / size
     return out
 
 
-# LDS words a probe may stage its filters in (a little under 160 KB).
-LDS_WORDS = 36_000
+def modelled_ms(problem, costs: CostTable, setting: tuple[int, int, int]) -> float:
+    """Modelled time of `problem` with `setting`, from the costs at the
+    size class nearest (in log scale) to the problem's median table. Every
+    edge is probed once per pass at each end's table and built from the
+    other end's rows."""
+    n = sorted(problem.n_rows(t) for t in range(problem.n_tables))
+    median = max(1, n[len(n) // 2])
+    sizes = sorted({key[0] for key in costs.probe})
+    if not sizes:
+        raise ValueError("empty cost table")
+    size = min(sizes, key=lambda c: abs(math.log(c) - math.log(median)))
+    rows = [problem.n_rows(t) for t in range(problem.n_tables)]
+    work = sum(rows[u] + rows[v] for u, _, v, _ in problem.edges)
+    key = (size, *setting)
+    return work * (costs.probe[key] + costs.build[key]) * 1e-6
 
 
 def choose(problem, costs: CostTable, fpr_cap: float = 0.02):
     """(block_bits, k, bits_per_key) for one problem (`workloads.Problem`):
-    the cheapest modelled setting with blocked_fpr <= fpr_cap."""
-    n = [problem.n_rows(t) for t in range(problem.n_tables)]
-    # Work of the schedule, from the shape only: every edge is probed once
-    # per pass at each end's table and built from the other end's rows.
-    probe_rows, build_keys, max_filter_keys = 0, 0, 0
-    for u, _, v, _ in problem.edges:
-        probe_rows += n[u] + n[v]
-        build_keys += n[u] + n[v]
-        max_filter_keys = max(max_filter_keys, min(n[u], n[v]))
+    the measured setting (all within fpr_cap) with the lowest modelled time,
+    using the costs measured at the size class nearest (in log scale) to the
+    problem's median table. Model: every edge is probed once per pass at
+    each end's table and built from the other end's rows."""
+    n = sorted(problem.n_rows(t) for t in range(problem.n_tables))
+    median = max(1, n[len(n) // 2])
+    sizes = sorted({key[0] for key in costs.probe})
+    if not sizes:
+        raise ValueError("empty cost table")
+    size = min(sizes, key=lambda c: abs(math.log(c) - math.log(median)))
+    rows = [problem.n_rows(t) for t in range(problem.n_tables)]
+    work = sum(rows[u] + rows[v] for u, _, v, _ in problem.edges)
     best = None
-    for B in BLOCK_BITS:
-        for k in HASHES:
-            for bpk in BITS_PER_KEY:
-                fpr = blocked_fpr(B, k, bpk)
-                if fpr > fpr_cap:
-                    continue
-                words = max_filter_keys * bpk / 32
-                probe = costs.probe_lds if words <= LDS_WORDS else costs.probe_global
-                t = probe_rows * probe[(B, k)] + build_keys * costs.build[(B, k)]
-                # more bits per key only costs filter memory: prefer fewer on ties
-                key = (round(t, 3), bpk, fpr)
-                if best is None or key < best[0]:
-                    best = (key, (B, k, bpk))
-    if best is None:
-        raise ValueError(f"no setting reaches a false-positive rate of {fpr_cap}")
+    for key in sorted(k for k in costs.probe if k[0] == size):
+        t = work * (costs.probe[key] + costs.build[key])
+        if best is None or t < best[0]:
+            best = (t, key[1:])
     return best[1]
 
 
 def tune(problems, costs: CostTable | None = None, fpr_cap: float = 0.02):
-    """pt_params for every problem (measuring the cost table first when none
-    is given) and the table used."""
+    """pt_params for every problem and the cost table used (measured first
+    when none is given)."""
     from . import pt
     if costs is None:
-        t0 = time.time()
-        costs = measure()
-        costs.seconds = time.time() - t0
-    return [pt.params(*choose(p, costs, fpr_cap)) for p in problems], costs
+        costs = measure(fpr_cap=fpr_cap)
+    picks = [choose(p, costs, fpr_cap) for p in problems]
+    # Settings that differ in B or k run in separate launches of a batch: a
+    # problem takes the most common setting when it costs at most 3 % more.
+    if picks:
+        common = max(set(picks), key=picks.count)
+        picks = [common if modelled_ms(p, costs, common) <= 1.03 * modelled_ms(p, costs, c) else c
+                 for p, c in zip(problems, picks)]
+    return [pt.params(*c) for c in picks], costs
