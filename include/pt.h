@@ -71,8 +71,23 @@ typedef enum pt_status {
   PT_EINVAL = 1,       /* an argument was rejected; nothing was queued */
   PT_ENOMEM = 2,       /* a caller-provided workspace is too small */
   PT_EDEVICE = 3,      /* a HIP call or kernel launch failed */
-  PT_EUNSUPPORTED = 4  /* a valid request this build does not implement */
+  PT_EUNSUPPORTED = 4, /* a valid request this build does not implement */
+  PT_EOVERFLOW = 5     /* pt_check_status: a kernel found a size above a capacity */
 } pt_status;
+
+/* Device status word. Kernels OR these bits into a call's status word (a
+ * device uint32) when a size read on the device exceeds the room the host
+ * set aside; the kernel then clamps and carries on, so nothing is written
+ * out of bounds, but the result no longer follows the filter specification.
+ * The checks on the host make both impossible inside pt_transfer and the
+ * batches; they catch wrong counts or block counts handed to the primitives.
+ *   FILTER_OVERFLOW   a filter needed more blocks than cap_words holds, or a
+ *                     block count read from d_nb exceeded it (clamped)
+ *   ENTRIES_OVERFLOW  a partitioned build met more keys than its count
+ *                     said (the extra keys were not inserted)
+ * pt_check_status() reads and clears the word. */
+#define PT_STATUS_FILTER_OVERFLOW 1u
+#define PT_STATUS_ENTRIES_OVERFLOW 2u
 
 typedef enum pt_dtype { PT_I32 = 0, PT_I64 = 1 } pt_dtype;
 
@@ -97,9 +112,12 @@ typedef struct pt_table {
 } pt_table;
 
 /* One inner equi-join tables[u].cols[u_col] = tables[v].cols[v_col]
- * (Sec. 3.1). A composite key is several edges between the same tables. */
+ * (Sec. 3.1). A composite key is several edges between the same tables.
+ * flags: 0 (an inner join); other values are reserved for outer joins
+ * (Sec. 3.4) and rejected with PT_EUNSUPPORTED. */
 typedef struct pt_edge {
   uint32_t u, u_col, v, v_col;
+  uint32_t flags;
 } pt_edge;
 
 /* The join graph. `orient` is NULL for the paper's rule (Sec. 3.2: each edge
@@ -128,13 +146,32 @@ typedef struct pt_pred {
   int64_t lo, hi;
 } pt_pred;
 
-/* Filter parameters, one set for every filter of a call. */
+/* Filter parameters, one set for every filter of a call. The first three
+ * fix the filter bits (with the hash version); the rest only change how the
+ * work is laid out on the device, never a bit of any result.
+ *   hash_version  0 or 1: the filter specification above (PTSPEC-1); other
+ *                 values are rejected with PT_EUNSUPPORTED
+ *   lds_budget    bytes of LDS a probe workgroup may stage filters in
+ *                 (0: as much as the device allows); filters that do not
+ *                 fit together are read from global memory
+ *   tile_rows     rows one workgroup of a batch takes per work item: 0 for
+ *                 65 536, else a multiple of 4 096 up to 2^24
+ *   probe_order   PT_PROBE_SELECTIVE (0): the filter whose builder kept the
+ *                 smallest share of its rows is tested first;
+ *                 PT_PROBE_GIVEN (1): in edge order */
 typedef struct pt_params {
   uint32_t block_bits;   /* B: 32, 64, 128, 256, 512 or 1024 */
   uint32_t k;            /* 1..16 */
   uint32_t bits_per_key; /* 1..64 */
   uint32_t flags;        /* 0 or PT_FLAG_NO_APPEND */
+  uint32_t hash_version;
+  uint32_t lds_budget;
+  uint32_t tile_rows;
+  uint32_t probe_order;
 } pt_params;
+
+#define PT_PROBE_SELECTIVE 0u
+#define PT_PROBE_GIVEN 1u
 
 /* pt_transfer normally appends the keys of a probe's surviving rows while it
  * scans the table, so that the filters the table then builds read those keys
@@ -145,11 +182,14 @@ typedef struct pt_params {
 
 /* A Bloom filter in device memory. `words` holds cap_words uint32 words; the
  * filter in use is its first nb * B/32 words, where nb is the uint64 at
- * device address `d_nb` (written by pt_bloom_build). */
+ * device address `d_nb` (written by pt_bloom_build). `d_status` is NULL or
+ * a device uint32 status word (PT_STATUS_* bits) that builds and probes of
+ * this filter report into; pt_check_status reads it. */
 typedef struct pt_bloom {
   uint32_t *words;
   uint64_t cap_words;
   uint64_t *d_nb;
+  uint32_t *d_status;
   pt_params params;
 } pt_bloom;
 
@@ -166,6 +206,16 @@ typedef struct pt_kernel_time {
 
 /* Library version string. */
 const char *pt_version(void);
+
+/* Waits for `stream`, then reads and clears the device status word
+ * d_status: a pt_bloom's d_status, or the workspace of pt_transfer or of a
+ * batch (its first 4 bytes hold the status of the latest call on it, see
+ * the PT_STATUS_* bits above). Returns PT_OK when no bit is set,
+ * PT_EOVERFLOW otherwise (pt_last_error names the bits), PT_EINVAL for a
+ * NULL pointer, PT_EDEVICE if the copy fails. The paper's schedule ends
+ * with every table reduced (Sec. 3.2); this call tells whether the reduced
+ * tables are the ones the specification defines. */
+pt_status pt_check_status(const void *d_status, pt_stream stream);
 
 /* Message of the calling thread's last failed call ("" if none). */
 const char *pt_last_error(void);

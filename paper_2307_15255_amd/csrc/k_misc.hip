@@ -1,0 +1,350 @@
+// k_misc.hip - the small steps of the transfer phase: local filters (Sec.
+// 3.2: inherent filters applied during the scan; Sec. 3.4: predicates on
+// base tables), filter sizing, ordered compaction (the reduced row sets
+// handed to the join phase, Sec. 3.3), counters, and the launch helpers the
+// other kernel units share.
+#include <map>
+#include <mutex>
+
+#include "build_impl.hpp"
+
+namespace pt {
+
+namespace {
+
+__global__ void __launch_bounds__(kThreads) k_zero_u64(uint64_t *p, uint64_t n) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    p[i] = 0;
+}
+
+// All rows selected: the bitmap of a table without predicates.
+__global__ void __launch_bounds__(kThreads) k_fill_all(uint64_t *bitmap, uint64_t n_rows, uint64_t *count) {
+  const uint64_t n_words = (n_rows + 63) / 64;
+  for (uint64_t w = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; w < n_words;
+       w += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    bitmap[w] = tail_mask(w, n_words, n_rows);
+  if (count && blockIdx.x == 0 && threadIdx.x == 0) *count = n_rows;
+}
+
+// ---------------------------------------------------------- local filter
+//
+// Each wave takes seg_words (1..64) consecutive words, builds word j with the
+// ballot of step j, keeps it in lane j, and stores the segment with one
+// coalesced store. Eight words are evaluated per step so their loads
+// overlap.
+
+__device__ __forceinline__ bool pred_holds(uint32_t op, int64_t v, int64_t lo, int64_t hi) {
+  switch (op) {
+    case PT_LT: return v < lo;
+    case PT_LE: return v <= lo;
+    case PT_GT: return v > lo;
+    case PT_GE: return v >= lo;
+    case PT_EQ: return v == lo;
+    case PT_NE: return v != lo;
+    default: return lo <= v && v <= hi;
+  }
+}
+
+__device__ __forceinline__ void local_body(const PredSet &ps, uint64_t n_rows, uint64_t *__restrict__ bitmap,
+                                           unsigned long long *count, uint32_t seg_words, const VGrid &vg) {
+  constexpr int T = 8;
+  __shared__ unsigned long long s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const uint32_t lane = lane_id();
+  const uint64_t n_words = (n_rows + 63) / 64;
+  uint64_t cnt = 0;
+  for (uint64_t seg = global_wave(vg); seg * seg_words < n_words; seg += wave_count(vg)) {
+    const uint64_t w_base = seg * seg_words;
+    const uint32_t n_j = static_cast<uint32_t>(n_words - w_base < seg_words ? n_words - w_base : seg_words);
+    uint64_t mine = 0;
+    for (uint32_t j0 = 0; j0 < n_j; j0 += T) {
+      bool keep[T];
+      uint64_t r[T];
+#pragma unroll
+      for (int t = 0; t < T; t++) {
+        const uint64_t row = (w_base + j0 + t) * 64 + lane;
+        keep[t] = j0 + t < n_j && row < n_rows;
+        r[t] = row < n_rows ? row : n_rows - 1;
+        if (ps.and_into && j0 + t < n_j) keep[t] = keep[t] && ((uniform64(bitmap[w_base + j0 + t]) >> lane) & 1);
+      }
+      for (uint32_t i = 0; i < ps.n; i++) {
+        const PredRef &p = ps.p[i];
+#pragma unroll
+        for (int t = 0; t < T; t++) {
+          const int64_t v = static_cast<int64_t>(load_key(p.col, p.col64, r[t]));
+          keep[t] = keep[t] && pred_holds(p.op, v, p.lo, p.hi);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < T; t++) {
+        const uint64_t m = __ballot(keep[t]);
+        if (lane == j0 + t) mine = m;
+      }
+    }
+    if (lane < n_j) bitmap[w_base + lane] = mine;
+    cnt += __popcll(mine);
+  }
+  block_count_add(static_cast<int64_t>(wave_sum(cnt)), &s_cnt, count);
+}
+
+__global__ void __launch_bounds__(kWideThreads)
+    k_local(PredSet ps, uint64_t n_rows, uint64_t *__restrict__ bitmap, unsigned long long *count,
+            uint32_t seg_words) {
+  local_body(ps, n_rows, bitmap, count, seg_words, whole_grid());
+}
+
+__global__ void __launch_bounds__(kBatchThreads)
+    k_local_batch(const LocalTask *__restrict__ tasks, const uint32_t *__restrict__ first, uint32_t n) {
+  VGrid vg;
+  const LocalTask &t = tasks[task_of(first, n, vg)];
+  local_body(t.ps, t.n_rows, t.bitmap, reinterpret_cast<unsigned long long *>(t.count), t.seg_words, vg);
+}
+
+// --------------------------------------------------------- size and zero
+//
+// Filter i (blockIdx.y) gets nb = max(1, ceil(count * bits_per_key / B))
+// blocks, read from the device counter so the launch sequence never waits
+// for the host. Its first nb blocks are zeroed unless the partitioned build
+// (which writes every block) will run.
+
+__global__ void __launch_bounds__(kThreads)
+    k_size_zero(FilterSet fs, uint32_t lg, uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
+                uint64_t entries_cap, uint32_t *status) {
+  const FilterRef &f = fs.f[blockIdx.y];
+  const uint64_t W = 1u << (lg - 5);
+  const uint64_t nb = blocks_needed(count ? *count : n_rows, 1u << lg, bits_per_key, f.cap_words / W,
+                                    blockIdx.x == 0 && threadIdx.x == 0 ? status : nullptr);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *f.nb = nb;
+  if (entries_cap && part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, true).ok) return;
+  const uint64_t n = nb * W;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    f.words[i] = 0;
+}
+
+__global__ void __launch_bounds__(kBatchThreads)
+    k_size_batch(const SizeTask *__restrict__ tasks, const uint32_t *__restrict__ first, uint32_t n,
+                 uint32_t *status) {
+  VGrid vg;
+  const SizeTask &t = tasks[task_of(first, n, vg)];
+  const uint64_t W = t.block_bits / 32;
+  const bool lead = vg.block == 0 && threadIdx.x == 0;
+  const uint64_t nb = blocks_needed(t.count ? *t.count : t.n_rows, t.block_bits, t.bits_per_key, t.f.cap_words / W,
+                                    lead ? status : nullptr);
+  if (lead) *t.f.nb = nb;
+  const uint64_t words = nb * W;
+  for (uint64_t i = static_cast<uint64_t>(vg.block) * blockDim.x + threadIdx.x; i < words;
+       i += static_cast<uint64_t>(vg.blocks) * blockDim.x)
+    t.f.words[i] = 0;
+}
+
+// ------------------------------------------------------------- counters
+
+struct SlotTable {
+  uint32_t slot[64];
+};
+
+__global__ void k_copy_counts(const uint64_t *src, SlotTable t, uint32_t n, uint64_t *dst) {
+  const uint32_t i = threadIdx.x;
+  if (i < n) dst[i] = src[t.slot[i]];
+}
+
+__global__ void k_copy_pairs(const CopyPair *__restrict__ pairs, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) *pairs[i].dst = *pairs[i].src;
+}
+
+// -------------------------------------------------------------- compact
+//
+// Ordered compaction in three steps: per-workgroup popcounts of 1024 bitmap
+// words, one exclusive scan over the workgroup totals, then each workgroup
+// rescans its words and writes the set rows' ids in ascending order.
+
+constexpr uint64_t kCompactWordsPerBlock = 1024;  // 4 words per thread
+
+__global__ void __launch_bounds__(kThreads)
+    k_compact_count(const uint64_t *__restrict__ bitmap, uint64_t n_words, uint64_t n_rows, uint64_t *partials) {
+  __shared__ unsigned long long s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const uint64_t base = blockIdx.x * kCompactWordsPerBlock + threadIdx.x * 4;
+  uint64_t c = 0;
+#pragma unroll
+  for (int j = 0; j < 4; j++)
+    if (base + j < n_words) c += __popcll(bitmap[base + j] & tail_mask(base + j, n_words, n_rows));
+  atomicAdd(&s_cnt, static_cast<unsigned long long>(c));
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = s_cnt;
+}
+
+__global__ void __launch_bounds__(1024) k_compact_scan(uint64_t *partials, uint64_t n_parts, uint64_t *count) {
+  __shared__ uint64_t s[1024];
+  uint64_t carry = 0;
+  for (uint64_t base = 0; base < n_parts; base += blockDim.x) {
+    const uint64_t i = base + threadIdx.x;
+    const uint64_t v = i < n_parts ? partials[i] : 0;
+    uint64_t total;
+    const uint64_t ex = block_exclusive_scan(v, s, total);
+    if (i < n_parts) partials[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) *count = carry;
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_compact_write(const uint64_t *__restrict__ bitmap, uint64_t n_words, uint64_t n_rows,
+                    const uint64_t *partials, uint32_t *__restrict__ idx) {
+  __shared__ uint64_t s[kThreads];
+  const uint64_t base = blockIdx.x * kCompactWordsPerBlock + threadIdx.x * 4;
+  uint64_t words[4];
+  uint64_t c = 0;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    words[j] = base + j < n_words ? bitmap[base + j] & tail_mask(base + j, n_words, n_rows) : 0;
+    c += __popcll(words[j]);
+  }
+  uint64_t total;
+  uint64_t pos = partials[blockIdx.x] + block_exclusive_scan(c, s, total);
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    uint64_t m = words[j];
+    while (m) {
+      const uint32_t b = __ffsll(static_cast<unsigned long long>(m)) - 1;
+      idx[pos++] = static_cast<uint32_t>((base + j) * 64 + b);
+      m &= m - 1;
+    }
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- helpers
+
+hipError_t allow_lds(const void *kern, uint64_t bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void *>, uint64_t> granted;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  uint64_t &g = granted[{dev, kern}];
+  if (bytes <= g) return hipSuccess;
+  const uint64_t want = static_cast<uint64_t>(device_info().max_lds_block) - 1024;
+  hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     static_cast<int>(bytes > want ? bytes : want));
+  if (e == hipSuccess) g = bytes > want ? bytes : want;
+  return e;
+}
+
+uint32_t segment_words(uint64_t n_words) {
+  const uint64_t target_waves = static_cast<uint64_t>(device_info().n_cu) * 32;
+  uint64_t seg = (n_words + target_waves - 1) / target_waves;
+  return static_cast<uint32_t>(seg < 1 ? 1 : (seg > 64 ? 64 : seg));
+}
+
+uint32_t grid_for(uint64_t waves_of_work, uint32_t threads, uint32_t per_cu) {
+  const uint64_t blocks = (waves_of_work * kWave + threads - 1) / threads;
+  const uint64_t cap = static_cast<uint64_t>(device_info().n_cu) * per_cu;
+  const uint64_t g = blocks < cap ? blocks : cap;
+  return static_cast<uint32_t>(g == 0 ? 1 : g);
+}
+
+// ------------------------------------------------------------ launchers
+
+hipError_t launch_zero_u64(uint64_t *p, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t grid = grid_for((n + 63) / 64, kThreads, 4);
+  hipLaunchKernelGGL(k_zero_u64, dim3(grid), dim3(kThreads), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_all(uint64_t *bitmap, uint64_t n_rows, uint64_t *count, hipStream_t s) {
+  const uint64_t n_words = (n_rows + 63) / 64;
+  const uint32_t grid = grid_for((n_words + 63) / 64, kThreads, 8);
+  hipLaunchKernelGGL(k_fill_all, dim3(grid), dim3(kThreads), 0, s, n_words ? bitmap : nullptr, n_rows, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_local_filter(const PredSet &preds, uint64_t n_rows, uint64_t *bitmap, uint64_t *count,
+                               hipStream_t s) {
+  const uint64_t n_words = (n_rows + 63) / 64;
+  if (n_words == 0) return hipSuccess;
+  const uint32_t seg_words = segment_words(n_words);
+  const uint32_t grid = grid_for((n_words + seg_words - 1) / seg_words, kWideThreads, 1);
+  hipLaunchKernelGGL(k_local, dim3(grid), dim3(kWideThreads), 0, s, preds, n_rows, bitmap,
+                     reinterpret_cast<unsigned long long *>(count), seg_words);
+  return hipGetLastError();
+}
+
+hipError_t launch_size(uint32_t block_bits, uint32_t bits_per_key, const FilterSet &fs, const uint64_t *count,
+                       uint64_t n_rows, uint64_t entries_cap, uint32_t *status, hipStream_t s) {
+  if (fs.n == 0) return hipSuccess;
+  const uint32_t lg = log2_of(static_cast<int>(block_bits));
+  if (lg == 0) return hipErrorInvalidValue;
+  uint64_t max_cap_words = 0;
+  for (uint32_t i = 0; i < fs.n; i++) max_cap_words = fs.f[i].cap_words > max_cap_words ? fs.f[i].cap_words : max_cap_words;
+  uint64_t gx = (max_cap_words + kThreads * 4 - 1) / (kThreads * 4);
+  const uint64_t cap = static_cast<uint64_t>(device_info().n_cu) * 2;
+  gx = gx > cap ? cap : (gx == 0 ? 1 : gx);
+  hipLaunchKernelGGL(k_size_zero, dim3(static_cast<uint32_t>(gx), fs.n), dim3(kThreads), 0, s, fs, lg, bits_per_key,
+                     count, n_rows, entries_cap, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_counts(const uint64_t *src, const uint32_t *slot, uint32_t n, uint64_t *dst, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  SlotTable t{};
+  for (uint32_t i = 0; i < n && i < 64; i++) t.slot[i] = slot[i];
+  hipLaunchKernelGGL(k_copy_counts, dim3(1), dim3(64), 0, s, src, t, n, dst);
+  return hipGetLastError();
+}
+
+uint64_t compact_partials(uint64_t n_rows) {
+  const uint64_t n_words = (n_rows + 63) / 64;
+  return (n_words + kCompactWordsPerBlock - 1) / kCompactWordsPerBlock;
+}
+
+hipError_t launch_compact(const uint64_t *bitmap, uint64_t n_rows, uint32_t *idx, uint64_t *count,
+                          uint64_t *partials, hipStream_t s) {
+  const uint64_t n_words = (n_rows + 63) / 64;
+  const uint64_t n_parts = compact_partials(n_rows);
+  if (n_parts == 0) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, count, 1);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_compact_count, dim3(static_cast<uint32_t>(n_parts)), dim3(kThreads), 0, s, bitmap, n_words,
+                     n_rows, partials);
+  hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, partials, n_parts, count);
+  hipLaunchKernelGGL(k_compact_write, dim3(static_cast<uint32_t>(n_parts)), dim3(kThreads), 0, s, bitmap, n_words,
+                     n_rows, partials, idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_local_batch(const LocalTask *tasks, const uint32_t *first, uint32_t n, uint32_t grid,
+                              hipStream_t s) {
+  if (n == 0 || grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_local_batch, dim3(grid), dim3(kBatchThreads), 0, s, tasks, first, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_size_batch(const SizeTask *tasks, const uint32_t *first, uint32_t n, uint32_t grid,
+                             uint32_t *status, hipStream_t s) {
+  if (n == 0 || grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_size_batch, dim3(grid), dim3(kBatchThreads), 0, s, tasks, first, n, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_pairs(const CopyPair *pairs, uint32_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_pairs, dim3((n + 255) / 256), dim3(256), 0, s, pairs, n);
+  return hipGetLastError();
+}
+
+hipError_t prepare_batch_kernels(uint32_t block_bits, uint32_t k, bool any64) {
+  hipError_t e = prepare_build_batch_kernel(block_bits, k);
+  if (e != hipSuccess) return e;
+  return prepare_probe_batch_kernel(block_bits, k, any64);
+}
+
+}  // namespace pt

@@ -13,7 +13,6 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pt.h"
 #include "pt_internal.hpp"
 
 namespace pt {
@@ -127,7 +126,25 @@ pt_status check_params(const pt_params *p) {
   if (p->bits_per_key < 1 || p->bits_per_key > 64)
     return fail(PT_EINVAL, "bits_per_key %u outside [1, 64]", p->bits_per_key);
   if ((p->flags & ~PT_FLAG_NO_APPEND) != 0) return fail(PT_EINVAL, "params.flags: unknown bits 0x%x", p->flags);
+  if (p->hash_version > 1)
+    return fail(PT_EUNSUPPORTED, "hash_version %u (this library implements version 1)", p->hash_version);
+  if (p->tile_rows != 0 && (p->tile_rows % 4096 != 0 || p->tile_rows > (1u << 24)))
+    return fail(PT_EINVAL, "tile_rows %u is not 0 or a multiple of 4096 up to 2^24", p->tile_rows);
+  if (p->probe_order > PT_PROBE_GIVEN) return fail(PT_EINVAL, "probe_order %u", p->probe_order);
   return PT_OK;
+}
+
+// The parameters that fix the filter bits: equal for every filter of a call.
+bool same_filter(const pt_params &a, const pt_params &b) {
+  return a.block_bits == b.block_bits && a.k == b.k && a.bits_per_key == b.bits_per_key &&
+         (a.hash_version <= 1) == (b.hash_version <= 1);
+}
+
+ProbeOpts probe_opts(const pt_params &p) {
+  ProbeOpts o;
+  o.lds_budget = p.lds_budget;
+  o.keep_order = p.probe_order == PT_PROBE_GIVEN;
+  return o;
 }
 
 uint64_t blocks_for(uint64_t n_keys, const pt_params &p) {
@@ -163,8 +180,7 @@ pt_status check_filter(const pt_bloom &f, const pt_params &p0, uint64_t n_rows, 
   if (!f.words || !f.d_nb) return fail(PT_EINVAL, "filter %u: words or d_nb is NULL", i);
   pt_status st = check_params(&f.params);
   if (st != PT_OK) return st;
-  if (std::memcmp(&f.params, &p0, sizeof p0) != 0)
-    return fail(PT_EINVAL, "filter %u: parameters differ from filter 0", i);
+  if (!same_filter(f.params, p0)) return fail(PT_EINVAL, "filter %u: parameters differ from filter 0", i);
   const uint64_t need = capacity_words(n_rows, f.params);
   if (need / (f.params.block_bits / 32) > 0xFFFFFFFFull)
     return fail(PT_EINVAL, "filter %u: %llu blocks exceed 2^32 - 1", i,
@@ -299,6 +315,7 @@ pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *
     const pt_edge &ed = g->edges[e];
     if (ed.u >= pl.n_t || ed.v >= pl.n_t) return fail(PT_EINVAL, "edge %u: table out of range", e);
     if (ed.u == ed.v) return fail(PT_EINVAL, "edge %u joins table %u with itself", e, ed.u);
+    if (ed.flags != 0) return fail(PT_EUNSUPPORTED, "edge %u: flags 0x%x (only inner joins, flags = 0)", e, ed.flags);
     if (ed.u_col >= tables[ed.u].n_cols || ed.v_col >= tables[ed.v].n_cols)
       return fail(PT_EINVAL, "edge %u: column out of range", e);
     bool u_first;
@@ -430,6 +447,23 @@ const char *pt_version(void) { return "pt-mi355x 0.1 (gfx950)"; }
 
 const char *pt_last_error(void) { return g_error.c_str(); }
 
+pt_status pt_check_status(const void *d_status, pt_stream stream) {
+  if (!d_status) return fail(PT_EINVAL, "d_status is NULL");
+  static const uint32_t kZeroWord = 0;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  uint32_t word = 0;
+  pt_status st = check_hip(hipMemcpyAsync(&word, d_status, 4, hipMemcpyDeviceToHost, s), "status read");
+  if (st == PT_OK)
+    st = check_hip(hipMemcpyAsync(const_cast<void *>(d_status), &kZeroWord, 4, hipMemcpyHostToDevice, s),
+                   "status clear");
+  if (st == PT_OK) st = check_hip(hipStreamSynchronize(s), "status wait");
+  if (st != PT_OK) return st;
+  if (word == 0) return PT_OK;
+  return fail(PT_EOVERFLOW, "device status 0x%x:%s%s", word,
+              (word & PT_STATUS_FILTER_OVERFLOW) ? " a filter needed more blocks than its capacity (clamped)" : "",
+              (word & PT_STATUS_ENTRIES_OVERFLOW) ? " a partitioned build met more keys than its count" : "");
+}
+
 pt_status pt_profile_enable(int on) {
   if (on < 0 || on > 2) return fail(PT_EINVAL, "pt_profile_enable: mode %d", on);
   g_prof_mode = on;
@@ -504,7 +538,8 @@ pt_status pt_bloom_capacity(uint64_t max_keys, const pt_params *params, uint64_t
 static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
                                uint64_t n_rows, const uint64_t *d_bitmap, const uint64_t *d_count,
                                const BuildScratch *scratch, const AppendSet *app,
-                               const uint32_t *app_idx, hipStream_t s, uint32_t table, uint32_t pass) {
+                               const uint32_t *app_idx, uint32_t *status, hipStream_t s, uint32_t table,
+                               uint32_t pass) {
   const pt_params &p = filters[0].params;
   for (uint32_t done = 0; done < n_filters;) {
     FilterSet fs{};
@@ -516,7 +551,7 @@ static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const 
     }
     Timed tm("build", table, pass, n_rows, bytes, s);
     pt_status st = check_hip(launch_build(p.block_bits, p.k, p.bits_per_key, fs, n_rows, d_bitmap,
-                                          d_count, scratch, app, s),
+                                          d_count, scratch, app, status, s),
                              "build launch");
     if (st != PT_OK) return st;
   }
@@ -532,8 +567,8 @@ static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const 
 static pt_status probe_filters(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
                                const uint64_t *const *sel, const uint64_t *rows, uint64_t n_rows,
                                uint64_t *d_bitmap, uint64_t *d_count, bool input_all,
-                               bool count_zeroed, AppendSet *app, uint64_t capacity, hipStream_t s,
-                               uint32_t table, uint32_t pass) {
+                               bool count_zeroed, AppendSet *app, uint64_t capacity, uint32_t *status,
+                               hipStream_t s, uint32_t table, uint32_t pass) {
   const pt_params &p = filters[0].params;
   if (d_count && !count_zeroed) {
     pt_status st = check_hip(launch_zero_u64(d_count, 1, s), "zero count");
@@ -555,7 +590,7 @@ static pt_status probe_filters(uint32_t n_filters, const pt_column *keys, const 
     Timed tm("probe", table, pass, n_rows, bytes, s);
     pt_status st = check_hip(launch_probe(p.block_bits, p.k, fs, n_rows, d_bitmap,
                                           last ? d_count : nullptr, input_all && first,
-                                          last ? app : nullptr, capacity, s),
+                                          last ? app : nullptr, capacity, probe_opts(p), status, s),
                              "probe launch");
     if (st != PT_OK) return st;
   }
@@ -576,7 +611,8 @@ pt_status pt_bloom_build(uint32_t n_filters, const pt_column *keys, const pt_blo
     if (st != PT_OK) return st;
   }
   return build_filters(n_filters, keys, filters, n_rows, d_bitmap, d_bitmap ? d_count : nullptr,
-                       nullptr, nullptr, nullptr, reinterpret_cast<hipStream_t>(stream), 0, 0);
+                       nullptr, nullptr, nullptr, filters[0].d_status, reinterpret_cast<hipStream_t>(stream), 0,
+                       0);
 }
 
 pt_status pt_bloom_probe(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
@@ -593,7 +629,7 @@ pt_status pt_bloom_probe(uint32_t n_filters, const pt_column *keys, const pt_blo
     if (st != PT_OK) return st;
     if (filters[i].cap_words < filters[i].params.block_bits / 32)
       return fail(PT_EINVAL, "filter %u: cap_words below one block", i);
-    if (std::memcmp(&filters[i].params, &filters[0].params, sizeof(pt_params)) != 0)
+    if (!same_filter(filters[i].params, filters[0].params))
       return fail(PT_EINVAL, "filter %u: parameters differ from filter 0", i);
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -606,7 +642,7 @@ pt_status pt_bloom_probe(uint32_t n_filters, const pt_column *keys, const pt_blo
     return check_hip(launch_local_filter(ps, n_rows, d_bitmap, d_count, s), "count launch");
   }
   return probe_filters(n_filters, keys, filters, nullptr, nullptr, n_rows, d_bitmap, d_count, false,
-                       false, nullptr, 0, s, 0, 0);
+                       false, nullptr, 0, filters[0].d_status, s, 0, 0);
 }
 
 pt_status pt_compact_workspace_size(uint64_t n_rows, size_t *bytes) {
@@ -654,6 +690,7 @@ pt_status pt_transfer_filter(const pt_graph *graph, const pt_table *tables, cons
   out->words = reinterpret_cast<uint32_t *>(ws + pl.off_filter[slot]);
   out->cap_words = pl.cap_words[slot];
   out->d_nb = reinterpret_cast<uint64_t *>(ws + pl.off_nb) + slot;
+  out->d_status = reinterpret_cast<uint32_t *>(ws);
   out->params = *params;
   if (builder) *builder = pass == 1 ? pl.src[edge] : pl.dst[edge];
   return PT_OK;
@@ -679,18 +716,23 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
   char *ws = static_cast<char *>(d_ws);
   uint64_t *counts = reinterpret_cast<uint64_t *>(ws + pl.off_counts);
   uint64_t *nbs = reinterpret_cast<uint64_t *>(ws + pl.off_nb);
+  uint32_t *status = reinterpret_cast<uint32_t *>(ws);  // the call's status word
   auto bloom_at = [&](uint32_t slot) {
     pt_bloom b{};
     b.words = reinterpret_cast<uint32_t *>(ws + pl.off_filter[slot]);
     b.cap_words = pl.cap_words[slot];
     b.d_nb = nbs + slot;
+    b.d_status = status;
     b.params = *params;
     return b;
   };
 
   {
-    Timed tm("zero", 0, 0, 0, 3ull * pl.n_t * 8, s);
-    st = check_hip(launch_zero_u64(counts, 3ull * pl.n_t, s), "zero counters");
+    // the status word and the counters (everything before off_counts is
+    // the workspace header)
+    const uint64_t words = (pl.off_counts + 3ull * pl.n_t * 8) / 8;
+    Timed tm("zero", 0, 0, 0, words * 8, s);
+    st = check_hip(launch_zero_u64(reinterpret_cast<uint64_t *>(ws), words, s), "zero counters");
     if (st != PT_OK) return st;
   }
 
@@ -789,7 +831,7 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
         st = probe_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), sel.data(),
                            rows.data(), tb.n_rows, d_bitmaps[v], cnt, all_rows[v] != 0,
                            /*count_zeroed=*/true, ap.cols.empty() ? nullptr : &app,
-                           append_capacity(tb.n_rows), s, v, p + 1);
+                           append_capacity(tb.n_rows), status, s, v, p + 1);
         if (st != PT_OK) return st;
         if (app.n_cols > 0) {
           pending = app;
@@ -819,7 +861,7 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
         const bool all = all_rows[v] != 0;
         st = build_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), tb.n_rows,
                            all ? nullptr : d_bitmaps[v], all ? nullptr : counts + cur[v] * pl.n_t + v,
-                           &scratch, use_app ? &pending : nullptr, app_idx.data(), s, v, p + 1);
+                           &scratch, use_app ? &pending : nullptr, app_idx.data(), status, s, v, p + 1);
         if (st != PT_OK) return st;
       }
       if (pending_table == v && pending_pass == p) pending_table = pl.n_t;
@@ -1253,6 +1295,7 @@ struct pt_batch {
 
 // timed: bracket the probe launches with profiling events (eager runs).
 static pt_status enqueue_batch(const pt_batch &b, hipStream_t s, bool timed) {
+  uint32_t *status = reinterpret_cast<uint32_t *>(b.ws);
   for (size_t li = 0; li < b.launches.size(); li++) {
     const BatchLaunch &l = b.launches[li];
     Timed tm(timed && l.kind == kProbe ? "batch probe" : nullptr, static_cast<uint32_t>(li), l.pass, l.rows,
@@ -1262,28 +1305,29 @@ static pt_status enqueue_batch(const pt_batch &b, hipStream_t s, bool timed) {
     hipError_t e = hipSuccess;
     switch (l.kind) {
       case kZero:
-        e = launch_zero_u64(reinterpret_cast<uint64_t *>(b.ws + b.off_counts), b.n_counts, s);
+        // the status word (workspace header) and every counter
+        e = launch_zero_u64(reinterpret_cast<uint64_t *>(b.ws), b.off_counts / 8 + b.n_counts, s);
         break;
       case kLocal:
         e = launch_local_batch(reinterpret_cast<const LocalTask *>(tasks), first, l.n, l.grid, s);
         break;
       case kSize:
-        e = launch_size_batch(reinterpret_cast<const SizeTask *>(tasks), first, l.n, l.grid, s);
+        e = launch_size_batch(reinterpret_cast<const SizeTask *>(tasks), first, l.n, l.grid, status, s);
         break;
       case kBuild:
         e = launch_build_batch(l.block_bits, l.k, reinterpret_cast<const BuildTask *>(tasks), first, l.n,
-                               l.grid, l.lds_words, s);
+                               l.grid, l.lds_words, status, s);
         break;
       case kProbe:
         e = launch_probe_batch(l.block_bits, l.k, l.any64, reinterpret_cast<const ProbeTask *>(tasks), first,
-                               l.n, l.grid, l.lds_words, s);
+                               l.n, l.grid, l.lds_words, status, s);
         break;
       case kCopy:
         e = launch_copy_pairs(reinterpret_cast<const CopyPair *>(tasks), l.n, s);
         break;
       case kSoloBuild:
         e = launch_build(l.block_bits, l.k, l.bits_per_key, l.fs, l.rows, l.bitmap, l.count, &b.scratch,
-                         nullptr, s);
+                         nullptr, status, s);
         break;
     }
     pt_status st = check_hip(e, "batch launch");

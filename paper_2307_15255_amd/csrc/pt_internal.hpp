@@ -1,14 +1,18 @@
-// pt_internal.hpp - launch descriptors shared by the host API and the kernels.
+// pt_internal.hpp - launch descriptors shared by the host API and the kernel
+// translation units, and the launchers each of those units exports.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <string>
-
-#include "pt_device.hpp"
+#include "../../include/pt.h"
 
 namespace pt {
+
+constexpr int kWave = 64;
+constexpr int kMaxFilters = 8;  // filters handled by one build launch
+constexpr int kMaxProbe = 4;    // filters handled by one probe launch (their keys stay in registers)
+constexpr int kMaxPreds = 8;    // predicates handled by one local-filter launch
 
 // One filter as a probe or build launch sees it.
 struct FilterRef {
@@ -73,18 +77,12 @@ struct AppendSet {
 // Upper bound of a probe grid's waves (regions of an AppendSet).
 constexpr uint32_t kMaxRegions = 65536;
 
-// Launchers (pt_kernels.hip). Each returns hipSuccess or the launch error.
-hipError_t launch_zero_u64(uint64_t *p, uint64_t n, hipStream_t s);
-hipError_t launch_local_filter(const PredSet &preds, uint64_t n_rows, uint64_t *bitmap,
-                               uint64_t *count, hipStream_t s);
-hipError_t launch_fill_all(uint64_t *bitmap, uint64_t n_rows, uint64_t *count, hipStream_t s);
-// input_all: every row starts selected (the bitmap is not read, only written).
-// app (optional, in/out): columns to append (n_cols, src, dst, key64,
-// counts) and the capacity of each dst in entries (capacity); the launch
-// fills in its region geometry, or sets n_cols = 0 when it appends nothing.
-hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows,
-                        uint64_t *bitmap, uint64_t *count, bool input_all, AppendSet *app,
-                        uint64_t capacity, hipStream_t s);
+// Launch options of a probe that come from the caller's parameters.
+struct ProbeOpts {
+  uint64_t lds_budget = 0;  // bytes of LDS to stage filters in (0: as much as the device allows)
+  bool keep_order = false;  // test the filters in the given order (no selectivity ordering)
+};
+
 constexpr uint32_t kTileWords = 16384;   // 64 KB of filter per partitioned-build tile
 constexpr uint32_t kMaxBuckets = 16384;  // (filter, tile) buckets of one partitioned build
 
@@ -103,20 +101,85 @@ struct BuildScratch {
   uint64_t entries_cap = 0;
 };
 
+// ------------------------------------------------------------ launchers
+//
+// Each returns hipSuccess or the launch error. `status` (may be NULL) is the
+// call's device status word: kernels OR PT_STATUS_* bits into it.
+
+// k_misc.hip
+hipError_t launch_zero_u64(uint64_t *p, uint64_t n, hipStream_t s);
+hipError_t launch_local_filter(const PredSet &preds, uint64_t n_rows, uint64_t *bitmap, uint64_t *count,
+                               hipStream_t s);
+hipError_t launch_fill_all(uint64_t *bitmap, uint64_t n_rows, uint64_t *count, hipStream_t s);
+hipError_t launch_copy_counts(const uint64_t *src, const uint32_t *slot, uint32_t n, uint64_t *dst,
+                              hipStream_t s);
+hipError_t launch_compact(const uint64_t *bitmap, uint64_t n_rows, uint32_t *idx, uint64_t *count,
+                          uint64_t *partials, hipStream_t s);
+uint64_t compact_partials(uint64_t n_rows);
+// Sizes filters from *count (n_rows when count is NULL) and zeroes their
+// blocks, except when a partitioned build with entries_cap entries (0:
+// none) will write every block: that is decided on the device from *count.
+hipError_t launch_size(uint32_t block_bits, uint32_t bits_per_key, const FilterSet &fs, const uint64_t *count,
+                       uint64_t n_rows, uint64_t entries_cap, uint32_t *status, hipStream_t s);
+
+// Raises a kernel's dynamic-LDS limit once per device (to the largest
+// request seen); later launches that fit skip the call.
+hipError_t allow_lds(const void *kern, uint64_t bytes);
+// Bitmap words per wave for the word-segment kernels: enough waves to cover
+// the device several times over, at most one word per lane.
+uint32_t segment_words(uint64_t n_words);
+uint32_t grid_for(uint64_t waves_of_work, uint32_t threads, uint32_t per_cu);
+
+// k_probe*.hip
+// input_all: every row starts selected (the bitmap is not read, only written).
+// app (optional, in/out): columns to append (n_cols, src, dst, key64,
+// counts) and the capacity of each dst in entries (capacity); the launch
+// fills in its region geometry, or sets n_cols = 0 when it appends nothing.
+hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows, uint64_t *bitmap,
+                        uint64_t *count, bool input_all, AppendSet *app, uint64_t capacity,
+                        const ProbeOpts &opt, uint32_t *status, hipStream_t s);
+
+// Arguments of one probe kernel launch (built by launch_probe).
+struct ProbeLaunch {
+  FilterSet fs;
+  uint32_t k, lg;
+  uint64_t n_rows;
+  uint64_t *bitmap;
+  unsigned long long *count;
+  uint32_t lds_filter_words;
+  uint32_t input_all;
+  uint32_t keep_order;
+  uint32_t *status;
+  AppendSet app;
+  uint32_t grid;
+  uint64_t lds_bytes;
+  bool any64;
+};
+// One probe kernel, specialised for B = 512 and k = 3 (k_probe_512.hip) or
+// generic in B and k (k_probe_gen.hip).
+hipError_t launch_probe_512_k3(const ProbeLaunch &pl, hipStream_t s);
+hipError_t launch_probe_generic(const ProbeLaunch &pl, hipStream_t s);
+
+// k_build.hip / k_part.hip
 // Sizes filters from *count (n_rows when count is NULL) and builds them
 // from the selected rows (bitmap NULL: all rows). With app (the AppendSet
 // of the probe that produced the bitmap, every filter's `app` set), the
 // keys are read from the appended columns.
 hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, const FilterSet &fs,
                         uint64_t n_rows, const uint64_t *bitmap, const uint64_t *count,
-                        const BuildScratch *scratch, const AppendSet *app, hipStream_t s);
+                        const BuildScratch *scratch, const AppendSet *app, uint32_t *status, hipStream_t s);
 // Words of LDS one build workgroup uses for its private filter copies.
 uint64_t build_lds_words();
-hipError_t launch_copy_counts(const uint64_t *src, const uint32_t *slot, uint32_t n,
-                              uint64_t *dst, hipStream_t s);
-hipError_t launch_compact(const uint64_t *bitmap, uint64_t n_rows, uint32_t *idx, uint64_t *count,
-                          uint64_t *partials, hipStream_t s);
-uint64_t compact_partials(uint64_t n_rows);
+// Partitioned build of filters too large for LDS (sized and not zeroed
+// beforehand by launch_size); falls back to global atomics in place when
+// the plan does not fit the scratch (then the filters must be zeroed).
+hipError_t launch_part_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, const FilterSet &fs,
+                             uint64_t n_rows, const uint64_t *bitmap, const uint64_t *count,
+                             const BuildScratch &scratch, const AppendSet &app, uint32_t seg_words,
+                             uint32_t *status, hipStream_t s);
+// Buckets a partitioned build aims for: its fill kernel runs one workgroup
+// per (filter, tile) bucket.
+constexpr uint64_t kTargetBuckets = 1024;
 
 // ------------------------------------------------------------ batched steps
 //
@@ -173,19 +236,21 @@ constexpr int kBatchThreads = 1024;  // every batched kernel: sixteen waves per 
 hipError_t launch_local_batch(const LocalTask *tasks, const uint32_t *first, uint32_t n, uint32_t grid,
                               hipStream_t s);
 hipError_t launch_size_batch(const SizeTask *tasks, const uint32_t *first, uint32_t n, uint32_t grid,
-                             hipStream_t s);
+                             uint32_t *status, hipStream_t s);
 // lds_words: LDS words per workgroup for private filter copies (a task whose
 // filters need more inserts with global atomics).
 hipError_t launch_build_batch(uint32_t block_bits, uint32_t k, const BuildTask *tasks, const uint32_t *first,
-                              uint32_t n, uint32_t grid, uint32_t lds_words, hipStream_t s);
+                              uint32_t n, uint32_t grid, uint32_t lds_words, uint32_t *status, hipStream_t s);
 // lds_filter_words: LDS words per workgroup for staged filters.
 hipError_t launch_probe_batch(uint32_t block_bits, uint32_t k, bool any64, const ProbeTask *tasks,
                               const uint32_t *first, uint32_t n, uint32_t grid, uint32_t lds_filter_words,
-                              hipStream_t s);
+                              uint32_t *status, hipStream_t s);
 hipError_t launch_copy_pairs(const CopyPair *pairs, uint32_t n, hipStream_t s);
 // Bytes of LDS a probe workgroup needs besides its staged filters.
 uint64_t probe_queue_bytes(bool any64);
 // Kernels whose LDS limit must be raised before a batch is captured.
 hipError_t prepare_batch_kernels(uint32_t block_bits, uint32_t k, bool any64);
+hipError_t prepare_probe_batch_kernel(uint32_t block_bits, uint32_t k, bool any64);
+hipError_t prepare_build_batch_kernel(uint32_t block_bits, uint32_t k);
 
 }  // namespace pt

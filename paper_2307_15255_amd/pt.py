@@ -5,8 +5,9 @@ kernels behind the C ABI. torch provides device memory (tensors) and streams.
 The functions keep the C names; the classes at the end assemble the arguments
 of a whole join problem.
 
-Importing this module loads the library and raises if it has not been built
-(``python -m paper_2307_15255_amd.build``); there is no fallback.
+Importing this module loads the library, building it first when it is
+missing or was built from other sources (``build.ensure_built``); a build or
+load failure raises. There is no fallback: every call runs on the GPU.
 """
 from __future__ import annotations
 
@@ -19,7 +20,9 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpt_hip.so")
 
-PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EUNSUPPORTED = 0, 1, 2, 3, 4
+PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EUNSUPPORTED, PT_EOVERFLOW = 0, 1, 2, 3, 4, 5
+PT_STATUS_FILTER_OVERFLOW, PT_STATUS_ENTRIES_OVERFLOW = 1, 2
+PT_PROBE_SELECTIVE, PT_PROBE_GIVEN = 0, 1
 PT_I32, PT_I64 = 0, 1
 OPS = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "eq": 4, "ne": 5, "between": 6}
 
@@ -40,7 +43,8 @@ class pt_table(C.Structure):
 
 
 class pt_edge(C.Structure):
-    _fields_ = [("u", C.c_uint32), ("u_col", C.c_uint32), ("v", C.c_uint32), ("v_col", C.c_uint32)]
+    _fields_ = [("u", C.c_uint32), ("u_col", C.c_uint32), ("v", C.c_uint32), ("v_col", C.c_uint32),
+                ("flags", C.c_uint32)]
 
 
 class pt_graph(C.Structure):
@@ -55,12 +59,13 @@ class pt_pred(C.Structure):
 
 class pt_params(C.Structure):
     _fields_ = [("block_bits", C.c_uint32), ("k", C.c_uint32), ("bits_per_key", C.c_uint32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("hash_version", C.c_uint32), ("lds_budget", C.c_uint32),
+                ("tile_rows", C.c_uint32), ("probe_order", C.c_uint32)]
 
 
 class pt_bloom(C.Structure):
     _fields_ = [("words", C.c_void_p), ("cap_words", C.c_uint64), ("d_nb", C.c_void_p),
-                ("params", pt_params)]
+                ("d_status", C.c_void_p), ("params", pt_params)]
 
 
 class pt_problem(C.Structure):
@@ -76,14 +81,15 @@ class pt_kernel_time(C.Structure):
 
 
 def _load() -> C.CDLL:
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2307_15255_amd.build`")
+    from . import build
+    build.ensure_built()
     L = C.CDLL(LIB_PATH)
     vp, u32, u64, st = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
     sizep = C.POINTER(C.c_size_t)
     sigs = {
         "pt_version": ([], C.c_char_p),
         "pt_last_error": ([], C.c_char_p),
+        "pt_check_status": ([vp, vp], st),
         "pt_local_filter": ([C.POINTER(pt_table), C.POINTER(pt_pred), u32, vp, vp, vp], st),
         "pt_bloom_capacity": ([u64, C.POINTER(pt_params), C.POINTER(u64)], st),
         "pt_bloom_build": ([u32, C.POINTER(pt_column), C.POINTER(pt_bloom), u64, vp, vp, vp], st),
@@ -114,7 +120,7 @@ def _load() -> C.CDLL:
 
 
 _lib = _load()
-EXPORTS = ("pt_version", "pt_last_error", "pt_local_filter", "pt_bloom_capacity", "pt_bloom_build",
+EXPORTS = ("pt_version", "pt_last_error", "pt_check_status", "pt_local_filter", "pt_bloom_capacity", "pt_bloom_build",
            "pt_bloom_probe", "pt_compact_workspace_size", "pt_compact", "pt_transfer_workspace_size",
            "pt_transfer", "pt_transfer_filter", "pt_batch_workspace_size", "pt_batch_prepare",
            "pt_batch_prepare_async", "pt_batch_run",
@@ -150,8 +156,19 @@ def column(t: torch.Tensor) -> pt_column:
 PT_FLAG_NO_APPEND = 1
 
 
-def params(block_bits: int = 512, k: int = 3, bits_per_key: int = 10, flags: int = 0) -> pt_params:
-    return pt_params(block_bits, k, bits_per_key, flags)
+def params(block_bits: int = 512, k: int = 3, bits_per_key: int = 10, flags: int = 0, *, hash_version: int = 1,
+           lds_budget: int = 0, tile_rows: int = 0, probe_order: int = PT_PROBE_SELECTIVE) -> pt_params:
+    """Filter parameters: the first three fix the filter bits; lds_budget,
+    tile_rows and probe_order only change the launch layout."""
+    return pt_params(block_bits, k, bits_per_key, flags, hash_version, lds_budget, tile_rows, probe_order)
+
+
+def pt_check_status(d_status, stream=None) -> None:
+    """Waits for the stream, reads and clears a device status word (a
+    workspace tensor, a Bloom's status tensor or a raw device address) and
+    raises PtError(PT_EOVERFLOW) when a kernel reported an overflow."""
+    addr = d_status.data_ptr() if isinstance(d_status, torch.Tensor) else int(d_status)
+    _check(_lib.pt_check_status(C.c_void_p(addr), _stream(stream)))
 
 
 def bitmap_words(n_rows: int) -> int:
@@ -189,9 +206,11 @@ class Bloom:
         self.cap_words = pt_bloom_capacity(max_keys, p)
         self.words = torch.zeros(self.cap_words, dtype=torch.int32, device=device)
         self.nb = torch.zeros(1, dtype=torch.int64, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
 
     def c(self) -> pt_bloom:
-        return pt_bloom(self.words.data_ptr(), self.cap_words, self.nb.data_ptr(), self.params)
+        return pt_bloom(self.words.data_ptr(), self.cap_words, self.nb.data_ptr(), self.status.data_ptr(),
+                        self.params)
 
     def used_words(self) -> np.ndarray:
         nb = int(self.nb.item())
@@ -259,7 +278,8 @@ class DeviceProblem:
             self._ccols.append(cc)
             self.tables[t] = pt_table(self.n_rows[t], len(columns[t]), 0, cc)
         self.edges = (pt_edge * max(1, len(problem.edges)))(*[
-            pt_edge(u, problem.col_index(u, uc), v, problem.col_index(v, vc)) for u, uc, v, vc in problem.edges])
+            pt_edge(u, problem.col_index(u, uc), v, problem.col_index(v, vc), 0)
+            for u, uc, v, vc in problem.edges])
         self._orient = None
         orient_ptr = None
         if problem.orient is not None:
@@ -312,6 +332,11 @@ class Transfer:
 
     def run(self, stream=None) -> None:
         pt_transfer(self.dp, self.params, self.ws, self.bitmaps, self.counts, stream)
+
+    def check_status(self, stream=None) -> None:
+        """Raises PtError(PT_EOVERFLOW) if the latest run's kernels reported
+        an overflow (waits for the stream)."""
+        pt_check_status(self.ws, stream)
 
     def bitmap(self, t: int) -> np.ndarray:
         return self.bitmaps[t].cpu().numpy().view(np.uint64)
@@ -376,6 +401,9 @@ class Batch:
 
     def run(self, stream=None, eager: bool = False) -> None:
         _check(_lib.pt_batch_run(self._h, _stream(stream), PT_BATCH_EAGER if eager else 0))
+
+    def check_status(self, stream=None) -> None:
+        pt_check_status(self.ws, stream)
 
     def info(self) -> tuple[int, int]:
         """(kernel launches per run, rows probed per run)."""

@@ -108,3 +108,33 @@ def test_planner_validation(ptlib):
     # a cycle in the join graph itself is fine: the size rule orients it acyclically
     st, _ = _HostProblem(ptlib, [10, 100, 5], [(0, 0, 1, 0), (1, 0, 2, 0), (2, 0, 0, 0)]).ws(ptlib, p)
     assert st == ptlib.PT_OK
+
+
+def test_layout_parameters_validation(ptlib):
+    """hash_version, tile_rows and probe_order are checked on the host; only
+    the filter specification of version 1 is implemented."""
+    ok = [ptlib.params(512, 3, 10, hash_version=0), ptlib.params(512, 3, 10, hash_version=1),
+          ptlib.params(512, 3, 10, tile_rows=4096), ptlib.params(512, 3, 10, tile_rows=1 << 24),
+          ptlib.params(512, 3, 10, probe_order=ptlib.PT_PROBE_GIVEN), ptlib.params(512, 3, 10, lds_budget=1)]
+    for p in ok:
+        assert ptlib.pt_bloom_capacity(10, p) == 16
+    for p, status in [(ptlib.params(512, 3, 10, hash_version=2), ptlib.PT_EUNSUPPORTED),
+                      (ptlib.params(512, 3, 10, tile_rows=100), ptlib.PT_EINVAL),
+                      (ptlib.params(512, 3, 10, tile_rows=(1 << 24) + 4096), ptlib.PT_EINVAL),
+                      (ptlib.params(512, 3, 10, probe_order=2), ptlib.PT_EINVAL)]:
+        with pytest.raises(ptlib.PtError) as ei:
+            ptlib.pt_bloom_capacity(10, p)
+        assert ei.value.status == status
+
+
+def test_edge_flags_are_reserved(ptlib):
+    p = ptlib.params()
+    prob = _HostProblem(ptlib, [10, 100], [(0, 0, 1, 0, 0)])
+    assert prob.ws(ptlib, p)[0] == ptlib.PT_OK
+    prob = _HostProblem(ptlib, [10, 100], [(0, 0, 1, 0, 1)])
+    assert prob.ws(ptlib, p)[0] == ptlib.PT_EUNSUPPORTED
+    assert "flags" in ptlib.lib().pt_last_error().decode()
+
+
+def test_check_status_rejects_null(ptlib):
+    assert ptlib.lib().pt_check_status(None, None) == ptlib.PT_EINVAL

@@ -185,3 +185,36 @@ def test_rejects_bad_arguments_before_launch(pt):
     bm = torch.zeros(2, dtype=torch.int64, device="cuda")
     with pytest.raises(pt.PtError):         # a bitmap without its count
         pt.pt_bloom_build([keys], [pt.Bloom(100, p)], 100, bm, None)
+
+
+def test_overflow_is_reported(pt):
+    """A count above the filter's capacity, or a block count above it, is
+    clamped on the device and reported through the status word."""
+    n = 5000
+    rng = np.random.default_rng(77)
+    keys = dev(rng.integers(0, 1 << 30, n).astype(np.int32))
+    p = pt.params()
+    f = pt.Bloom(n, p)
+    bm = torch.full(((n + 63) // 64,), -1, dtype=torch.int64, device="cuda")
+    bm[-1] = (1 << (n % 64)) - 1
+    cnt = torch.tensor([n], dtype=torch.int64, device="cuda")
+    say("overflow: clean build and probe")
+    pt.pt_bloom_build([keys], [f], n, bm, cnt)
+    pt.pt_check_status(f.status)
+    probe_bm = bm.clone()
+    pt.pt_bloom_probe([keys], [f], n, probe_bm)
+    pt.pt_check_status(f.status)
+    assert torch.equal(probe_bm, bm)  # no false negatives
+    say("overflow: count above the capacity")
+    cnt.fill_(4 * n)
+    pt.pt_bloom_build([keys], [f], n, bm, cnt)
+    with pytest.raises(pt.PtError) as ei:
+        pt.pt_check_status(f.status)
+    assert ei.value.status == pt.PT_EOVERFLOW
+    assert int(f.nb.item()) == f.cap_words // (p.block_bits // 32)  # clamped to the capacity
+    pt.pt_check_status(f.status)  # the read cleared it
+    say("overflow: block count above the capacity")
+    f.nb.fill_(1 << 40)
+    pt.pt_bloom_probe([keys], [f], n, probe_bm)
+    with pytest.raises(pt.PtError):
+        pt.pt_check_status(f.status)

@@ -27,12 +27,12 @@ def pt():
     return ptmod
 
 
-def check_transfer(pt, prob, B=512, k=3, bpk=10, filters=True, runs=1, flags=0):
+def check_transfer(pt, prob, B=512, k=3, bpk=10, filters=True, runs=1, flags=0, **layout):
     dp = pt.DeviceProblem(prob)
-    tr = pt.Transfer(dp, pt.params(B, k, bpk, flags))
+    tr = pt.Transfer(dp, pt.params(B, k, bpk, flags, **layout))
     for _ in range(runs):
         tr.run()
-    torch.cuda.synchronize()
+    tr.check_status()  # waits for the stream; no kernel reported an overflow
     ref = oracle.transfer(prob, B, k, bpk, dump_filters=filters)
     counts = tr.counts.cpu().numpy()
     for t in range(prob.n_tables):
@@ -61,6 +61,20 @@ def test_parameters(pt, B, k, bpk):
         prob = W.tiny_random(np.random.default_rng(777 + s), SHAPES[s % 6], max_rows=300, domain=64)
         say("params", B, k, bpk, s)
         check_transfer(pt, prob, B, k, bpk)
+
+
+@pytest.mark.parametrize("layout", [dict(probe_order=1), dict(lds_budget=64), dict(lds_budget=4096, probe_order=1),
+                                    dict(hash_version=0)])
+def test_layout_parameters_keep_bits(pt, layout):
+    """probe order, LDS staging budget (filters read from global memory when
+    they do not fit) and the hash-version alias change no bit."""
+    for s in range(6):
+        prob = W.tiny_random(np.random.default_rng(4242 + s), SHAPES[s % 6], max_rows=3000, domain=500)
+        say("layout", layout, s)
+        check_transfer(pt, prob, **layout)
+    prob = W.star(seed=3, n_fact=300_000, dims=(20_000, 2_000, 100, 25))
+    say("layout star", layout)
+    check_transfer(pt, prob, **layout)
 
 
 @pytest.mark.parametrize("name", ["fig2_transform.json", "fig3_chain.json"])
