@@ -52,21 +52,53 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(workload: str, dom_key) -> float | None:
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (profiles/), scaled by the calibration kernel; None unless the
-    kernel source is the one the counters were taken on."""
+# Sources the probe kernels are compiled from: counters taken on other
+# sources do not describe the kernel that runs.
+PROBE_SOURCES = ["include/pt.h", "paper_2307_15255_amd/csrc/pt_internal.hpp",
+                 "paper_2307_15255_amd/csrc/pt_common.hpp", "paper_2307_15255_amd/csrc/probe_impl.hpp",
+                 "paper_2307_15255_amd/csrc/k_probe_512.hip", "paper_2307_15255_amd/csrc/k_probe_gen.hip"]
+
+
+def probe_source_hash() -> str:
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(here, "profiles", "probe_star_fact_traffic.json")
-    if workload != "star" or dom_key[:3] != ("probe", 0, 1) or not os.path.exists(path):
-        return None
+    h = hashlib.sha256()
+    for rel in PROBE_SOURCES:
+        with open(os.path.join(here, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, dom_key) -> tuple[float | None, str | None]:
+    """HBM bytes per launch of the dominant kernel as two rocprofv3 --pmc
+    runs measured them (FETCH_SIZE, WRITE_SIZE, scaled by a copy kernel of
+    known traffic), from the committed summary under profiles/, and that
+    file's name; (None, None) unless the counters were taken on the probe
+    sources that are built now."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", f"probe_{workload}_fact_traffic.json")
+    if dom_key[0] != "probe" or dom_key[2] != 1 or not os.path.exists(path):
+        return None, None
     with open(path) as f:
         rec = json.load(f)
-    with open(os.path.join(here, "paper_2307_15255_amd", "csrc", "pt_kernels.hip"), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-            return None
-    return float(rec["traffic_bytes"])
+    if rec.get("source_sha256") != probe_source_hash() or rec.get("table") != dom_key[1]:
+        return None, None
+    return float(rec["traffic_bytes"]), os.path.relpath(path, here)
+
+
+def host_cpu() -> str:
+    """Logical CPUs of the host and its model name."""
+    model = "unknown model"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return f"{n} logical CPUs available ({os.cpu_count()} online), {model}"
 
 
 def rows_probed(prob, order_src_dst) -> int:
@@ -133,8 +165,8 @@ def main():
         tr.run()
     torch.cuda.synchronize()
 
-    # HIP events around the probe launches only (the dominant kernel is a probe)
-    pt.pt_profile_enable(0 if args.no_kernel_events else 2)
+    # HIP events around every launch, on the stream each is launched on
+    pt.pt_profile_enable(0 if args.no_kernel_events else 1)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
@@ -162,7 +194,8 @@ def main():
                           "ms_per_step": round(ms_per_step, 4), "steps": args.steps,
                           "note": "no per-kernel events"}), flush=True)
         return
-    # the dominant kernel: the probe launch with the largest total time
+    # the dominant kernel: the launch (step, table, pass) with the largest
+    # total time over the timed steps
     by_key: dict[tuple, list] = {}
     for r in records:
         by_key.setdefault((r["name"], r["table"], r["pass_"]), []).append(r)
@@ -205,22 +238,29 @@ def main():
 
     if args.calibrate_copy:
         out["calibration_copy_bytes"] = 1 << 30
-    out["roofline"]["traffic"] = measured_traffic(args.workload, dom_key)
+    traffic, source = measured_traffic(args.workload, dom_key)
+    out["roofline"]["traffic"] = traffic
+    if source:
+        out["roofline"]["traffic_source"] = source
 
     if args.check or not args.no_cpu_baseline:
         import oracle
-        host = os.cpu_count()
-        t = time.perf_counter()
-        ref = oracle.transfer(prob, 512, 3, bpk)
-        cpu_s = time.perf_counter() - t
+        # the whole workload, repeated until about 10 s of oracle work (at
+        # least once); the median run is reported
+        runs = []
+        while not runs or (sum(runs) < 10 and len(runs) < 5):
+            t = time.perf_counter()
+            ref = oracle.transfer(prob, 512, 3, bpk)
+            runs.append(time.perf_counter() - t)
+        cpu_s = float(np.median(runs))
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = {
                 "value": round(n_probed / cpu_s / 1e9, 4),
                 "unit": "G rows/s",
                 "cores": 1,
                 "kind": "oracle",
-                "sample": f"the whole workload once ({n_probed} rows probed in {cpu_s:.2f} s, "
-                          f"single thread; host has {host} logical CPUs)",
+                "sample": f"the whole workload ({n_probed} rows probed), median of {len(runs)} runs of "
+                          f"{cpu_s:.2f} s, single thread; host: {host_cpu()}",
             }
         if args.check:
             ok = all(np.array_equal(tr.bitmap(t), ref.bitmaps[t]) for t in range(prob.n_tables))

@@ -341,10 +341,10 @@ hipError_t launch_copy_pairs(const CopyPair *pairs, uint32_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t prepare_batch_kernels(uint32_t block_bits, uint32_t k, bool any64) {
+hipError_t prepare_batch_kernels(uint32_t block_bits, uint32_t k) {
   hipError_t e = prepare_build_batch_kernel(block_bits, k);
   if (e != hipSuccess) return e;
-  return prepare_probe_batch_kernel(block_bits, k, any64);
+  return prepare_probe_batch_kernel(block_bits, k);
 }
 
 }  // namespace pt

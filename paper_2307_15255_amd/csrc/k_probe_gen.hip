@@ -7,9 +7,7 @@ namespace pt {
 
 hipError_t launch_probe_generic(const ProbeLaunch &pl, hipStream_t s) { return launch_probe_kernel<0, 0>(pl, s); }
 
-uint64_t probe_queue_bytes(bool any64) {
-  return static_cast<uint64_t>(kProbeWaves) * 4 * (any64 ? probe_slice_words<true>() : probe_slice_words<false>());
-}
+uint64_t probe_queue_bytes() { return static_cast<uint64_t>(kProbeWaves) * 4 * probe_slice_words(); }
 
 hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, uint64_t n_rows, uint64_t *bitmap,
                         uint64_t *count, bool input_all, AppendSet *app, uint64_t capacity, const ProbeOpts &opt,
@@ -21,14 +19,10 @@ hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, ui
   }
   const uint32_t lg = log2_of(static_cast<int>(block_bits));
   if (lg == 0) return hipErrorInvalidValue;
-  bool any64 = false;
   uint64_t want_words = 0;
-  for (uint32_t i = 0; i < fs.n; i++) {
-    any64 = any64 || fs.f[i].key64;
-    want_words += fs.f[i].cap_words;
-  }
+  for (uint32_t i = 0; i < fs.n; i++) want_words += fs.f[i].cap_words;
   const DeviceInfo &di = device_info();
-  const uint64_t queue_bytes = probe_queue_bytes(any64);
+  const uint64_t queue_bytes = probe_queue_bytes();
   // Leave room for the kernel's own static LDS (a few dozen bytes).
   const uint64_t lds_max = static_cast<uint64_t>(di.max_lds_block) - 1024;
   uint64_t filter_bytes = lds_max > queue_bytes ? lds_max - queue_bytes : 0;
@@ -37,7 +31,7 @@ hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, ui
   filter_bytes &= ~uint64_t(7);  // keep the slices 8-byte aligned
   const uint64_t lds_bytes = filter_bytes + queue_bytes;
   const uint32_t per_cu = lds_bytes * 2 <= lds_max ? 2 : 1;
-  const int U = any64 ? probe_group_words<true>() : probe_group_words<false>();
+  const int U = kGroupWords;
   ProbeLaunch pl{};
   pl.grid = grid_for((n_words + U - 1) / U, kProbeThreads, per_cu);
   pl.lds_filter_words = static_cast<uint32_t>(filter_bytes / 4);
@@ -51,7 +45,6 @@ hipError_t launch_probe(uint32_t block_bits, uint32_t k, const FilterSet &fs, ui
   pl.input_all = input_all ? 1u : 0u;
   pl.keep_order = opt.keep_order ? 1u : 0u;
   pl.status = status;
-  pl.any64 = any64;
   // Region geometry of the appended keys: one region per wave of the grid,
   // capacity / regions slots each (at most the rows a wave can see).
   if (app && app->n_cols > 0 && app->n_cols <= static_cast<uint32_t>(kMaxAppend) && app->counts) {

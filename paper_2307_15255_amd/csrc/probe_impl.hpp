@@ -2,21 +2,25 @@
 // half of the filter transformation), shared by the probe translation units
 // that instantiate it for particular block sizes and hash counts.
 //
-// One scan of the table probes every incoming filter. At start each
-// workgroup:
+// One scan of the table probes every incoming filter, in the order the
+// paper describes for a transformation: the first filter is probed with its
+// key column on every row, each later filter only on the rows that are
+// still alive. At start each workgroup
 //   - orders the filters by their estimated pass rate (builder rows kept /
 //     builder rows), most selective first - the order cannot change the
 //     result, only the work;
 //   - copies all filters into its LDS when they fit together, else reads
 //     all of them from global memory (L2 / Infinity Cache / HBM).
-// Each wave then streams U bitmap words per iteration: it loads every key
-// column of those rows, tests the first filter on all of them, and, when
-// at most 64 rows survive, compacts the survivors (word, lane and
-// remaining keys) into its LDS slice so that one fully occupied wave
-// instruction stream tests them against the remaining filters. Failures are
-// folded back into the group's words through an LDS mask, and every word is
-// stored once. Groups with more survivors test the remaining filters on the
-// words directly.
+// Each wave then takes groups of kGroupWords bitmap words (1024 rows):
+//   - it streams the first filter's key column for the group (coalesced,
+//     the next group's keys already in flight while this one is tested) and
+//     tests every row;
+//   - when at most 64 rows of the group survive, it compacts them into its
+//     LDS slice, one lane each, and gathers only those rows' keys of the
+//     other columns, so a selective first filter spares the reads of most
+//     of the other columns' cache lines; when more survive, it streams the
+//     other columns for the words that still hold rows;
+//   - it stores each bitmap word once, from lane u for word u.
 #pragma once
 
 #include "pt_common.hpp"
@@ -30,6 +34,8 @@ struct Slot {
   uint32_t key64;
 };
 
+constexpr int kGroupWords = 16;  // bitmap words (64 rows each) per wave and group
+
 template <int K, bool STAGED>
 __device__ __forceinline__ bool slot_has(const Slot &s, const uint32_t *lds_filter, uint32_t h1, uint32_t h2,
                                          uint32_t k, uint32_t lg) {
@@ -38,224 +44,262 @@ __device__ __forceinline__ bool slot_has(const Slot &s, const uint32_t *lds_filt
   return block_has<K>(s.words + (static_cast<uint64_t>(blk) << (lg - 5)), h2, k, lg);
 }
 
-template <bool ANY64>
-constexpr int probe_group_words() {
-  return ANY64 ? 4 : 8;
-}
+// 32-bit words of one wave's LDS slice: the compacted survivors' tags
+// (word and lane), their first-column keys (low and high halves), and one
+// 64-bit failure mask per word of the group.
+constexpr int probe_slice_words() { return kWave * 3 + 2 * kGroupWords; }
 
-// 32-bit words of one wave's LDS slice: compacted survivors (word-and-lane
-// tag, the keys of every slot) plus one 64-bit failure mask per word of the
-// group.
-template <bool ANY64>
-constexpr int probe_slice_words() {
-  return kWave * (1 + kMaxProbe * (ANY64 ? 2 : 1)) + 2 * probe_group_words<ANY64>();
-}
-
-// Stores the key of appended column c for a surviving row at region slot
-// pos: from the probe's registers (klo/khi of slot app_slot[c]) or, for a
-// column the probe did not read, from the table.
-template <bool ANY64>
-__device__ __forceinline__ void append_key(const AppendSet &app, int c, int slot, const uint32_t (&klo)[kMaxProbe],
-                                           const uint32_t (&khi)[kMaxProbe], uint64_t row, uint64_t at) {
-  uint32_t lo = 0, hi = 0;
-  bool have = false;
-#pragma unroll
-  for (int q = 0; q < kMaxProbe; q++)
-    if (slot == q) {
-      lo = klo[q];
-      hi = ANY64 ? khi[q] : 0;
-      have = true;
-    }
-  if (app.key64[c]) {
-    static_cast<uint64_t *>(app.dst[c])[at] =
-        have ? ((static_cast<uint64_t>(hi) << 32) | lo) : static_cast<const uint64_t *>(app.src[c])[row];
+// Key of row `row` of a column as low and high halves of its int64 value.
+__device__ __forceinline__ void gather_key(const void *col, uint32_t key64, uint64_t row, uint32_t &lo,
+                                           uint32_t &hi) {
+  if (key64) {
+    const uint64_t x = static_cast<const uint64_t *>(col)[row];
+    lo = static_cast<uint32_t>(x);
+    hi = static_cast<uint32_t>(x >> 32);
   } else {
-    static_cast<uint32_t *>(app.dst[c])[at] = have ? lo : static_cast<const uint32_t *>(app.src[c])[row];
+    const int32_t x = static_cast<const int32_t *>(col)[row];
+    lo = static_cast<uint32_t>(x);
+    hi = static_cast<uint32_t>(x >> 31);
   }
 }
 
-template <int K, bool ANY64, bool STAGED, bool APPEND>
+// The group's first-column keys: lane l gets rows base + 64 u + l (clamped to
+// the last row, `last` rows past base), u < kGroupWords.
+template <bool KEY64>
+__device__ __forceinline__ void load_group(const void *col, uint64_t base, uint32_t last,
+                                           uint32_t (&lo)[kGroupWords], uint32_t (&hi)[KEY64 ? kGroupWords : 1]) {
+  const uint32_t lane = lane_id();
+  if constexpr (KEY64) {
+    const uint64_t *p = static_cast<const uint64_t *>(col) + base;
+#pragma unroll
+    for (int u = 0; u < kGroupWords; u++) {
+      const uint64_t x = p[min(static_cast<uint32_t>(u * 64) + lane, last)];
+      lo[u] = static_cast<uint32_t>(x);
+      hi[u] = static_cast<uint32_t>(x >> 32);
+    }
+  } else {
+    const uint32_t *p = static_cast<const uint32_t *>(col) + base;
+#pragma unroll
+    for (int u = 0; u < kGroupWords; u++) lo[u] = p[min(static_cast<uint32_t>(u * 64) + lane, last)];
+  }
+}
+
+template <int K, bool KEY64, bool STAGED, bool APPEND>
 __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const uint32_t (&lds_off)[kMaxProbe],
                                               uint32_t n_f, uint32_t k, uint32_t lg, uint64_t n_rows,
                                               uint64_t *bitmap, uint32_t input_all, const uint32_t *lds_filters,
                                               uint32_t *slice, const AppendSet &app,
                                               const int (&app_slot)[kMaxAppend], const VGrid &vg) {
-  constexpr int U = probe_group_words<ANY64>();
-  uint32_t *q_tag = slice;                                          // [kWave]
-  uint32_t *q_lo = slice + kWave;                                   // [kMaxProbe][kWave]
-  uint32_t *q_hi = slice + kWave * (1 + kMaxProbe);                 // [kMaxProbe][kWave] (int64)
-  unsigned long long *fail_mask = reinterpret_cast<unsigned long long *>(
-      slice + kWave * (1 + kMaxProbe * (ANY64 ? 2 : 1)));           // [U]
+  constexpr int U = kGroupWords;
+  uint32_t *q_tag = slice;                                                     // [kWave]
+  uint32_t *q_lo = slice + kWave;                                              // [kWave]
+  uint32_t *q_hi = slice + 2 * kWave;                                          // [kWave]
+  unsigned long long *fail = reinterpret_cast<unsigned long long *>(slice + 3 * kWave);  // [U]
   const uint32_t lane = lane_id();
   const uint64_t n_words = (n_rows + 63) / 64;
   const uint64_t stride = wave_count(vg) * U;
   int64_t cnt = 0;
   uint32_t app_n = 0;  // survivors of this wave's region so far
   const uint64_t app_base = global_wave(vg) * static_cast<uint64_t>(app.region_cap);
+  const void *col0 = sl[0].keys;
 
-  for (uint64_t w0 = global_wave(vg) * U; w0 < n_words; w0 += stride) {
-    // The group's U words: lane u loads word w0 + u (one load), then every
-    // lane reads them back as scalars.
-    uint64_t mine = 0;
-    if (!input_all) {
-      const uint64_t wl = w0 + (lane < U ? lane : 0);
-      mine = bitmap[wl < n_words ? wl : n_words - 1];
-    }
-    uint64_t word[U];
-    uint64_t any = 0;
+  // Software pipeline: the keys (and bitmap words) of the group after the
+  // current one are requested before the current one is tested.
+  uint64_t w0 = global_wave(vg) * U;
+  uint32_t nlo[U], nhi[KEY64 ? U : 1];
+  uint64_t nbits = 0;
+  if (w0 < n_words) {
+    const uint64_t left = n_rows - 1 - w0 * 64;
+    load_group<KEY64>(col0, w0 * 64, left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu, nlo, nhi);
+    if (!input_all) nbits = bitmap[min(w0 + (lane < U ? lane : 0), n_words - 1)];
+  }
+  for (; w0 < n_words; w0 += stride) {
+    uint32_t lo[U], hi[KEY64 ? U : 1];
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      const uint64_t m = tail_mask(w0 + u, n_words, n_rows);
-      // readlane returns int: widen through uint32_t (no sign extension)
-      const uint32_t b_hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(mine >> 32), u);
-      const uint32_t b_lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(mine), u);
-      const uint64_t b = (static_cast<uint64_t>(b_hi) << 32) | b_lo;
-      word[u] = input_all ? m : (b & m);
-      any |= word[u];
+      lo[u] = nlo[u];
+      if constexpr (KEY64) hi[u] = nhi[u];
     }
-    if (any == 0) continue;
-
-    // Every key column of the group, for every lane, in straight-line code so
-    // that all loads of the group are in flight together. Rows past the end
-    // are clamped; slots past n_f read slot 0's column again (cache hits).
-    // Offsets are 32-bit from a per-group scalar base.
+    const uint64_t bits = nbits;  // lane u < U: bitmap word w0 + u (unless input_all)
+    const uint64_t w_next = w0 + stride;
+    if (w_next < n_words) {
+      const uint64_t left = n_rows - 1 - w_next * 64;
+      load_group<KEY64>(col0, w_next * 64, left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu, nlo,
+                        nhi);
+      if (!input_all) nbits = bitmap[min(w_next + (lane < U ? lane : 0), n_words - 1)];
+    }
     const uint64_t base_row = w0 * 64;
-    const uint64_t left = n_rows - 1 - base_row;  // rows left after base_row (>= 0)
-    const uint32_t last = left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu;
-    uint32_t rel[U];
+
+    // The first (most selective) filter on every row of the group. The
+    // group's words go to lane-parallel form (lane u holds word w0 + u), and
+    // the survivors are compacted into the LDS slice as they appear (the
+    // first 64 of them: more than that take the dense path below).
+    uint64_t mine = 0;
+    uint32_t total0 = 0;  // survivors of the first filter
 #pragma unroll
-    for (int u = 0; u < U; u++) rel[u] = min(static_cast<uint32_t>(u * 64) + lane, last);
-    uint32_t lo[kMaxProbe][U];
-    uint32_t hi[ANY64 ? kMaxProbe : 1][U];
-#pragma unroll
-    for (int s = 0; s < kMaxProbe; s++) {
-      if (ANY64 && sl[s].key64) {
-        const uint64_t *col = static_cast<const uint64_t *>(sl[s].keys) + base_row;
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-          const uint64_t x = col[rel[u]];
-          lo[s][u] = static_cast<uint32_t>(x);
-          hi[ANY64 ? s : 0][u] = static_cast<uint32_t>(x >> 32);
-        }
-      } else {
-        const int32_t *col = static_cast<const int32_t *>(sl[s].keys) + base_row;
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-          const int32_t x = col[rel[u]];
-          lo[s][u] = static_cast<uint32_t>(x);
-          if (ANY64) hi[ANY64 ? s : 0][u] = static_cast<uint32_t>(x >> 31);
+    for (int u = 0; u < U; u++) {
+      uint64_t word = tail_mask(w0 + u, n_words, n_rows);
+      if (!input_all) {
+        // readlane returns int: widen through uint32_t (no sign extension)
+        const uint32_t b_hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(bits >> 32), u);
+        const uint32_t b_lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(bits), u);
+        word &= (static_cast<uint64_t>(b_hi) << 32) | b_lo;
+      }
+      if (word) {
+        uint32_t h1, h2;
+        if constexpr (KEY64)
+          hash_key((static_cast<uint64_t>(hi[u]) << 32) | lo[u], h1, h2);
+        else
+          hash_key32(lo[u], h1, h2);
+        const bool ok = slot_has<K, STAGED>(sl[0], lds_filters + lds_off[0], h1, h2, k, lg);
+        const uint64_t m = __ballot(ok) & word;
+        mine = lane == u ? m : mine;
+        if (m) {
+          if ((m >> lane) & 1) {
+            const uint32_t pos = total0 + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0));
+            if (pos < kWave) {
+              q_tag[pos] = (static_cast<uint32_t>(u) << 6) | lane;
+              if (APPEND) {
+                q_lo[pos] = lo[u];
+                if constexpr (KEY64) q_hi[pos] = hi[u];
+              }
+            }
+          }
+          total0 += static_cast<uint32_t>(__popcll(m));
         }
       }
     }
 
-    // The first (most selective) filter on every row of the group.
-    uint64_t m0[U];
-    uint32_t total = 0;
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      uint32_t h1, h2;
-      hash_parts(lo[0][u], ANY64 ? hi[0][u] : 0, ANY64 && sl[0].key64, h1, h2);
-      const bool ok = slot_has<K, STAGED>(sl[0], lds_filters + lds_off[0], h1, h2, k, lg);
-      m0[u] = __ballot(ok && ((word[u] >> lane) & 1));
-      total += __popcll(m0[u]);
-    }
-
-    bool appended = false;  // the survivors' keys are stored
-    if (n_f > 1 && total > kWave) {
-      // Many survivors: test the remaining filters on the words themselves.
+    uint32_t total = total0;  // rows left in the group
+    bool appended = false;    // the final survivors' keys are stored
+    if (total0 > kWave && n_f > 1) {
+      // Many survivors: stream the other columns for the words that still
+      // hold rows (four words at a time, their loads in flight together),
+      // and test them there.
+      const uint64_t left = n_rows - 1 - base_row;
+      const uint32_t last = left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu;
 #pragma unroll
       for (int s = 1; s < kMaxProbe; s++) {
         if (s < static_cast<int>(n_f)) {
 #pragma unroll
-          for (int u = 0; u < U; u++) {
-            if (m0[u]) {
-              uint32_t h1, h2;
-              hash_parts(lo[s][u], ANY64 ? hi[ANY64 ? s : 0][u] : 0, ANY64 && sl[s].key64, h1, h2);
-              const bool ok = slot_has<K, STAGED>(sl[s], lds_filters + lds_off[s], h1, h2, k, lg);
-              m0[u] = __ballot(ok && ((m0[u] >> lane) & 1));
+          for (int u0 = 0; u0 < U; u0 += 4) {
+            uint64_t m[4];
+            uint32_t xlo[4], xhi[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+              const uint32_t m_hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(mine >> 32), u0 + j);
+              const uint32_t m_lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(mine), u0 + j);
+              m[j] = (static_cast<uint64_t>(m_hi) << 32) | m_lo;
+              xlo[j] = xhi[j] = 0;
+              if (m[j])
+                gather_key(sl[s].keys, sl[s].key64, base_row + min(static_cast<uint32_t>((u0 + j) * 64) + lane, last),
+                           xlo[j], xhi[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+              if (m[j]) {
+                uint32_t h1, h2;
+                hash_parts(xlo[j], xhi[j], sl[s].key64, h1, h2);
+                m[j] &= __ballot(slot_has<K, STAGED>(sl[s], lds_filters + lds_off[s], h1, h2, k, lg));
+                mine = lane == u0 + j ? m[j] : mine;
+              }
             }
           }
         }
       }
-    } else if (total > 0 && total <= kWave && (n_f > 1 || (APPEND && app_n < app.region_cap))) {
-      // Few survivors: compact them into the LDS slice, one lane each, and
-      // test the remaining filters with every lane busy.
-      uint32_t pos0 = 0;
+      total = 0;
 #pragma unroll
       for (int u = 0; u < U; u++) {
-        if (lane == 0) fail_mask[u] = 0;
-        if ((m0[u] >> lane) & 1) {
-          const uint32_t pos = pos0 + __popcll(m0[u] & ((1ull << lane) - 1));
-          q_tag[pos] = (static_cast<uint32_t>(u) << 6) | lane;
-#pragma unroll
-          for (int s = APPEND ? 0 : 1; s < kMaxProbe; s++) {
-            if (s < static_cast<int>(n_f)) {
-              q_lo[s * kWave + pos] = lo[s][u];
-              if (ANY64) q_hi[s * kWave + pos] = hi[ANY64 ? s : 0][u];
-            }
-          }
-        }
-        pos0 += __popcll(m0[u]);
+        const uint32_t m_hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(mine >> 32), u);
+        const uint32_t m_lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(mine), u);
+        total += static_cast<uint32_t>(__popcll((static_cast<uint64_t>(m_hi) << 32) | m_lo));
       }
+    }
+
+    if (total0 > 0 && total0 <= kWave && (n_f > 1 || (APPEND && app_n < app.region_cap))) {
+      // Few survivors, compacted above, one lane each: gather their keys of
+      // the other columns and test those with every lane busy.
+      if (lane < U) fail[lane] = 0;
       // The LDS accesses of one wave execute in program order; the wave
       // barrier only keeps the compiler from moving them across.
       __builtin_amdgcn_wave_barrier();
-      const bool act = lane < total;
+      const bool act = lane < total0;
       const uint32_t idx = act ? lane : 0;
-      bool ok = act;
+      const uint32_t tag = q_tag[idx];
+      const uint64_t row = base_row + (tag >> 6) * 64 + (tag & 63);
       uint32_t klo[kMaxProbe] = {}, khi[kMaxProbe] = {};
+      if (APPEND) {
+        klo[0] = q_lo[idx];
+        khi[0] = KEY64 ? q_hi[idx] : static_cast<uint32_t>(static_cast<int32_t>(klo[0]) >> 31);
+      }
 #pragma unroll
-      for (int s = APPEND ? 0 : 1; s < kMaxProbe; s++) {
+      for (int s = 1; s < kMaxProbe; s++)
+        if (s < static_cast<int>(n_f)) gather_key(sl[s].keys, sl[s].key64, row, klo[s], khi[s]);
+      bool ok = act;
+#pragma unroll
+      for (int s = 1; s < kMaxProbe; s++) {
         if (s < static_cast<int>(n_f)) {
-          klo[s] = q_lo[s * kWave + idx];
-          khi[s] = ANY64 ? q_hi[s * kWave + idx] : 0;
-          if (s > 0) {
-            uint32_t h1, h2;
-            hash_parts(klo[s], khi[s], ANY64 && sl[s].key64, h1, h2);
-            ok = ok && slot_has<K, STAGED>(sl[s], lds_filters + lds_off[s], h1, h2, k, lg);
-          }
+          uint32_t h1, h2;
+          hash_parts(klo[s], khi[s], sl[s].key64, h1, h2);
+          ok = ok && slot_has<K, STAGED>(sl[s], lds_filters + lds_off[s], h1, h2, k, lg);
         }
       }
-      const uint32_t tag = q_tag[idx];
-      if (act && !ok) atomicOr(&fail_mask[tag >> 6], 1ull << (tag & 63));
+      const uint64_t failed = __ballot(act && !ok);
+      if (failed) {
+        if (act && !ok) atomicOr(&fail[tag >> 6], 1ull << (tag & 63));
+        __builtin_amdgcn_wave_barrier();
+        if (lane < U) mine &= ~fail[lane];
+        total -= static_cast<uint32_t>(__popcll(failed));
+      }
       if (APPEND) {
         // The final survivors append their keys: one store per column.
         const uint64_t fin = __ballot(ok);
-        const uint32_t pos = app_n + static_cast<uint32_t>(__popcll(fin & ((1ull << lane) - 1)));
+        const uint32_t pos =
+            app_n + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(fin >> 32),
+                                              __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(fin), 0));
         if (ok && pos < app.region_cap) {
-          const uint64_t row = base_row + (tag >> 6) * 64 + (tag & 63);
 #pragma unroll
-          for (int c = 0; c < kMaxAppend; c++)
-            if (c < static_cast<int>(app.n_cols)) append_key<ANY64>(app, c, app_slot[c], klo, khi, row, app_base + pos);
+          for (int c = 0; c < kMaxAppend; c++) {
+            if (c < static_cast<int>(app.n_cols)) {
+              uint32_t alo = 0, ahi = 0;
+              bool have = false;
+#pragma unroll
+              for (int q = 0; q < kMaxProbe; q++)
+                if (app_slot[c] == q) {
+                  alo = klo[q];
+                  ahi = khi[q];
+                  have = true;
+                }
+              if (!have) gather_key(app.src[c], app.key64[c], row, alo, ahi);
+              if (app.key64[c])
+                static_cast<uint64_t *>(app.dst[c])[app_base + pos] = (static_cast<uint64_t>(ahi) << 32) | alo;
+              else
+                static_cast<uint32_t *>(app.dst[c])[app_base + pos] = alo;
+            }
+          }
         }
         app_n += static_cast<uint32_t>(__popcll(fin));
         appended = true;
       }
       __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int u = 0; u < U; u++) m0[u] &= ~uniform64(fail_mask[u]);
-      __builtin_amdgcn_wave_barrier();
     }
 
-    if (APPEND && !appended && total > 0) {
+    if (APPEND && !appended && total0 > 0) {
       // Too many first-filter survivors to compact (or a full region): the
       // region is marked as overflowed, and builds walk its bitmap words
       // (dense survivors read coalesced anyway).
       app_n = app.region_cap + 1;
     }
 
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      const uint64_t w = w0 + u;
-      if (lane == 0 && w < n_words) bitmap[w] = m0[u];
-      cnt += __popcll(m0[u]);
-    }
+    if (lane < U && w0 + lane < n_words) bitmap[w0 + lane] = mine;
+    cnt += total;
   }
   if (APPEND && lane == 0) app.counts[global_wave(vg)] = app_n;
   return cnt;
 }
 
-template <int B, int K, bool ANY64, bool APPEND>
+template <int B, int K, bool APPEND>
 __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint32_t lg_rt, uint64_t n_rows,
                                            uint64_t *__restrict__ bitmap, unsigned long long *count,
                                            uint32_t lds_filter_words, uint32_t input_all, uint32_t keep_order,
@@ -263,7 +307,7 @@ __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint
   extern __shared__ __align__(16) uint32_t lds[];
   const uint32_t lg = block_log2<B>(lg_rt);
   const uint32_t W = 1u << (lg - 5);
-  constexpr int kSliceWords = probe_slice_words<ANY64>();
+  constexpr int kSliceWords = probe_slice_words();
   __shared__ uint32_t s_ord[kMaxProbe];
   __shared__ uint32_t s_nb[kMaxProbe];
   __shared__ uint32_t s_off[kMaxProbe];
@@ -342,7 +386,7 @@ __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint
     sl[j].key64 = f.key64;
     off[j] = __builtin_amdgcn_readfirstlane(s_off[jj]);
   }
-  // Appended column c comes from slot app_slot[c]'s registers (-1: loaded).
+  // Appended column c comes from slot app_slot[c]'s registers (-1: gathered).
   int app_slot[kMaxAppend];
 #pragma unroll
   for (int c = 0; c < kMaxAppend; c++) {
@@ -357,25 +401,34 @@ __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint
   // each slice's 64-bit failure masks stay 8-byte aligned.
   uint32_t *slice = lds + lds_filter_words + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) * kSliceWords;
   int64_t cnt;
-  if (staged)
-    cnt = probe_loop<K, ANY64, true, APPEND>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
-                                             app_slot, vg);
-  else
-    cnt = probe_loop<K, ANY64, false, APPEND>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
+  if (sl[0].key64) {
+    if (staged)
+      cnt = probe_loop<K, true, true, APPEND>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
                                               app_slot, vg);
+    else
+      cnt = probe_loop<K, true, false, APPEND>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
+                                               app_slot, vg);
+  } else {
+    if (staged)
+      cnt = probe_loop<K, false, true, APPEND>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
+                                               app_slot, vg);
+    else
+      cnt = probe_loop<K, false, false, APPEND>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
+                                                app_slot, vg);
+  }
   block_count_add(cnt, &s_cnt, count);
 }
 
-template <int B, int K, bool ANY64, bool APPEND>
+template <int B, int K, bool APPEND>
 __global__ void __launch_bounds__(kProbeThreads)
     k_probe(FilterSet fs, uint32_t k, uint32_t lg, uint64_t n_rows, uint64_t *__restrict__ bitmap,
             unsigned long long *count, uint32_t lds_filter_words, uint32_t input_all, uint32_t keep_order,
             uint32_t *status, AppendSet app) {
-  probe_body<B, K, ANY64, APPEND>(fs, k, lg, n_rows, bitmap, count, lds_filter_words, input_all, keep_order,
-                                  status, app, whole_grid());
+  probe_body<B, K, APPEND>(fs, k, lg, n_rows, bitmap, count, lds_filter_words, input_all, keep_order, status, app,
+                           whole_grid());
 }
 
-// Launches k_probe<B, K, *, *> for one ProbeLaunch.
+// Launches k_probe<B, K, *> for one ProbeLaunch.
 template <int B, int K>
 hipError_t launch_probe_kernel(const ProbeLaunch &pl, hipStream_t s) {
   auto launch = [&](auto kern) -> hipError_t {
@@ -385,9 +438,8 @@ hipError_t launch_probe_kernel(const ProbeLaunch &pl, hipStream_t s) {
                        pl.bitmap, pl.count, pl.lds_filter_words, pl.input_all, pl.keep_order, pl.status, pl.app);
     return hipGetLastError();
   };
-  if (pl.app.n_cols)
-    return pl.any64 ? launch(k_probe<B, K, true, true>) : launch(k_probe<B, K, false, true>);
-  return pl.any64 ? launch(k_probe<B, K, true, false>) : launch(k_probe<B, K, false, false>);
+  if (pl.app.n_cols) return launch(k_probe<B, K, true>);
+  return launch(k_probe<B, K, false>);
 }
 
 }  // namespace pt

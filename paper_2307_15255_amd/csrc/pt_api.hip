@@ -78,7 +78,9 @@ hipEvent_t take_event() {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  // timing only: no system-scope fence, so the events add no cache flush
+  // (and no bubble) between the launches they bracket
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -925,7 +927,6 @@ constexpr uint64_t kBatchProbeLdsBytes = 64 * 1024;
 struct BatchLaunch {
   LaunchKind kind;
   uint32_t block_bits = 0, k = 0;
-  bool any64 = false;
   uint64_t tasks_off = 0, first_off = 0;  // workspace offsets
   uint32_t n = 0, grid = 0, lds_words = 0;
   uint32_t pass = 0;                      // 1 forward, 2 backward (probes, builds)
@@ -1083,7 +1084,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
     }
   }
   for (uint32_t i = 0; i < n_problems; i++) cur[i].assign(bp.plans[i].n_t, 0);
-  using Key = std::tuple<uint32_t, uint32_t, bool>;  // block_bits, k, any64
+  using Key = std::pair<uint32_t, uint32_t>;  // block_bits, k
   for (uint32_t p = 0; p < 2; p++) {
     for (uint32_t L = 0; L <= max_lvl[p]; L++) {
       // Probes: one launch per (parameters, key width, chunk of kMaxProbe).
@@ -1101,7 +1102,6 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
           bp.rows_probed += pr.tables[v].n_rows;
           for (uint32_t c0 = 0, chunk = 0; c0 < in.size(); c0 += kMaxProbe, chunk++) {
             ProbeTask pt{};
-            bool any64 = false;
             uint64_t need = 0;
             for (uint32_t j = c0; j < in.size() && pt.fs.n < static_cast<uint32_t>(kMaxProbe); j++) {
               const uint32_t e = in[j];
@@ -1109,7 +1109,6 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
               FilterRef r = filter_ref(i, p, e, v);
               r.sel = count_ptr(i, cur[i][from], from);
               r.rows = pr.tables[from].n_rows;
-              any64 = any64 || r.key64;
               need += r.cap_words;
               pt.fs.f[pt.fs.n++] = r;
             }
@@ -1119,12 +1118,11 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
             pt.count = last ? count_ptr(i, p + 1, v) : nullptr;
             pt.input_all = 0;
             const uint64_t n_words = (pt.n_rows + 63) / 64;
-            const Key key{pr.params.block_bits, pr.params.k, any64};
+            const Key key{pr.params.block_bits, pr.params.k};
             LaunchDraft &d = probes[{key, chunk}];
             d.l.kind = kProbe;
             d.l.block_bits = pr.params.block_bits;
             d.l.k = pr.params.k;
-            d.l.any64 = any64;
             d.add(pt, clamp_u32((n_words + kBatchWordsPerBlock - 1) / kBatchWordsPerBlock, 1, 4096));
             d.l.pass = p + 1;
             d.l.rows += pt.n_rows;
@@ -1144,9 +1142,8 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
           if (kv.first.second != chunk) continue;
           any = true;
           LaunchDraft d = std::move(kv.second);
-          const bool any64 = std::get<2>(kv.first.first);
           const uint64_t lds_cap = std::min<uint64_t>(lds_max, kBatchProbeLdsBytes);
-          const uint64_t room = lds_cap > probe_queue_bytes(any64) ? (lds_cap - probe_queue_bytes(any64)) / 4 : 0;
+          const uint64_t room = lds_cap > probe_queue_bytes() ? (lds_cap - probe_queue_bytes()) / 4 : 0;
           d.l.lds_words = static_cast<uint32_t>(std::min<uint64_t>(room, probe_need[kv.first]));
           d.l.n = static_cast<uint32_t>(d.first.size() - 1);
           bp.drafts.push_back(std::move(d));
@@ -1319,7 +1316,7 @@ static pt_status enqueue_batch(const pt_batch &b, hipStream_t s, bool timed) {
                                l.grid, l.lds_words, status, s);
         break;
       case kProbe:
-        e = launch_probe_batch(l.block_bits, l.k, l.any64, reinterpret_cast<const ProbeTask *>(tasks), first,
+        e = launch_probe_batch(l.block_bits, l.k, reinterpret_cast<const ProbeTask *>(tasks), first,
                                l.n, l.grid, l.lds_words, status, s);
         break;
       case kCopy:
@@ -1373,7 +1370,7 @@ pt_status pt_batch_prepare_async(uint32_t n_problems, const pt_problem *problems
   // Raise the LDS limits now: the capture must not change kernel attributes.
   for (const LaunchDraft &d : bp.drafts) {
     if (d.l.kind != kBuild && d.l.kind != kProbe) continue;
-    st = check_hip(prepare_batch_kernels(d.l.block_bits, d.l.k, d.l.any64), "batch kernel setup");
+    st = check_hip(prepare_batch_kernels(d.l.block_bits, d.l.k), "batch kernel setup");
     if (st != PT_OK) return st;
   }
   char *ws = static_cast<char *>(d_ws);

@@ -172,14 +172,17 @@ __device__ __forceinline__ void hash_key(uint64_t x, uint32_t &h1, uint32_t &h2)
 }
 
 // The filter hash of an int32 key: the same value as hash_key on its
-// sign-extended image, with the sign correction done by a mask instead of
-// a second full multiply.
+// sign-extended image x. With A = A_hi * 2^32 + A_lo and A_lo < 2^31, the
+// signed product x * A_lo is exact in 64 bits, and x * A mod 2^64 has
+// high word hi(x * A_lo) + lo * A_hi mod 2^32 (x and lo agree mod 2^32):
+// one signed and one unsigned multiply-add instead of three multiplies and a
+// sign correction.
 __device__ __forceinline__ void hash_key32(uint32_t lo, uint32_t &h1, uint32_t &h2) {
   constexpr uint32_t a_lo = static_cast<uint32_t>(kHashMul);
   constexpr uint32_t a_hi = static_cast<uint32_t>(kHashMul >> 32);
-  const uint64_t p = static_cast<uint64_t>(lo) * a_lo;
-  const uint32_t fix = static_cast<uint32_t>(static_cast<int32_t>(lo) >> 31) & (0u - a_lo);
-  const uint32_t hi = static_cast<uint32_t>(p >> 32) + lo * a_hi + fix;
+  static_assert(a_lo < 0x80000000u, "the low word of the multiplier must be a positive int32");
+  const int64_t p = static_cast<int64_t>(static_cast<int32_t>(lo)) * static_cast<int64_t>(a_lo);
+  const uint32_t hi = static_cast<uint32_t>(static_cast<uint64_t>(p) >> 32) + lo * a_hi;
   uint32_t t = static_cast<uint32_t>(p) ^ hi;
   t ^= t >> 16;
   h1 = hi;

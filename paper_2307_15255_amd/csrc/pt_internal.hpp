@@ -153,7 +153,6 @@ struct ProbeLaunch {
   AppendSet app;
   uint32_t grid;
   uint64_t lds_bytes;
-  bool any64;
 };
 // One probe kernel, specialised for B = 512 and k = 3 (k_probe_512.hip) or
 // generic in B and k (k_probe_gen.hip).
@@ -242,15 +241,15 @@ hipError_t launch_size_batch(const SizeTask *tasks, const uint32_t *first, uint3
 hipError_t launch_build_batch(uint32_t block_bits, uint32_t k, const BuildTask *tasks, const uint32_t *first,
                               uint32_t n, uint32_t grid, uint32_t lds_words, uint32_t *status, hipStream_t s);
 // lds_filter_words: LDS words per workgroup for staged filters.
-hipError_t launch_probe_batch(uint32_t block_bits, uint32_t k, bool any64, const ProbeTask *tasks,
+hipError_t launch_probe_batch(uint32_t block_bits, uint32_t k, const ProbeTask *tasks,
                               const uint32_t *first, uint32_t n, uint32_t grid, uint32_t lds_filter_words,
                               uint32_t *status, hipStream_t s);
 hipError_t launch_copy_pairs(const CopyPair *pairs, uint32_t n, hipStream_t s);
 // Bytes of LDS a probe workgroup needs besides its staged filters.
-uint64_t probe_queue_bytes(bool any64);
+uint64_t probe_queue_bytes();
 // Kernels whose LDS limit must be raised before a batch is captured.
-hipError_t prepare_batch_kernels(uint32_t block_bits, uint32_t k, bool any64);
-hipError_t prepare_probe_batch_kernel(uint32_t block_bits, uint32_t k, bool any64);
+hipError_t prepare_batch_kernels(uint32_t block_bits, uint32_t k);
+hipError_t prepare_probe_batch_kernel(uint32_t block_bits, uint32_t k);
 hipError_t prepare_build_batch_kernel(uint32_t block_bits, uint32_t k);
 
 }  // namespace pt

@@ -243,7 +243,7 @@ class GpuExecutor:
             bt.run(stream=s, eager=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        return ("batch", bt, ev, qs)
+        return ("batch", bt, ev, qs, s)
 
     def launch_single(self, q: Query):
         torch = self.torch
@@ -253,18 +253,22 @@ class GpuExecutor:
             tr.run(stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
-        return ("single", tr, ev, [q])
+        return ("single", tr, ev, [q], s)
 
     def done(self, h) -> bool:
         return h[2].query()
 
     def finish(self, h) -> None:
-        kind, obj, _, qs = h
+        kind, obj, _, qs, stream = h
         if self.keep:
-            if kind == "batch":
-                for i, q in enumerate(qs):
-                    self.results[q.qid] = ([b.clone() for b in obj.bitmaps[i]], obj.counts[i].clone())
-            else:
-                self.results[qs[0].qid] = ([b.clone() for b in obj.bitmaps], obj.counts.clone())
+            # Copied on the stream the results were made on: their blocks go
+            # back to that stream's pool when `obj` is dropped, so the next
+            # launch there cannot reuse them before the copies have run.
+            with self.torch.cuda.stream(stream):
+                if kind == "batch":
+                    for i, q in enumerate(qs):
+                        self.results[q.qid] = ([b.clone() for b in obj.bitmaps[i]], obj.counts[i].clone())
+                else:
+                    self.results[qs[0].qid] = ([b.clone() for b in obj.bitmaps], obj.counts.clone())
         if kind == "batch":
             obj.close()
