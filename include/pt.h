@@ -264,6 +264,19 @@ pt_status pt_compact_workspace_size(uint64_t n_rows, size_t *bytes);
 pt_status pt_compact(const uint64_t *d_bitmap, uint64_t n_rows, uint32_t *d_idx,
                      uint64_t *d_count, void *d_ws, size_t ws_bytes, pt_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * compaction as pt_compact, with the same results, but without a workspace.
+ * Its partial counts live in a static device array of the library (256 KiB
+ * per GPU, held until the process ends), so n_rows is at most 2^31; larger
+ * inputs are rejected with PT_EINVAL before anything is queued. It allocates
+ * nothing: the array's address is looked up once per device, on the first
+ * call there. Every call on one GPU shares that array, so calls that overlap
+ * on a GPU (on different streams, or from different threads) race; order
+ * them on one stream. */
+pt_status pt_compact_noalloc(const uint64_t *d_bitmap, uint64_t n_rows, uint32_t *d_idx,
+                             uint64_t *d_count, pt_stream stream);
+
 /* Bytes of workspace pt_transfer needs for this graph, these tables' row
  * counts and these parameters (every filter at its largest possible size,
  * plus counters). */

@@ -218,7 +218,33 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// The allocation-free compaction keeps its partial counts here: one array
+// per GPU, alive until the process ends. In host code `scratch` only names
+// the symbol; its device address comes from hipGetSymbolAddress.
+static_assert(kStaticCompactRows % (64 * kCompactWordsPerBlock) == 0, "whole partials");
+constexpr uint64_t kStaticCompactPartials = kStaticCompactRows / 64 / kCompactWordsPerBlock;
+static __device__ __align__(256) uint64_t scratch[kStaticCompactPartials];
+
 }  // namespace
+
+hipError_t static_compact_scratch(uint64_t **out) {
+  static std::mutex mu;
+  static uint64_t *addr[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    // once per device, with that device current: its own copy of the array
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<uint64_t *>(p);
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
 
 // ------------------------------------------------------------- helpers
 

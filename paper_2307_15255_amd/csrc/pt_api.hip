@@ -669,6 +669,22 @@ pt_status pt_compact(const uint64_t *d_bitmap, uint64_t n_rows, uint32_t *d_idx,
                    "compact launch");
 }
 
+pt_status pt_compact_noalloc(const uint64_t *d_bitmap, uint64_t n_rows, uint32_t *d_idx, uint64_t *d_count,
+                             pt_stream stream) {
+  if (n_rows > kStaticCompactRows)
+    return fail(PT_EINVAL,
+                "pt_compact_noalloc: %llu rows exceed its static scratch (at most 2^31 rows); "
+                "use pt_compact with a workspace",
+                (unsigned long long)n_rows);
+  if (!d_count) return fail(PT_EINVAL, "d_count is NULL");
+  if (n_rows > 0 && (!d_bitmap || !d_idx)) return fail(PT_EINVAL, "d_bitmap or d_idx is NULL");
+  uint64_t *partials = nullptr;
+  pt_status st = check_hip(static_compact_scratch(&partials), "static scratch address");
+  if (st != PT_OK) return st;
+  return check_hip(launch_compact(d_bitmap, n_rows, d_idx, d_count, partials, reinterpret_cast<hipStream_t>(stream)),
+                   "compact launch");
+}
+
 pt_status pt_transfer_workspace_size(const pt_graph *graph, const pt_table *tables,
                                      const pt_params *params, size_t *bytes) {
   if (!bytes) return fail(PT_EINVAL, "bytes is NULL");

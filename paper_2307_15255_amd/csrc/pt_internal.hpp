@@ -116,6 +116,11 @@ hipError_t launch_copy_counts(const uint64_t *src, const uint32_t *slot, uint32_
 hipError_t launch_compact(const uint64_t *bitmap, uint64_t n_rows, uint32_t *idx, uint64_t *count,
                           uint64_t *partials, hipStream_t s);
 uint64_t compact_partials(uint64_t n_rows);
+// Rows the allocation-free compaction takes at most, and the device address
+// of its partial counts on the current device (a static device array, found
+// once per device).
+constexpr uint64_t kStaticCompactRows = 1ull << 31;
+hipError_t static_compact_scratch(uint64_t **out);
 // Sizes filters from *count (n_rows when count is NULL) and zeroes their
 // blocks, except when a partitioned build with entries_cap entries (0:
 // none) will write every block: that is decided on the device from *count.

@@ -96,6 +96,7 @@ def _load() -> C.CDLL:
         "pt_bloom_probe": ([u32, C.POINTER(pt_column), C.POINTER(pt_bloom), u64, vp, vp, vp], st),
         "pt_compact_workspace_size": ([u64, sizep], st),
         "pt_compact": ([vp, u64, vp, vp, vp, C.c_size_t, vp], st),
+        "pt_compact_noalloc": ([vp, u64, vp, vp, vp], st),
         "pt_transfer_workspace_size": ([C.POINTER(pt_graph), C.POINTER(pt_table),
                                         C.POINTER(pt_params), sizep], st),
         "pt_transfer": ([C.POINTER(pt_graph), C.POINTER(pt_table), C.POINTER(pt_pred), u32,
@@ -121,7 +122,7 @@ def _load() -> C.CDLL:
 
 _lib = _load()
 EXPORTS = ("pt_version", "pt_last_error", "pt_check_status", "pt_local_filter", "pt_bloom_capacity", "pt_bloom_build",
-           "pt_bloom_probe", "pt_compact_workspace_size", "pt_compact", "pt_transfer_workspace_size",
+           "pt_bloom_probe", "pt_compact_workspace_size", "pt_compact", "pt_compact_noalloc", "pt_transfer_workspace_size",
            "pt_transfer", "pt_transfer_filter", "pt_batch_workspace_size", "pt_batch_prepare",
            "pt_batch_prepare_async", "pt_batch_run",
            "pt_batch_info", "pt_batch_free", "pt_transfer_batch", "pt_profile_enable", "pt_profile_read")
@@ -242,6 +243,12 @@ def pt_compact(bitmap: torch.Tensor, n_rows: int, idx: torch.Tensor, count: torc
                ws: torch.Tensor, stream=None) -> None:
     _check(_lib.pt_compact(_ptr(bitmap), n_rows, _ptr(idx), _ptr(count), _ptr(ws), ws.numel(),
                            _stream(stream)))
+
+
+def pt_compact_noalloc(bitmap: torch.Tensor, n_rows: int, idx: torch.Tensor, count: torch.Tensor,
+                       stream=None) -> None:
+    """pt_compact without a workspace (static device scratch; n_rows <= 2^31)."""
+    _check(_lib.pt_compact_noalloc(_ptr(bitmap), n_rows, _ptr(idx), _ptr(count), _stream(stream)))
 
 
 def pt_profile_enable(on: bool | int) -> None:

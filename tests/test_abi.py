@@ -138,3 +138,11 @@ def test_edge_flags_are_reserved(ptlib):
 
 def test_check_status_rejects_null(ptlib):
     assert ptlib.lib().pt_check_status(None, None) == ptlib.PT_EINVAL
+
+
+def test_compact_noalloc_rejects_inputs_beyond_its_scratch(ptlib):
+    """Host-side checks of the allocation-free compaction: nothing is queued."""
+    lib = ptlib.lib()
+    assert lib.pt_compact_noalloc(None, (1 << 31) + 1, None, None, None) == ptlib.PT_EINVAL
+    assert "2^31" in lib.pt_last_error().decode()
+    assert lib.pt_compact_noalloc(None, 10, None, None, None) == ptlib.PT_EINVAL  # NULL count
