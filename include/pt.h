@@ -88,6 +88,10 @@ typedef enum pt_status {
  * pt_check_status() reads and clears the word. */
 #define PT_STATUS_FILTER_OVERFLOW 1u
 #define PT_STATUS_ENTRIES_OVERFLOW 2u
+/*   WAIT_TIMEOUT      a batch's work item waited longer than its limit for
+ *                     the steps it depends on and ran without them (the
+ *                     batch's results are then not to be trusted) */
+#define PT_STATUS_WAIT_TIMEOUT 4u
 
 typedef enum pt_dtype { PT_I32 = 0, PT_I64 = 1 } pt_dtype;
 
@@ -360,6 +364,16 @@ pt_status pt_batch_run(pt_batch *batch, pt_stream stream, uint32_t flags);
 /* Kernel launches in one run of the batch, and rows it probes (the sum
  * over probe steps of the probed table's rows). */
 pt_status pt_batch_info(const pt_batch *batch, uint32_t *n_launches, uint64_t *rows_probed);
+
+/* Profiling of a batch prepared while the environment variable
+ * PT_BATCH_TIMELINE is 1 (the workspace size query must see it too): after
+ * a run, waits for the device and copies up to max_items records of four
+ * uint64 each - the item's start and end on the device's wall clock, its
+ * task kind and its phase - into `out`, sets *n_items, and the clock's ticks
+ * per millisecond into *ticks_per_ms (may be NULL). PT_EUNSUPPORTED for a
+ * batch prepared without it. */
+pt_status pt_batch_timeline(const pt_batch *batch, uint64_t *out, uint32_t max_items, uint32_t *n_items,
+                            uint32_t *ticks_per_ms);
 
 /* Frees the handle and its graph (after the last run has completed). */
 void pt_batch_free(pt_batch *batch);

@@ -173,16 +173,19 @@ __device__ __forceinline__ uint32_t part_blocks(const FilterRef &f, uint32_t lg,
   return clamp_blocks(*f.nb, cap_blocks, nullptr);
 }
 
+// target_buckets: how many (filter, tile) buckets the build aims for - many
+// for one large build that must fill the device by itself, few for the
+// builds of a batch, which fill it together (fewer, larger tiles).
 __device__ __forceinline__ PartGeo part_geo(const FilterSet &fs, uint32_t lg, uint32_t bits_per_key,
                                             const uint64_t *count, uint64_t n_rows, uint64_t entries_cap,
-                                            bool from_count) {
+                                            bool from_count, uint32_t target_buckets = kTargetBuckets) {
   PartGeo g{};
   g.n_sel = count ? *count : n_rows;
   uint64_t all_blocks = 0;
   for (uint32_t i = 0; i < fs.n; i++) all_blocks += part_blocks(fs.f[i], lg, bits_per_key, g.n_sel, from_count);
   // Tiles of at most 64 KB, small enough that the group has about
-  // kTargetBuckets of them (the fill kernel runs one workgroup per tile).
-  uint64_t tb = (all_blocks + kTargetBuckets - 1) / kTargetBuckets;
+  // target_buckets of them (the fill step runs one workgroup per tile).
+  uint64_t tb = (all_blocks + target_buckets - 1) / target_buckets;
   const uint64_t max_tb = kTileWords >> (lg - 5);
   g.tile_blocks = static_cast<uint32_t>(tb < 1 ? 1 : (tb > max_tb ? max_tb : tb));
   uint64_t buckets = 0;

@@ -117,66 +117,6 @@ __global__ void __launch_bounds__(kWideThreads)
   }
 }
 
-// Many builds in one launch (one task each, see VGrid). Filters that fit the
-// launch's LDS are built in private copies and merged into the (zeroed)
-// filters: stored when the task has one workgroup, OR-ed with atomics
-// otherwise. Larger ones are built with global atomics.
-template <int B, int K>
-__global__ void __launch_bounds__(kBatchThreads)
-    k_build_batch(const BuildTask *__restrict__ tasks, const uint32_t *__restrict__ first, uint32_t n, uint32_t k,
-                  uint32_t lg_rt, uint32_t lds_words, uint32_t *status) {
-  extern __shared__ __align__(16) uint32_t lds[];
-  const uint32_t lg = block_log2<B>(lg_rt);
-  const uint32_t W = 1u << (lg - 5);
-  VGrid vg;
-  const BuildTask &t = tasks[task_of(first, n, vg)];
-  const FilterSet &fs = t.fs;
-  const AppendSet none{};
-  const uint32_t total = lds_total(fs, lg, lds_words);
-  if (total == 0) {
-    // atomic OR without a prior read: nothing waits on the result, so a
-    // wave's inserts overlap
-    for (uint32_t i = 0; i < fs.n; i++) {
-      const FilterRef &f = fs.f[i];
-      const uint32_t nb = filter_blocks(f, lg, status);
-      uint32_t *words = f.words;
-      for_each_key<false>(f, none, t.n_rows, t.bitmap, t.seg_words, vg,
-                          [&](uint32_t h1, uint32_t h2) { or_bits<K>(words, nb, k, h1, h2, lg); });
-    }
-    return;
-  }
-  for (uint32_t j = threadIdx.x; j < total; j += blockDim.x) lds[j] = 0;
-  __syncthreads();
-  uint32_t off = 0;
-  for (uint32_t i = 0; i < fs.n; i++) {
-    const FilterRef &f = fs.f[i];
-    const uint32_t nb = filter_blocks(f, lg, status);
-    uint32_t *mine = lds + off;
-    for_each_key<false>(f, none, t.n_rows, t.bitmap, t.seg_words, vg,
-                        [&](uint32_t h1, uint32_t h2) { insert_lds<K>(mine, nb, k, h1, h2, lg); });
-    off += nb * W;
-  }
-  __syncthreads();
-  const bool alone = vg.blocks == 1;
-  off = 0;
-  for (uint32_t i = 0; i < fs.n; i++) {
-    uint32_t *words = fs.f[i].words;
-    const uint32_t nw = filter_blocks(fs.f[i], lg, nullptr) * W;
-    const uint32_t *mine = lds + off;
-    for (uint32_t j = threadIdx.x; j < nw; j += blockDim.x) {
-      const uint32_t v = mine[j];
-      if (alone) words[j] = v;
-      else if (v) atomicOr(words + j, v);
-    }
-    off += nw;
-  }
-}
-
-const void *build_batch_kernel(uint32_t block_bits, uint32_t k) {
-  if (block_bits == 512 && k == 3) return reinterpret_cast<const void *>(k_build_batch<512, 3>);
-  return reinterpret_cast<const void *>(k_build_batch<0, 0>);
-}
-
 }  // namespace
 
 uint64_t build_lds_words() {
@@ -251,24 +191,6 @@ hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, 
   if (gx > 1024) gx = 1024;
   hipLaunchKernelGGL(k_build_reduce, dim3(static_cast<uint32_t>(gx), fs.n), dim3(kWideThreads), 0, s, fs, lg,
                      scratch->copies, n_parts, cw);
-  return hipGetLastError();
-}
-
-hipError_t prepare_build_batch_kernel(uint32_t block_bits, uint32_t k) {
-  const uint64_t lds_max = static_cast<uint64_t>(device_info().max_lds_block) - 1024;
-  return allow_lds(build_batch_kernel(block_bits, k), lds_max);
-}
-
-hipError_t launch_build_batch(uint32_t block_bits, uint32_t k, const BuildTask *tasks, const uint32_t *first,
-                              uint32_t n, uint32_t grid, uint32_t lds_words, uint32_t *status, hipStream_t s) {
-  if (n == 0 || grid == 0) return hipSuccess;
-  const uint32_t lg = log2_of(static_cast<int>(block_bits));
-  if (lg == 0) return hipErrorInvalidValue;
-  auto kern = (block_bits == 512 && k == 3) ? k_build_batch<512, 3> : k_build_batch<0, 0>;
-  hipError_t e = allow_lds(reinterpret_cast<const void *>(kern), static_cast<uint64_t>(lds_words) * 4);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBatchThreads), static_cast<uint64_t>(lds_words) * 4, s, tasks, first,
-                     n, k, lg, lds_words, status);
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <mutex>
 
 #include "build_impl.hpp"
+#include "local_impl.hpp"
 
 namespace pt {
 
@@ -27,79 +28,10 @@ __global__ void __launch_bounds__(kThreads) k_fill_all(uint64_t *bitmap, uint64_
   if (count && blockIdx.x == 0 && threadIdx.x == 0) *count = n_rows;
 }
 
-// ---------------------------------------------------------- local filter
-//
-// Each wave takes seg_words (1..64) consecutive words, builds word j with the
-// ballot of step j, keeps it in lane j, and stores the segment with one
-// coalesced store. Eight words are evaluated per step so their loads
-// overlap.
-
-__device__ __forceinline__ bool pred_holds(uint32_t op, int64_t v, int64_t lo, int64_t hi) {
-  switch (op) {
-    case PT_LT: return v < lo;
-    case PT_LE: return v <= lo;
-    case PT_GT: return v > lo;
-    case PT_GE: return v >= lo;
-    case PT_EQ: return v == lo;
-    case PT_NE: return v != lo;
-    default: return lo <= v && v <= hi;
-  }
-}
-
-__device__ __forceinline__ void local_body(const PredSet &ps, uint64_t n_rows, uint64_t *__restrict__ bitmap,
-                                           unsigned long long *count, uint32_t seg_words, const VGrid &vg) {
-  constexpr int T = 8;
-  __shared__ unsigned long long s_cnt;
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
-  const uint32_t lane = lane_id();
-  const uint64_t n_words = (n_rows + 63) / 64;
-  uint64_t cnt = 0;
-  for (uint64_t seg = global_wave(vg); seg * seg_words < n_words; seg += wave_count(vg)) {
-    const uint64_t w_base = seg * seg_words;
-    const uint32_t n_j = static_cast<uint32_t>(n_words - w_base < seg_words ? n_words - w_base : seg_words);
-    uint64_t mine = 0;
-    for (uint32_t j0 = 0; j0 < n_j; j0 += T) {
-      bool keep[T];
-      uint64_t r[T];
-#pragma unroll
-      for (int t = 0; t < T; t++) {
-        const uint64_t row = (w_base + j0 + t) * 64 + lane;
-        keep[t] = j0 + t < n_j && row < n_rows;
-        r[t] = row < n_rows ? row : n_rows - 1;
-        if (ps.and_into && j0 + t < n_j) keep[t] = keep[t] && ((uniform64(bitmap[w_base + j0 + t]) >> lane) & 1);
-      }
-      for (uint32_t i = 0; i < ps.n; i++) {
-        const PredRef &p = ps.p[i];
-#pragma unroll
-        for (int t = 0; t < T; t++) {
-          const int64_t v = static_cast<int64_t>(load_key(p.col, p.col64, r[t]));
-          keep[t] = keep[t] && pred_holds(p.op, v, p.lo, p.hi);
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < T; t++) {
-        const uint64_t m = __ballot(keep[t]);
-        if (lane == j0 + t) mine = m;
-      }
-    }
-    if (lane < n_j) bitmap[w_base + lane] = mine;
-    cnt += __popcll(mine);
-  }
-  block_count_add(static_cast<int64_t>(wave_sum(cnt)), &s_cnt, count);
-}
-
 __global__ void __launch_bounds__(kWideThreads)
     k_local(PredSet ps, uint64_t n_rows, uint64_t *__restrict__ bitmap, unsigned long long *count,
             uint32_t seg_words) {
   local_body(ps, n_rows, bitmap, count, seg_words, whole_grid());
-}
-
-__global__ void __launch_bounds__(kBatchThreads)
-    k_local_batch(const LocalTask *__restrict__ tasks, const uint32_t *__restrict__ first, uint32_t n) {
-  VGrid vg;
-  const LocalTask &t = tasks[task_of(first, n, vg)];
-  local_body(t.ps, t.n_rows, t.bitmap, reinterpret_cast<unsigned long long *>(t.count), t.seg_words, vg);
 }
 
 // --------------------------------------------------------- size and zero
@@ -124,22 +56,6 @@ __global__ void __launch_bounds__(kThreads)
     f.words[i] = 0;
 }
 
-__global__ void __launch_bounds__(kBatchThreads)
-    k_size_batch(const SizeTask *__restrict__ tasks, const uint32_t *__restrict__ first, uint32_t n,
-                 uint32_t *status) {
-  VGrid vg;
-  const SizeTask &t = tasks[task_of(first, n, vg)];
-  const uint64_t W = t.block_bits / 32;
-  const bool lead = vg.block == 0 && threadIdx.x == 0;
-  const uint64_t nb = blocks_needed(t.count ? *t.count : t.n_rows, t.block_bits, t.bits_per_key, t.f.cap_words / W,
-                                    lead ? status : nullptr);
-  if (lead) *t.f.nb = nb;
-  const uint64_t words = nb * W;
-  for (uint64_t i = static_cast<uint64_t>(vg.block) * blockDim.x + threadIdx.x; i < words;
-       i += static_cast<uint64_t>(vg.blocks) * blockDim.x)
-    t.f.words[i] = 0;
-}
-
 // ------------------------------------------------------------- counters
 
 struct SlotTable {
@@ -149,11 +65,6 @@ struct SlotTable {
 __global__ void k_copy_counts(const uint64_t *src, SlotTable t, uint32_t n, uint64_t *dst) {
   const uint32_t i = threadIdx.x;
   if (i < n) dst[i] = src[t.slot[i]];
-}
-
-__global__ void k_copy_pairs(const CopyPair *__restrict__ pairs, uint32_t n) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) *pairs[i].dst = *pairs[i].src;
 }
 
 // -------------------------------------------------------------- compact
@@ -345,32 +256,6 @@ hipError_t launch_compact(const uint64_t *bitmap, uint64_t n_rows, uint32_t *idx
   hipLaunchKernelGGL(k_compact_write, dim3(static_cast<uint32_t>(n_parts)), dim3(kThreads), 0, s, bitmap, n_words,
                      n_rows, partials, idx);
   return hipGetLastError();
-}
-
-hipError_t launch_local_batch(const LocalTask *tasks, const uint32_t *first, uint32_t n, uint32_t grid,
-                              hipStream_t s) {
-  if (n == 0 || grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_local_batch, dim3(grid), dim3(kBatchThreads), 0, s, tasks, first, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_size_batch(const SizeTask *tasks, const uint32_t *first, uint32_t n, uint32_t grid,
-                             uint32_t *status, hipStream_t s) {
-  if (n == 0 || grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_size_batch, dim3(grid), dim3(kBatchThreads), 0, s, tasks, first, n, status);
-  return hipGetLastError();
-}
-
-hipError_t launch_copy_pairs(const CopyPair *pairs, uint32_t n, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_pairs, dim3((n + 255) / 256), dim3(256), 0, s, pairs, n);
-  return hipGetLastError();
-}
-
-hipError_t prepare_batch_kernels(uint32_t block_bits, uint32_t k) {
-  hipError_t e = prepare_build_batch_kernel(block_bits, k);
-  if (e != hipSuccess) return e;
-  return prepare_probe_batch_kernel(block_bits, k);
 }
 
 }  // namespace pt

@@ -1,0 +1,149 @@
+// part_impl.hpp - bodies of the partitioned build of Bloom filters too
+// large for LDS (Sec. 2.1 and Sec. 3.2 of the paper: the outgoing filters of
+// a table receive the keys of its selected rows), over a (virtual) grid:
+// shared by the partitioned-build kernels and the batch kernel.
+//
+// Each filter's blocks are cut into tiles of at most 64 KB, and every
+// (filter, tile) pair is a bucket (buckets of filter i follow those of
+// filters < i).
+//   count    each workgroup walks its rows and histograms their bucket
+//            in LDS, then stores its histogram row;
+//   scan     per bucket, an exclusive scan over the workgroups' counts, then
+//            one scan over the bucket totals: every (workgroup, bucket) gets
+//            its own range of the entry buffer;
+//   scatter  the same walk again (same grid, so the same rows per
+//            workgroup) writes each entry - block within the tile and H2 -
+//            at its range's next slot (LDS cursors); when the plan does not
+//            fit, this kernel inserts in place with global atomics instead;
+//   fill     one workgroup per bucket sets the bits of its entries in an LDS
+//            tile and stores the whole tile (every block of the filter is
+//            written exactly once).
+#pragma once
+
+#include "build_impl.hpp"
+
+namespace pt {
+
+// An entry is 32 bits: the block within its tile above the top 2 log2(B)
+// bits of H2, the only bits of H2 the bit positions use. Tiles hold at most
+// 64 KB, so the block index fits (14 bits for B = 32, 9 for B = 1024).
+__device__ __forceinline__ uint32_t pack_entry(uint32_t blk_in_tile, uint32_t h2, uint32_t lg) {
+  return (blk_in_tile << (2 * lg)) | (h2 >> (32 - 2 * lg));
+}
+__device__ __forceinline__ uint32_t entry_block(uint32_t v, uint32_t lg) { return v >> (2 * lg); }
+__device__ __forceinline__ uint32_t entry_h2(uint32_t v, uint32_t lg) { return v << (32 - 2 * lg); }
+
+// Histogram of this workgroup's keys over the buckets, stored to hist_row.
+template <bool APP>
+__device__ __forceinline__ void part_count_body(const FilterSet &fs, const AppendSet &app, uint32_t lg,
+                                                uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
+                                                const uint64_t *bitmap, uint32_t seg_words, uint64_t entries_cap,
+                                                uint32_t *hist_row, bool from_count, uint32_t target,
+                                                const VGrid &vg) {
+  extern __shared__ __align__(16) uint32_t s_hist[];
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, from_count, target);
+  if (!geo.ok) return;
+  for (uint32_t b = threadIdx.x; b < geo.buckets; b += blockDim.x) s_hist[b] = 0;
+  __syncthreads();
+  const uint32_t tb = geo.tile_blocks;
+  uint32_t base = 0;
+  for (uint32_t i = 0; i < fs.n; i++) {
+    const FilterRef &f = fs.f[i];
+    const uint32_t nb = part_blocks(f, lg, bits_per_key, geo.n_sel, from_count);
+    uint32_t *mine = s_hist + base;
+    for_each_key<APP>(f, app, n_rows, bitmap, seg_words, vg,
+                      [&](uint32_t h1, uint32_t) { atomicAdd(&mine[block_of(h1, nb) / tb], 1u); });
+    base += (nb + tb - 1) / tb;
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < geo.buckets; b += blockDim.x) hist_row[b] = s_hist[b];
+}
+
+// Writes this workgroup's entries at its ranges (hist_row: its exclusive
+// offsets within each bucket, starts: the buckets' first entries). When the
+// plan does not fit the entry buffer, inserts in place with global atomics
+// instead (the filters were zeroed in that case).
+template <bool APP, int K>
+__device__ __forceinline__ void part_scatter_body(const FilterSet &fs, const AppendSet &app, uint32_t k, uint32_t lg,
+                                                  uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
+                                                  const uint64_t *bitmap, uint32_t seg_words, uint64_t entries_cap,
+                                                  const uint32_t *hist_row, const uint64_t *starts,
+                                                  uint32_t *entries, uint32_t *status, bool from_count,
+                                                  uint32_t target, const VGrid &vg) {
+  extern __shared__ __align__(16) uint64_t s_cur[];
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, from_count, target);
+  if (!geo.ok) {
+    for (uint32_t i = 0; i < fs.n; i++) {
+      const FilterRef &f = fs.f[i];
+      const uint32_t nb = part_blocks(f, lg, bits_per_key, geo.n_sel, from_count);
+      uint32_t *words = f.words;
+      for_each_key<APP>(f, app, n_rows, bitmap, seg_words, vg,
+                        [&](uint32_t h1, uint32_t h2) { insert_bits<K>(words, nb, k, h1, h2, lg); });
+    }
+    return;
+  }
+  // s_cur[b]: the next entry slot of this workgroup in bucket b
+  for (uint32_t b = threadIdx.x; b < geo.buckets; b += blockDim.x) s_cur[b] = starts[b] + hist_row[b];
+  __syncthreads();
+  const uint32_t tb = geo.tile_blocks;
+  uint32_t base = 0;
+  for (uint32_t i = 0; i < fs.n; i++) {
+    const FilterRef &f = fs.f[i];
+    const uint32_t nb = part_blocks(f, lg, bits_per_key, geo.n_sel, from_count);
+    unsigned long long *cur = reinterpret_cast<unsigned long long *>(s_cur) + base;
+    for_each_key<APP>(f, app, n_rows, bitmap, seg_words, vg, [&](uint32_t h1, uint32_t h2) {
+      const uint32_t blk = block_of(h1, nb);
+      const uint64_t pos = atomicAdd(&cur[blk / tb], 1ull);
+      if (pos < entries_cap)  // always true while *count is the bitmap's popcount
+        entries[pos] = pack_entry(blk % tb, h2, lg);
+      else
+        raise_status(status, PT_STATUS_ENTRIES_OVERFLOW);
+    });
+    base += (nb + tb - 1) / tb;
+  }
+}
+
+// Buckets b_first, b_first + b_step, ...: each tile built in LDS from its
+// entries and stored once. Entry ranges are clamped to the buffer, so
+// nothing is read outside it whatever the starts hold.
+template <int K>
+__device__ __forceinline__ void part_fill_body(const FilterSet &fs, uint32_t k, uint32_t lg, uint32_t bits_per_key,
+                                               const uint64_t *count, uint64_t n_rows, uint64_t entries_cap,
+                                               const uint64_t *starts, const uint32_t *entries, uint32_t b_first,
+                                               uint32_t b_step, bool from_count, uint32_t target) {
+  extern __shared__ __align__(16) uint32_t tile[];
+  const uint32_t W = 1u << (lg - 5);
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, from_count, target);
+  if (!geo.ok) return;
+  const uint32_t tb = geo.tile_blocks;
+  for (uint32_t b = b_first; b < geo.buckets; b += b_step) {
+    // the filter the bucket belongs to, and the tile within it
+    uint32_t f = 0, base = 0, nb = 0;
+    for (uint32_t i = 0; i < fs.n; i++) {
+      nb = part_blocks(fs.f[i], lg, bits_per_key, geo.n_sel, from_count);
+      const uint32_t tiles = (nb + tb - 1) / tb;
+      f = i;
+      if (b < base + tiles) break;
+      base += tiles;
+    }
+    const uint32_t t = b - base;
+    const uint32_t first = t * tb;
+    const uint32_t n_blocks = min(tb, nb - first);
+    for (uint32_t j = threadIdx.x; j < n_blocks * W; j += blockDim.x) tile[j] = 0;
+    __syncthreads();
+    const uint64_t e0 = min(starts[b], entries_cap), e1 = min(starts[b + 1], entries_cap);
+    for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+      const uint32_t v = entries[e];
+      // the entry names its block inside the tile; with nb = 1 and h1 = 0,
+      // insert_lds sets the key's k bits in the block it is pointed at
+      const uint32_t blk = min(entry_block(v, lg), n_blocks - 1);
+      insert_lds<K>(tile + blk * W, 1, k, 0, entry_h2(v, lg), lg);
+    }
+    __syncthreads();
+    uint32_t *out = fs.f[f].words + static_cast<uint64_t>(first) * W;
+    for (uint32_t j = threadIdx.x; j < n_blocks * W; j += blockDim.x) out[j] = tile[j];
+    __syncthreads();
+  }
+}
+
+}  // namespace pt

@@ -134,25 +134,40 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const
     // group's words go to lane-parallel form (lane u holds word w0 + u), and
     // the survivors are compacted into the LDS slice as they appear (the
     // first 64 of them: more than that take the dense path below).
+    // The filter reads of C words are issued before any of their results is
+    // used (they come from L2 or beyond when the filter is not in LDS).
+    constexpr int C = STAGED ? 1 : 4;
     uint64_t mine = 0;
     uint32_t total0 = 0;  // survivors of the first filter
 #pragma unroll
-    for (int u = 0; u < U; u++) {
-      uint64_t word = tail_mask(w0 + u, n_words, n_rows);
-      if (!input_all) {
-        // readlane returns int: widen through uint32_t (no sign extension)
-        const uint32_t b_hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(bits >> 32), u);
-        const uint32_t b_lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(bits), u);
-        word &= (static_cast<uint64_t>(b_hi) << 32) | b_lo;
+    for (int u0 = 0; u0 < U; u0 += C) {
+      uint64_t word[C];
+      bool ok[C];
+#pragma unroll
+      for (int j = 0; j < C; j++) {
+        const int u = u0 + j;
+        word[j] = tail_mask(w0 + u, n_words, n_rows);
+        if (!input_all) {
+          // readlane returns int: widen through uint32_t (no sign extension)
+          const uint32_t b_hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(bits >> 32), u);
+          const uint32_t b_lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(bits), u);
+          word[j] &= (static_cast<uint64_t>(b_hi) << 32) | b_lo;
+        }
+        ok[j] = false;
+        if (word[j]) {
+          uint32_t h1, h2;
+          if constexpr (KEY64)
+            hash_key((static_cast<uint64_t>(hi[u]) << 32) | lo[u], h1, h2);
+          else
+            hash_key32(lo[u], h1, h2);
+          ok[j] = slot_has<K, STAGED>(sl[0], lds_filters + lds_off[0], h1, h2, k, lg);
+        }
       }
-      if (word) {
-        uint32_t h1, h2;
-        if constexpr (KEY64)
-          hash_key((static_cast<uint64_t>(hi[u]) << 32) | lo[u], h1, h2);
-        else
-          hash_key32(lo[u], h1, h2);
-        const bool ok = slot_has<K, STAGED>(sl[0], lds_filters + lds_off[0], h1, h2, k, lg);
-        const uint64_t m = __ballot(ok) & word;
+#pragma unroll
+      for (int j = 0; j < C; j++) {
+        const int u = u0 + j;
+        if (!word[j]) continue;
+        const uint64_t m = __ballot(ok[j]) & word[j];
         mine = lane == u ? m : mine;
         if (m) {
           if ((m >> lane) & 1) {

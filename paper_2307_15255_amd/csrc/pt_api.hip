@@ -461,9 +461,10 @@ pt_status pt_check_status(const void *d_status, pt_stream stream) {
   if (st == PT_OK) st = check_hip(hipStreamSynchronize(s), "status wait");
   if (st != PT_OK) return st;
   if (word == 0) return PT_OK;
-  return fail(PT_EOVERFLOW, "device status 0x%x:%s%s", word,
+  return fail(PT_EOVERFLOW, "device status 0x%x:%s%s%s", word,
               (word & PT_STATUS_FILTER_OVERFLOW) ? " a filter needed more blocks than its capacity (clamped)" : "",
-              (word & PT_STATUS_ENTRIES_OVERFLOW) ? " a partitioned build met more keys than its count" : "");
+              (word & PT_STATUS_ENTRIES_OVERFLOW) ? " a partitioned build met more keys than its count" : "",
+              (word & PT_STATUS_WAIT_TIMEOUT) ? " a batch item ran without the steps it waited for" : "");
 }
 
 pt_status pt_profile_enable(int on) {
@@ -911,7 +912,8 @@ namespace {
 
 // Longest path from a source of pass p (0: forward edges, 1: reversed) to
 // every table: the schedule level. Tables of one level depend only on lower
-// levels, so all problems can run level by level in lockstep.
+// levels, so listing every problem's tasks level by level gives one order in
+// which every task follows the tasks it depends on.
 std::vector<uint32_t> levels(const Plan &pl, uint32_t p) {
   std::vector<uint32_t> lvl(pl.n_t, 0);
   std::vector<uint32_t> seq = pl.order;
@@ -925,71 +927,51 @@ std::vector<uint32_t> levels(const Plan &pl, uint32_t p) {
   return lvl;
 }
 
-enum LaunchKind : uint32_t { kZero, kLocal, kSize, kBuild, kProbe, kCopy, kSoloBuild };
+constexpr uint32_t kNoTask = 0xFFFFFFFFu;
+constexpr uint32_t kMaxBuildParts = 16;     // private copies of one LDS build
+constexpr uint32_t kMaxTileItems = 256;     // row tiles of one partitioned build
+constexpr uint32_t kMaxFillItems = 256;     // items of one partitioned fill
+constexpr uint64_t kDefaultTileRows = 65536;
+constexpr uint32_t kBatchSpinMs = 2000;     // longest wait of an item for its dependencies
 
-// A table of at least this many rows whose outgoing filters cannot fit in
-// LDS even at their smallest is built on its own with the partitioned build
-// (inside the batch's sequence), not by a batched build.
-constexpr uint64_t kSoloBuildRows = 8ull << 20;
+enum BatchKernel : uint32_t { kKernelGeneric, kKernel512k3, kKernel512k2 };
 
-// Bitmap words (64 rows each) one workgroup of a batched local filter,
-// probe or build takes: enough rows that its fixed cost (finding its task,
-// staging filters) is small beside its scan.
-constexpr uint64_t kBatchWordsPerBlock = 1024;
-
-// LDS a batched probe may stage filters in: two workgroups per CU.
-constexpr uint64_t kBatchProbeLdsBytes = 64 * 1024;
-
-struct BatchLaunch {
-  LaunchKind kind;
-  uint32_t block_bits = 0, k = 0;
-  uint64_t tasks_off = 0, first_off = 0;  // workspace offsets
-  uint32_t n = 0, grid = 0, lds_words = 0;
-  uint32_t pass = 0;                      // 1 forward, 2 backward (probes, builds)
-  uint64_t rows = 0, bytes = 0;           // rows scanned, algorithmic bytes (probes)
-  // kSoloBuild: one table's filters, built by launch_build
-  FilterSet fs{};
-  const uint64_t *bitmap = nullptr, *count = nullptr;
-  uint32_t bits_per_key = 0;
-};
-
-// Task lists of one launch before they are laid out.
-struct LaunchDraft {
-  BatchLaunch l;
-  std::vector<char> tasks;  // packed task structs
-  std::vector<uint32_t> first{0};
-  template <class T>
-  void add(const T &t, uint32_t blocks) {
-    const char *b = reinterpret_cast<const char *>(&t);
-    tasks.insert(tasks.end(), b, b + sizeof(T));
-    first.push_back(first.back() + std::max<uint32_t>(blocks, 1));
-  }
-};
-
-uint32_t clamp_u32(uint64_t v, uint64_t lo, uint64_t hi) {
-  return static_cast<uint32_t>(std::min(std::max(v, lo), hi));
-}
-
+// The host image of a batch: its task list, argument arrays and workspace
+// layout. Device pointers are ws + offset (offsets alone when ws is NULL).
 struct BatchPlan {
   std::vector<Plan> plans;
-  // scratch of the solo builds (partitioned), shared: they run one by one
-  uint64_t off_hist = 0, off_totals = 0, off_starts = 0, off_entries = 0, entries_cap = 0;
-  uint32_t hist_groups = 0;
-  std::vector<uint64_t> off_problem;  // per problem: its nb and filter region
-  uint64_t off_counts = 0, n_counts = 0;
-  uint64_t data_end = 0, total = 0;
-  std::vector<LaunchDraft> drafts;
-  uint64_t rows_probed = 0;
+  std::vector<BTask> tasks;
+  std::vector<uint32_t> item_task, phase_items, deps;
+  std::vector<std::pair<uint32_t, uint32_t>> dep_range;  // per task (host only)
+  std::vector<BLocal> locals;
+  std::vector<BProbe> probes;
+  std::vector<BBuild> builds;
+  std::vector<CopyPair> pairs;
+  uint64_t off_counts = 0, n_counts = 0, off_done = 0, zero_bytes = 0;
+  uint32_t n_items = 0;
+  uint64_t off_tables = 0, off_timeline = 0, total = 0;
+  uint64_t rows_probed = 0, bytes_moved = 0;
+  uint32_t kernel = kKernelGeneric;
 };
 
-// Plans a batch. With ws == nullptr only the sizes are computed (device
-// pointers in the task tables are then offsets from 0).
+uint32_t div_up32(uint64_t a, uint64_t b) { return static_cast<uint32_t>((a + b - 1) / b); }
+
+// Upper bound of the buckets a partitioned build of these filters uses (its
+// bucket count for the filters' actual sizes never exceeds it).
+uint32_t bucket_bound(const FilterSet &fs, uint32_t block_bits) {
+  const uint64_t W = block_bits / 32, max_tb = kTileWords / W;
+  uint64_t cap_blocks = 0;
+  for (uint32_t i = 0; i < fs.n; i++) cap_blocks += fs.f[i].cap_words / W;
+  const uint64_t bound = std::max<uint64_t>(kBatchTargetBuckets, (cap_blocks + max_tb - 1) / max_tb) + fs.n;
+  return static_cast<uint32_t>(std::min<uint64_t>(bound, kMaxBuckets));
+}
+
 pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, BatchPlan &bp) {
   if (n_problems > 0 && !probs) return fail(PT_EINVAL, "problems is NULL");
   bp.plans.resize(n_problems);
-  bp.off_problem.resize(n_problems);
-  uint64_t off = 256;
   uint64_t n_counts = 0;
+  bool all_512_3 = n_problems > 0, all_512_2 = n_problems > 0;
+  uint64_t tile_rows = kDefaultTileRows;
   for (uint32_t i = 0; i < n_problems; i++) {
     const pt_problem &pr = probs[i];
     Plan &pl = bp.plans[i];
@@ -1006,109 +988,175 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
         if (pr.tables[t].n_rows > 0 && !pr.d_bitmaps[t])
           return fail(PT_EINVAL, "problem %u: d_bitmaps[%u] is NULL", i, t);
     }
+    for (uint32_t t = 0; t < pl.n_t; t++) {
+      uint32_t n = 0;
+      for (uint32_t j = 0; j < pr.n_preds; j++) n += pr.preds[j].table == t;
+      if (n > static_cast<uint32_t>(kMaxPreds))
+        return fail(PT_EUNSUPPORTED, "problem %u table %u: more than %d predicates in a batch", i, t, kMaxPreds);
+    }
+    if (i == 0 && pr.params.tile_rows) tile_rows = pr.params.tile_rows;
+    all_512_3 = all_512_3 && pr.params.block_bits == 512 && pr.params.k == 3;
+    all_512_2 = all_512_2 && pr.params.block_bits == 512 && pr.params.k == 2;
     n_counts += 3ull * pl.n_t;
   }
+  bp.kernel = all_512_3 ? kKernel512k3 : all_512_2 ? kKernel512k2 : kKernelGeneric;
+  const uint64_t words_per_item = tile_rows / 64;
+  const uint64_t dyn_lds = static_cast<uint64_t>(device_info().max_lds_block) - 2048;
+  const uint64_t lds_words = dyn_lds / 4;
+  const uint64_t lds_filter_words = ((dyn_lds - probe_queue_bytes()) / 4) & ~uint64_t(1);
+
+  // Workspace: header (status word, queue head), counters, completion
+  // counts (all zeroed at every run), then the problems' filters and the
+  // builds' scratch, then the task tables.
+  uint64_t off = 256;
   bp.off_counts = off;
   bp.n_counts = n_counts;
   off = align256(off + n_counts * 8);
-  // Each problem: block counts of both passes, then its filters.
-  for (uint32_t i = 0; i < n_problems; i++) {
-    const Plan &pl = bp.plans[i];
-    bp.off_problem[i] = off;
-    off = align256(off + 2ull * pl.n_e * 8);
-    for (uint32_t slot = 0; slot < 2 * pl.n_e; slot++) off = align256(off + pl.cap_words[slot] * 4);
-  }
-  bp.data_end = off;
-
   auto ptr = [&](uint64_t o) -> char * { return ws ? ws + o : reinterpret_cast<char *>(o); };
-  const uint64_t lds_max = static_cast<uint64_t>(device_info().max_lds_block) - 1024;
-
-  // Per problem: counter slots, filter refs.
-  uint64_t count_base = bp.off_counts;
   std::vector<uint64_t> counts_of(n_problems);
-  for (uint32_t i = 0; i < n_problems; i++) {
-    counts_of[i] = count_base;
-    count_base += 3ull * bp.plans[i].n_t * 8;
+  {
+    uint64_t c = bp.off_counts;
+    for (uint32_t i = 0; i < n_problems; i++) {
+      counts_of[i] = c;
+      c += 3ull * bp.plans[i].n_t * 8;
+    }
   }
   auto count_ptr = [&](uint32_t i, uint32_t slot, uint32_t t) {
     return reinterpret_cast<uint64_t *>(ptr(counts_of[i] + (static_cast<uint64_t>(slot) * bp.plans[i].n_t + t) * 8));
   };
+  // The task list is built first (its size fixes the completion counters),
+  // with scratch offsets relative to `data`, resolved below.
+  struct Pending { uint32_t build; uint64_t copies, hist, totals, starts, entries; };
+  std::vector<Pending> scratch;
+  uint64_t data = 0;  // bytes of build scratch, laid out after the filters
+  std::vector<uint64_t> off_problem(n_problems);
+
+  // Tasks are created in an order where every dependency comes first; their
+  // phase (depth in the dependency graph) is computed as they are added.
+  std::vector<uint32_t> phase_of;
+  auto add_task = [&](uint32_t kind, uint32_t items, const std::vector<uint32_t> &deps, uint32_t arg,
+                      uint32_t n_arg = 0) {
+    BTask t{};
+    t.kind = kind;
+    t.n_items = std::max<uint32_t>(items, 1);
+    const uint32_t begin = static_cast<uint32_t>(bp.deps.size());
+    uint32_t phase = 0;
+    for (uint32_t d : deps)
+      if (d != kNoTask) {
+        bp.deps.push_back(d);
+        phase = std::max(phase, phase_of[d] + 1);
+      }
+    t.phase = phase;
+    t.arg = arg;
+    t.n_arg = n_arg;
+    const uint32_t id = static_cast<uint32_t>(bp.tasks.size());
+    bp.tasks.push_back(t);
+    bp.dep_range.emplace_back(begin, static_cast<uint32_t>(bp.deps.size()));
+    phase_of.push_back(phase);
+    return id;
+  };
+
+  // Filters of every problem (nb slots and words of both passes, at capacity).
+  // Their offsets are known once the completion counters are placed, so
+  // they are recorded relative to the start of the filter region.
+  uint64_t filters_bytes = 0;
+  std::vector<std::vector<uint64_t>> filter_off(n_problems);
+  for (uint32_t i = 0; i < n_problems; i++) {
+    const Plan &pl = bp.plans[i];
+    off_problem[i] = filters_bytes;
+    uint64_t o = align256(filters_bytes + 2ull * pl.n_e * 8);
+    filter_off[i].resize(2ull * pl.n_e);
+    for (uint32_t slot = 0; slot < 2 * pl.n_e; slot++) {
+      filter_off[i][slot] = o;
+      o = align256(o + pl.cap_words[slot] * 4);
+    }
+    filters_bytes = o;
+  }
+  // Completion counters: one per phase, at most one phase per task. The
+  // number of tasks is bounded by the plan, so reserve that many counters
+  // and place everything else after them.
+  // Per problem at most: a local filter per table; per pass, a probe chunk
+  // per table plus one per four extra incoming edges (fewer than n_t + n_e),
+  // and at most five build steps per group of outgoing filters (fewer than
+  // n_t + n_e groups); one count copy.
+  uint64_t max_tasks = 0;
+  for (uint32_t i = 0; i < n_problems; i++) {
+    const Plan &pl = bp.plans[i];
+    max_tasks += pl.n_t + 2ull * 6 * (pl.n_t + pl.n_e) + 1;
+  }
+  bp.off_done = off;
+  off = align256(off + max_tasks * 4);
+  bp.zero_bytes = off;
+  const uint64_t off_filters = off;
+  off = align256(off + filters_bytes);
+  const uint64_t off_scratch = off;
+
   auto filter_ref = [&](uint32_t i, uint32_t p, uint32_t e, uint32_t table) {
     const Plan &pl = bp.plans[i];
     const uint32_t slot = p * pl.n_e + e;
-    // Filter offsets inside the problem region mirror make_plan's order.
-    uint64_t o = align256(bp.off_problem[i] + 2ull * pl.n_e * 8);
-    for (uint32_t j = 0; j < slot; j++) o = align256(o + pl.cap_words[j] * 4);
     FilterRef r{};
     const pt_column &c = probs[i].tables[table].cols[col_at(probs[i].graph, e, table)];
     r.keys = c.data;
     r.key64 = c.dtype == PT_I64;
-    r.words = reinterpret_cast<uint32_t *>(ptr(o));
-    r.nb = reinterpret_cast<uint64_t *>(ptr(bp.off_problem[i] + slot * 8ull));
+    r.words = reinterpret_cast<uint32_t *>(ptr(off_filters + filter_off[i][slot]));
+    r.nb = reinterpret_cast<uint64_t *>(ptr(off_filters + off_problem[i] + slot * 8ull));
     r.cap_words = pl.cap_words[slot];
     return r;
   };
 
-  // 1. Zero every counter; 2. local predicates of every table (tables
-  // without predicates get every row, so every bitmap is materialised).
-  {
-    LaunchDraft d;
-    d.l.kind = kZero;
-    d.l.n = static_cast<uint32_t>(std::min<uint64_t>(n_counts, 0xFFFFFFFFu));
-    bp.drafts.push_back(std::move(d));
-  }
-  {
-    LaunchDraft d;
-    d.l.kind = kLocal;
-    for (uint32_t i = 0; i < n_problems; i++) {
-      const pt_problem &pr = probs[i];
-      for (uint32_t t = 0; t < bp.plans[i].n_t; t++) {
-        const pt_table &tb = pr.tables[t];
-        if (tb.n_rows == 0) continue;
-        std::vector<const pt_pred *> mine;
-        for (uint32_t j = 0; j < pr.n_preds; j++)
-          if (pr.preds[j].table == t) mine.push_back(&pr.preds[j]);
-        if (mine.size() > static_cast<size_t>(kMaxPreds))
-          return fail(PT_EUNSUPPORTED, "problem %u table %u: more than %d predicates in a batch", i, t, kMaxPreds);
-        LocalTask lt{};
-        for (const pt_pred *q : mine) {
-          const pt_column &c = tb.cols[q->col];
-          lt.ps.p[lt.ps.n++] = PredRef{c.data, c.dtype == PT_I64 ? 1u : 0u, q->op, q->lo, q->hi};
-        }
-        lt.n_rows = tb.n_rows;
-        lt.bitmap = ws ? pr.d_bitmaps[t] : nullptr;
-        lt.count = count_ptr(i, 0, t);
-        lt.seg_words = 16;
-        const uint64_t n_words = (tb.n_rows + 63) / 64;
-        d.add(lt, clamp_u32((n_words + kBatchWordsPerBlock - 1) / kBatchWordsPerBlock, 1, 4096));
+  // 1. Local predicates of every table (tables without predicates get
+  // every row, so every bitmap is materialised).
+  std::vector<std::vector<uint32_t>> writer(n_problems), cur(n_problems);
+  std::vector<std::vector<std::vector<uint32_t>>> readers(n_problems);
+  std::vector<std::vector<uint32_t>> final_of(n_problems);  // task that finishes filter slot
+  for (uint32_t i = 0; i < n_problems; i++) {
+    const Plan &pl = bp.plans[i];
+    const pt_problem &pr = probs[i];
+    writer[i].assign(pl.n_t, kNoTask);
+    cur[i].assign(pl.n_t, 0);
+    readers[i].assign(pl.n_t, {});
+    final_of[i].assign(2ull * pl.n_e, kNoTask);
+    for (uint32_t t = 0; t < pl.n_t; t++) {
+      const pt_table &tb = pr.tables[t];
+      if (tb.n_rows == 0) continue;
+      BLocal l{};
+      for (uint32_t j = 0; j < pr.n_preds; j++) {
+        if (pr.preds[j].table != t) continue;
+        const pt_column &c = tb.cols[pr.preds[j].col];
+        l.ps.p[l.ps.n++] = PredRef{c.data, c.dtype == PT_I64 ? 1u : 0u, pr.preds[j].op, pr.preds[j].lo,
+                                   pr.preds[j].hi};
+        bp.bytes_moved += tb.n_rows * key_bytes(c);
       }
+      const uint64_t n_words = (tb.n_rows + 63) / 64;
+      const uint32_t items = div_up32(n_words, words_per_item);
+      l.n_rows = tb.n_rows;
+      l.bitmap = ws ? pr.d_bitmaps[t] : nullptr;
+      l.count = count_ptr(i, 0, t);
+      l.seg_words = std::min<uint32_t>(64, std::max<uint32_t>(1, div_up32(n_words, uint64_t(items) * 16)));
+      bp.bytes_moved += n_words * 8;
+      writer[i][t] = add_task(kBLocal, items, {}, static_cast<uint32_t>(bp.locals.size()));
+      bp.locals.push_back(l);
     }
-    d.l.n = static_cast<uint32_t>(d.first.size() - 1);
-    bp.drafts.push_back(std::move(d));
   }
 
-  // 3. Both passes, level by level: the probes of a level, then the sizes
-  // and builds of the filters its tables send.
-  std::vector<std::vector<uint32_t>> cur(n_problems);  // counter slot of each table's count
+  // 2. Both passes, level by level over all problems: the probes of a level,
+  // then the builds of the filters its tables send.
+  bool missing_filter = false;
   std::vector<std::vector<uint32_t>> lvl[2];
-  uint32_t max_lvl[2] = {0, 0};
+  uint32_t max_lvl = 0;
   for (uint32_t p = 0; p < 2; p++) {
     lvl[p].resize(n_problems);
     for (uint32_t i = 0; i < n_problems; i++) {
       lvl[p][i] = levels(bp.plans[i], p);
-      for (uint32_t v : lvl[p][i]) max_lvl[p] = std::max(max_lvl[p], v);
+      for (uint32_t v : lvl[p][i]) max_lvl = std::max(max_lvl, v);
     }
   }
-  for (uint32_t i = 0; i < n_problems; i++) cur[i].assign(bp.plans[i].n_t, 0);
-  using Key = std::pair<uint32_t, uint32_t>;  // block_bits, k
   for (uint32_t p = 0; p < 2; p++) {
-    for (uint32_t L = 0; L <= max_lvl[p]; L++) {
-      // Probes: one launch per (parameters, key width, chunk of kMaxProbe).
-      std::map<std::pair<Key, uint32_t>, LaunchDraft> probes;
-      std::map<std::pair<Key, uint32_t>, uint64_t> probe_need;
+    for (uint32_t L = 0; L <= max_lvl; L++) {
       for (uint32_t i = 0; i < n_problems; i++) {
         const Plan &pl = bp.plans[i];
         const pt_problem &pr = probs[i];
+        const uint32_t lg = log2_of(static_cast<int>(pr.params.block_bits));
         for (uint32_t v = 0; v < pl.n_t; v++) {
           if (lvl[p][i][v] != L || pr.tables[v].n_rows == 0) continue;
           std::vector<uint32_t> in;
@@ -1116,179 +1164,178 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
             if ((p == 0 ? pl.dst[e] : pl.src[e]) == v) in.push_back(e);
           if (in.empty()) continue;
           bp.rows_probed += pr.tables[v].n_rows;
-          for (uint32_t c0 = 0, chunk = 0; c0 < in.size(); c0 += kMaxProbe, chunk++) {
-            ProbeTask pt{};
-            uint64_t need = 0;
+          const uint64_t n_rows = pr.tables[v].n_rows, n_words = (n_rows + 63) / 64;
+          for (uint32_t c0 = 0; c0 < in.size(); c0 += kMaxProbe) {
+            BProbe pt{};
+            std::vector<uint32_t> deps{writer[i][v]};
+            deps.insert(deps.end(), readers[i][v].begin(), readers[i][v].end());
             for (uint32_t j = c0; j < in.size() && pt.fs.n < static_cast<uint32_t>(kMaxProbe); j++) {
               const uint32_t e = in[j];
               const uint32_t from = p == 0 ? pl.src[e] : pl.dst[e];
               FilterRef r = filter_ref(i, p, e, v);
-              r.sel = count_ptr(i, cur[i][from], from);
-              r.rows = pr.tables[from].n_rows;
-              need += r.cap_words;
+              if (pr.params.probe_order != PT_PROBE_GIVEN) {
+                r.sel = count_ptr(i, cur[i][from], from);
+                r.rows = pr.tables[from].n_rows;
+              }
+              bp.bytes_moved += n_rows * (r.key64 ? 8 : 4);
               pt.fs.f[pt.fs.n++] = r;
+              missing_filter = missing_filter || final_of[i][p * pl.n_e + e] == kNoTask;
+              deps.push_back(final_of[i][p * pl.n_e + e]);
             }
             const bool last = c0 + kMaxProbe >= in.size();
-            pt.n_rows = pr.tables[v].n_rows;
+            pt.n_rows = n_rows;
             pt.bitmap = ws ? pr.d_bitmaps[v] : nullptr;
             pt.count = last ? count_ptr(i, p + 1, v) : nullptr;
-            pt.input_all = 0;
-            const uint64_t n_words = (pt.n_rows + 63) / 64;
-            const Key key{pr.params.block_bits, pr.params.k};
-            LaunchDraft &d = probes[{key, chunk}];
-            d.l.kind = kProbe;
-            d.l.block_bits = pr.params.block_bits;
-            d.l.k = pr.params.k;
-            d.add(pt, clamp_u32((n_words + kBatchWordsPerBlock - 1) / kBatchWordsPerBlock, 1, 4096));
-            d.l.pass = p + 1;
-            d.l.rows += pt.n_rows;
-            d.l.bytes += 2 * n_words * 8;  // bitmap read and written
-            for (uint32_t j = 0; j < pt.fs.n; j++) d.l.bytes += pt.n_rows * (pt.fs.f[j].key64 ? 8 : 4);
-            uint64_t &mx = probe_need[{key, chunk}];
-            mx = std::max(mx, need);
+            pt.k = pr.params.k;
+            pt.lg = lg;
+            bp.bytes_moved += 2 * n_words * 8;
+            // Every item first copies the filters into its LDS when they fit
+            // there: give it at least eight times their size in keys.
+            uint64_t filter_words = 0;
+            for (uint32_t j = 0; j < pt.fs.n; j++) filter_words += pt.fs.f[j].cap_words;
+            const uint64_t staged = filter_words <= lds_filter_words ? filter_words : 0;
+            const uint64_t probe_words = std::max<uint64_t>(words_per_item, staged * 4 * 8 / (64 * 4));
+            writer[i][v] = add_task(kBProbe, div_up32(n_words, probe_words), deps,
+                                    static_cast<uint32_t>(bp.probes.size()));
+            readers[i][v].clear();
+            bp.probes.push_back(pt);
           }
           cur[i][v] = p + 1;
         }
-      }
-      // Chunk 0 of every key first, then chunk 1, ... (a later chunk ANDs
-      // into the bitmap the earlier one wrote).
-      for (uint32_t chunk = 0;; chunk++) {
-        bool any = false;
-        for (auto &kv : probes) {
-          if (kv.first.second != chunk) continue;
-          any = true;
-          LaunchDraft d = std::move(kv.second);
-          const uint64_t lds_cap = std::min<uint64_t>(lds_max, kBatchProbeLdsBytes);
-          const uint64_t room = lds_cap > probe_queue_bytes() ? (lds_cap - probe_queue_bytes()) / 4 : 0;
-          d.l.lds_words = static_cast<uint32_t>(std::min<uint64_t>(room, probe_need[kv.first]));
-          d.l.n = static_cast<uint32_t>(d.first.size() - 1);
-          bp.drafts.push_back(std::move(d));
-        }
-        if (!any) break;
-      }
-      // Sizes and builds of the filters sent by this level's tables.
-      LaunchDraft size;
-      size.l.kind = kSize;
-      std::vector<LaunchDraft> solos;
-      std::map<std::pair<uint32_t, uint32_t>, LaunchDraft> builds;
-      std::map<std::pair<uint32_t, uint32_t>, uint64_t> build_need;
-      for (uint32_t i = 0; i < n_problems; i++) {
-        const Plan &pl = bp.plans[i];
-        const pt_problem &pr = probs[i];
         for (uint32_t v = 0; v < pl.n_t; v++) {
           if (lvl[p][i][v] != L) continue;
           std::vector<uint32_t> out;
           for (uint32_t e = 0; e < pl.n_e; e++)
             if ((p == 0 ? pl.src[e] : pl.dst[e]) == v) out.push_back(e);
-          if (out.empty()) continue;
-          const uint64_t n_rows = pr.tables[v].n_rows;
-          const uint64_t *cnt = count_ptr(i, cur[i][v], v);
-          uint64_t cap_all = 0;
-          for (uint32_t e : out) cap_all += pl.cap_words[p * pl.n_e + e];
-          if (n_rows >= kSoloBuildRows && cap_all > build_lds_words()) {
-            for (uint32_t c0 = 0; c0 < out.size(); c0 += kMaxFilters) {
-              LaunchDraft d;
-              d.l.kind = kSoloBuild;
-              d.l.block_bits = pr.params.block_bits;
-              d.l.k = pr.params.k;
-              d.l.bits_per_key = pr.params.bits_per_key;
-              d.l.pass = p + 1;
-              d.l.rows = n_rows;
-              d.l.bitmap = ws ? pr.d_bitmaps[v] : nullptr;
-              d.l.count = cnt;
-              for (uint32_t j = c0; j < out.size() && d.l.fs.n < static_cast<uint32_t>(kMaxFilters); j++)
-                d.l.fs.f[d.l.fs.n++] = filter_ref(i, p, out[j], v);
-              bp.entries_cap = std::max<uint64_t>(bp.entries_cap, d.l.fs.n * n_rows);
-              solos.push_back(std::move(d));
+          const uint64_t n_rows = pr.tables[v].n_rows, n_words = (n_rows + 63) / 64;
+          for (uint32_t c0 = 0; c0 < out.size(); c0 += kMaxFilters) {
+            BBuild b{};
+            for (uint32_t j = c0; j < out.size() && b.fs.n < static_cast<uint32_t>(kMaxFilters); j++)
+              b.fs.f[b.fs.n++] = filter_ref(i, p, out[j], v);
+            b.n_rows = n_rows;
+            b.bitmap = (ws && n_rows) ? pr.d_bitmaps[v] : nullptr;
+            b.count = count_ptr(i, cur[i][v], v);
+            b.k = pr.params.k;
+            b.lg = lg;
+            b.bits_per_key = pr.params.bits_per_key;
+            uint64_t cap_words = 0;
+            for (uint32_t j = 0; j < b.fs.n; j++) cap_words += b.fs.f[j].cap_words;
+            const uint32_t arg = static_cast<uint32_t>(bp.builds.size());
+            Pending sc{arg, 0, 0, 0, 0, 0};
+            uint32_t fin;
+            if (cap_words <= lds_words) {
+              // Small filters: private LDS copies, then an OR of the copies.
+              b.n_parts = std::min<uint32_t>(kMaxBuildParts, std::max<uint32_t>(1, div_up32(n_words, words_per_item)));
+              b.copy_words = static_cast<uint32_t>(cap_words);
+              b.seg_words = std::min<uint32_t>(64, std::max<uint32_t>(1, div_up32(n_words, uint64_t(b.n_parts) * 16)));
+              sc.copies = data;
+              data = align256(data + uint64_t(b.n_parts) * b.copy_words * 4);
+              const uint32_t build = add_task(kBBuild, b.n_parts, {writer[i][v]}, arg);
+              fin = add_task(kBReduce, div_up32(cap_words, kReduceWords), {build}, arg);
+              readers[i][v].push_back(build);
+            } else {
+              // Large filters: partitioned build, row tiles then filter tiles.
+              const uint32_t tiles = std::min<uint32_t>(kMaxTileItems,
+                                                        std::max<uint32_t>(1, div_up32(n_words, words_per_item)));
+              b.hist_rows = tiles;
+              b.hist_cols = bucket_bound(b.fs, pr.params.block_bits);
+              b.seg_words = std::min<uint32_t>(64, std::max<uint32_t>(1, div_up32(n_words, uint64_t(tiles) * 16)));
+              b.entries_cap = std::min<uint64_t>(n_rows * b.fs.n, kMaxEntries);
+              if (b.entries_cap == 0) b.entries_cap = 1;
+              sc.hist = data;
+              data = align256(data + uint64_t(b.hist_rows) * b.hist_cols * 4);
+              sc.totals = data;
+              data = align256(data + uint64_t(b.hist_cols) * 8);
+              sc.starts = data;
+              data = align256(data + (uint64_t(b.hist_cols) + 1) * 8);
+              sc.entries = data;
+              data = align256(data + b.entries_cap * 4);
+              // The plan may not fit at run time (more keys than entries, or
+              // more buckets than the table): the filters are then zeroed
+              // and built with atomics.
+              uint32_t first_dep = writer[i][v];
+              if (n_rows * b.fs.n > b.entries_cap || b.hist_cols >= kMaxBuckets)
+                first_dep = add_task(kBZero, div_up32(cap_words, kReduceWords), {writer[i][v]}, arg);
+              const uint32_t count = add_task(kBCount, tiles, {writer[i][v], first_dep}, arg);
+              const uint32_t scan = add_task(kBScan, 1, {count}, arg);
+              const uint32_t scatter = add_task(kBScatter, tiles, {scan}, arg);
+              fin = add_task(kBFill, std::min<uint32_t>(kMaxFillItems, b.hist_cols), {scatter}, arg);
+              readers[i][v].push_back(count);
+              readers[i][v].push_back(scatter);
             }
-            continue;
-          }
-          for (uint32_t c0 = 0; c0 < out.size(); c0 += kMaxProbe) {
-            BuildTask bt{};
-            uint64_t need = 0;
-            for (uint32_t j = c0; j < out.size() && bt.fs.n < static_cast<uint32_t>(kMaxProbe); j++) {
-              const FilterRef r = filter_ref(i, p, out[j], v);
-              SizeTask st{};
-              st.f = r;
-              st.count = cnt;
-              st.n_rows = n_rows;
-              st.block_bits = pr.params.block_bits;
-              st.bits_per_key = pr.params.bits_per_key;
-              size.add(st, clamp_u32((r.cap_words + kBatchThreads * 8 - 1) / (kBatchThreads * 8), 1, 256));
-              need += r.cap_words;
-              bt.fs.f[bt.fs.n++] = r;
-            }
-            bt.n_rows = n_rows;
-            bt.bitmap = (ws && n_rows) ? pr.d_bitmaps[v] : nullptr;
-            bt.seg_words = 16;
-            const uint64_t n_words = (n_rows + 63) / 64;
-            const std::pair<uint32_t, uint32_t> key{pr.params.block_bits, pr.params.k};
-            LaunchDraft &d = builds[key];
-            d.l.kind = kBuild;
-            d.l.block_bits = pr.params.block_bits;
-            d.l.k = pr.params.k;
-            d.add(bt, clamp_u32((n_words + kBatchWordsPerBlock - 1) / kBatchWordsPerBlock, 1, 1024));
-            uint64_t &mx = build_need[key];
-            mx = std::max(mx, need);
+            for (uint32_t j = c0; j < out.size() && j < c0 + kMaxFilters; j++) final_of[i][p * pl.n_e + out[j]] = fin;
+            bp.builds.push_back(b);
+            scratch.push_back(sc);
           }
         }
       }
-      if (size.first.size() > 1) {
-        size.l.n = static_cast<uint32_t>(size.first.size() - 1);
-        bp.drafts.push_back(std::move(size));
-      }
-      for (auto &kv : builds) {
-        LaunchDraft d = std::move(kv.second);
-        d.l.lds_words = static_cast<uint32_t>(std::min<uint64_t>(build_lds_words(), build_need[kv.first]));
-        d.l.n = static_cast<uint32_t>(d.first.size() - 1);
-        bp.drafts.push_back(std::move(d));
-      }
-      for (LaunchDraft &d : solos) bp.drafts.push_back(std::move(d));
     }
   }
-  // 4. Final counts to the callers' arrays.
+  // 3. Final counts to the callers' arrays.
+  for (uint32_t i = 0; i < n_problems; i++) {
+    if (ws && !probs[i].d_counts) continue;
+    const Plan &pl = bp.plans[i];
+    std::vector<uint32_t> deps;
+    const uint32_t first = static_cast<uint32_t>(bp.pairs.size());
+    for (uint32_t t = 0; t < pl.n_t; t++) {
+      bp.pairs.push_back(CopyPair{count_ptr(i, cur[i][t], t), ws ? probs[i].d_counts + t : nullptr});
+      deps.push_back(writer[i][t]);
+    }
+    add_task(kBCopy, 1, deps, first, pl.n_t);
+  }
+  if (bp.tasks.size() > max_tasks) return fail(PT_EDEVICE, "batch planner: %zu tasks over its bound", bp.tasks.size());
+  // The list in phase order (stable): items of a phase follow every item of
+  // the phases before it.
   {
-    LaunchDraft d;
-    d.l.kind = kCopy;
-    for (uint32_t i = 0; i < n_problems; i++) {
-      if (ws && !probs[i].d_counts) continue;  // sizes assume every problem wants its counts
-      for (uint32_t t = 0; t < bp.plans[i].n_t; t++) {
-        CopyPair cp{count_ptr(i, cur[i][t], t), probs[i].d_counts + t};
-        const char *b = reinterpret_cast<const char *>(&cp);
-        d.tasks.insert(d.tasks.end(), b, b + sizeof(cp));
-      }
+    std::vector<uint32_t> order(bp.tasks.size());
+    for (uint32_t t = 0; t < order.size(); t++) order[t] = t;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return bp.tasks[x].phase < bp.tasks[y].phase; });
+    std::vector<BTask> sorted;
+    sorted.reserve(order.size());
+    uint32_t n_phases = 0;
+    for (uint32_t t : order) {
+      BTask task = bp.tasks[t];
+      task.first_item = static_cast<uint32_t>(bp.item_task.size());
+      bp.item_task.insert(bp.item_task.end(), task.n_items, static_cast<uint32_t>(sorted.size()));
+      n_phases = std::max(n_phases, task.phase + 1);
+      sorted.push_back(task);
     }
-    d.l.n = static_cast<uint32_t>(d.tasks.size() / sizeof(CopyPair));
-    bp.drafts.push_back(std::move(d));
+    bp.phase_items.assign(n_phases, 0);
+    for (const BTask &task : sorted) bp.phase_items[task.phase] += task.n_items;
+    for (uint32_t t = 0; t < bp.tasks.size(); t++)
+      for (uint32_t d = bp.dep_range[t].first; d < bp.dep_range[t].second; d++)
+        if (bp.tasks[bp.deps[d]].phase >= bp.tasks[t].phase)
+          return fail(PT_EDEVICE, "batch planner: task %u does not follow its dependency", t);
+    bp.tasks = std::move(sorted);
+    bp.n_items = static_cast<uint32_t>(bp.item_task.size());
   }
-  // Scratch of the solo builds, then the task tables, after the data.
-  off = bp.data_end;
-  if (bp.entries_cap > 0) {
-    bp.entries_cap = std::min<uint64_t>(bp.entries_cap, kMaxEntries);
-    bp.hist_groups = static_cast<uint32_t>(device_info().n_cu);
-    bp.off_hist = off;
-    off = align256(off + static_cast<uint64_t>(bp.hist_groups) * kMaxBuckets * 4);
-    bp.off_totals = off;
-    off = align256(off + static_cast<uint64_t>(kMaxBuckets) * 8);
-    bp.off_starts = off;
-    off = align256(off + (static_cast<uint64_t>(kMaxBuckets) + 1) * 8);
-    bp.off_entries = off;
-    off = align256(off + bp.entries_cap * 4);
+  if (missing_filter) return fail(PT_EDEVICE, "batch planner: a probe precedes the build of its filter");
+
+  // Scratch offsets, then the tables.
+  for (const Pending &sc : scratch) {
+    BBuild &b = bp.builds[sc.build];
+    if (b.copy_words) b.copies = reinterpret_cast<uint32_t *>(ptr(off_scratch + sc.copies));
+    if (b.hist_rows) {
+      b.hist = reinterpret_cast<uint32_t *>(ptr(off_scratch + sc.hist));
+      b.totals = reinterpret_cast<uint64_t *>(ptr(off_scratch + sc.totals));
+      b.starts = reinterpret_cast<uint64_t *>(ptr(off_scratch + sc.starts));
+      b.entries = reinterpret_cast<uint32_t *>(ptr(off_scratch + sc.entries));
+    }
   }
-  const uint64_t tables_begin = off;
-  for (LaunchDraft &d : bp.drafts) {
-    d.l.tasks_off = off;
-    off = align256(off + d.tasks.size());
-    d.l.grid = d.first.back();
-    // the per-workgroup task map follows the task starts
-    const size_t n_first = d.first.size();
-    for (uint32_t t = 0; t + 1 < n_first; t++)
-      for (uint32_t b = d.first[t]; b < d.first[t + 1]; b++) d.first.push_back(t);
-    d.l.first_off = off;
-    off = align256(off + d.first.size() * 4);
+  off = align256(off_scratch + data);
+  bp.off_tables = off;
+  auto table_bytes = [](size_t n, size_t sz) { return align256(static_cast<uint64_t>(n * sz)); };
+  off += table_bytes(bp.tasks.size(), sizeof(BTask)) + table_bytes(bp.item_task.size(), 4) +
+         table_bytes(bp.phase_items.size(), 4) + table_bytes(bp.locals.size(), sizeof(BLocal)) +
+         table_bytes(bp.probes.size(), sizeof(BProbe)) + table_bytes(bp.builds.size(), sizeof(BBuild)) +
+         table_bytes(bp.pairs.size(), sizeof(CopyPair));
+  // PT_BATCH_TIMELINE=1 (profiling): room for every item's start and end.
+  if (const char *tl = std::getenv("PT_BATCH_TIMELINE"); tl && std::strcmp(tl, "1") == 0) {
+    bp.off_timeline = off;
+    off = align256(off + 16ull * bp.n_items);
   }
   bp.total = off;
-  bp.data_end = tables_begin;  // the task tables start here
   return PT_OK;
 }
 
@@ -1297,56 +1344,29 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
 struct pt_batch {
   int device = 0;
   char *ws = nullptr;
-  BuildScratch scratch;  // offsets resolved into ws (solo builds)
-  std::vector<char> staging;  // host copy of the task tables
-  std::vector<BatchLaunch> launches;
-  uint64_t off_counts = 0, n_counts = 0, rows_probed = 0;
+  std::vector<char> staging;  // host image of the task tables
+  BatchArgs args{};
+  uint32_t kernel = kKernelGeneric;
+  uint32_t grid = 0;
+  uint64_t lds_bytes = 0, zero_bytes = 0, rows_probed = 0, bytes_moved = 0;
+  uint32_t n_tasks = 0, n_phases = 0, rate_khz = 0;
+  std::vector<uint32_t> item_kind, item_phase;  // per item, for the timeline
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
 
-// timed: bracket the probe launches with profiling events (eager runs).
 static pt_status enqueue_batch(const pt_batch &b, hipStream_t s, bool timed) {
-  uint32_t *status = reinterpret_cast<uint32_t *>(b.ws);
-  for (size_t li = 0; li < b.launches.size(); li++) {
-    const BatchLaunch &l = b.launches[li];
-    Timed tm(timed && l.kind == kProbe ? "batch probe" : nullptr, static_cast<uint32_t>(li), l.pass, l.rows,
-             l.bytes, s);
-    const char *tasks = b.ws + l.tasks_off;
-    const uint32_t *first = reinterpret_cast<const uint32_t *>(b.ws + l.first_off);
-    hipError_t e = hipSuccess;
-    switch (l.kind) {
-      case kZero:
-        // the status word (workspace header) and every counter
-        e = launch_zero_u64(reinterpret_cast<uint64_t *>(b.ws), b.off_counts / 8 + b.n_counts, s);
-        break;
-      case kLocal:
-        e = launch_local_batch(reinterpret_cast<const LocalTask *>(tasks), first, l.n, l.grid, s);
-        break;
-      case kSize:
-        e = launch_size_batch(reinterpret_cast<const SizeTask *>(tasks), first, l.n, l.grid, status, s);
-        break;
-      case kBuild:
-        e = launch_build_batch(l.block_bits, l.k, reinterpret_cast<const BuildTask *>(tasks), first, l.n,
-                               l.grid, l.lds_words, status, s);
-        break;
-      case kProbe:
-        e = launch_probe_batch(l.block_bits, l.k, reinterpret_cast<const ProbeTask *>(tasks), first,
-                               l.n, l.grid, l.lds_words, status, s);
-        break;
-      case kCopy:
-        e = launch_copy_pairs(reinterpret_cast<const CopyPair *>(tasks), l.n, s);
-        break;
-      case kSoloBuild:
-        e = launch_build(l.block_bits, l.k, l.bits_per_key, l.fs, l.rows, l.bitmap, l.count, &b.scratch,
-                         nullptr, status, s);
-        break;
-    }
-    pt_status st = check_hip(e, "batch launch");
-    if (st != PT_OK) return st;
+  pt_status st = check_hip(launch_zero_u64(reinterpret_cast<uint64_t *>(b.ws), b.zero_bytes / 8, s), "batch zero");
+  if (st != PT_OK) return st;
+  Timed tm(timed ? "batch" : nullptr, b.n_tasks, 0, b.rows_probed, b.bytes_moved, s);
+  hipError_t e;
+  switch (b.kernel) {
+    case kKernel512k3: e = launch_batch_512_k3(b.args, b.grid, b.lds_bytes, s); break;
+    case kKernel512k2: e = launch_batch_512_k2(b.args, b.grid, b.lds_bytes, s); break;
+    default: e = launch_batch_generic(b.args, b.grid, b.lds_bytes, s); break;
   }
-  return PT_OK;
+  return check_hip(e, "batch launch");
 }
 
 extern "C" {
@@ -1384,23 +1404,51 @@ pt_status pt_batch_prepare_async(uint32_t n_problems, const pt_problem *problems
   if (ws_bytes < bp.total)
     return fail(PT_ENOMEM, "workspace %zu < %llu bytes", ws_bytes, (unsigned long long)bp.total);
   // Raise the LDS limits now: the capture must not change kernel attributes.
-  for (const LaunchDraft &d : bp.drafts) {
-    if (d.l.kind != kBuild && d.l.kind != kProbe) continue;
-    st = check_hip(prepare_batch_kernels(d.l.block_bits, d.l.k), "batch kernel setup");
-    if (st != PT_OK) return st;
-  }
+  st = check_hip(prepare_batch_kernels(), "batch kernel setup");
+  if (st != PT_OK) return st;
   char *ws = static_cast<char *>(d_ws);
+  auto *b = new pt_batch();
   // The task tables go to the workspace in one asynchronous copy on
   // `stream`, from a host buffer the handle keeps until it is freed.
-  auto *b = new pt_batch();
-  const uint64_t table_bytes = bp.total - bp.data_end;
-  b->staging.assign(table_bytes, 0);
-  for (const LaunchDraft &d : bp.drafts) {
-    std::memcpy(b->staging.data() + (d.l.tasks_off - bp.data_end), d.tasks.data(), d.tasks.size());
-    std::memcpy(b->staging.data() + (d.l.first_off - bp.data_end), d.first.data(), d.first.size() * 4);
-  }
-  if (table_bytes) {
-    st = check_hip(hipMemcpyAsync(ws + bp.data_end, b->staging.data(), table_bytes, hipMemcpyHostToDevice,
+  b->staging.assign((bp.off_timeline ? bp.off_timeline : bp.total) - bp.off_tables, 0);
+  uint64_t o = 0;
+  auto put = [&](const void *src, size_t n, size_t sz) {
+    const uint64_t at = o;
+    if (n) std::memcpy(b->staging.data() + o, src, n * sz);
+    o += align256(static_cast<uint64_t>(n * sz));
+    return ws + bp.off_tables + at;
+  };
+  BatchArgs &a = b->args;
+  a.tasks = reinterpret_cast<const BTask *>(put(bp.tasks.data(), bp.tasks.size(), sizeof(BTask)));
+  a.item_task = reinterpret_cast<const uint32_t *>(put(bp.item_task.data(), bp.item_task.size(), 4));
+  a.phase_items = reinterpret_cast<const uint32_t *>(put(bp.phase_items.data(), bp.phase_items.size(), 4));
+  a.locals = reinterpret_cast<const BLocal *>(put(bp.locals.data(), bp.locals.size(), sizeof(BLocal)));
+  a.probes = reinterpret_cast<const BProbe *>(put(bp.probes.data(), bp.probes.size(), sizeof(BProbe)));
+  a.builds = reinterpret_cast<const BBuild *>(put(bp.builds.data(), bp.builds.size(), sizeof(BBuild)));
+  a.pairs = reinterpret_cast<const CopyPair *>(put(bp.pairs.data(), bp.pairs.size(), sizeof(CopyPair)));
+  a.status = reinterpret_cast<uint32_t *>(ws);
+  a.head = reinterpret_cast<uint32_t *>(ws + 4);
+  a.phase_done = reinterpret_cast<uint32_t *>(ws + bp.off_done);
+  a.n_items = bp.n_items;
+  a.n_phases = static_cast<uint32_t>(bp.phase_items.size());
+  const uint64_t lds_bytes = static_cast<uint64_t>(device_info().max_lds_block) - 2048;
+  a.lds_filter_words = static_cast<uint32_t>((lds_bytes - probe_queue_bytes()) / 4) & ~1u;
+  int rate_khz = 0;
+  if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device_info().device) != hipSuccess ||
+      rate_khz <= 0)
+    rate_khz = 100000;
+  a.spin_limit = static_cast<uint64_t>(rate_khz) * kBatchSpinMs;
+  a.timeline = bp.off_timeline ? reinterpret_cast<uint64_t *>(ws + bp.off_timeline) : nullptr;
+  b->rate_khz = static_cast<uint32_t>(rate_khz);
+  b->item_kind.resize(bp.n_items);
+  b->item_phase.resize(bp.n_items);
+  for (const BTask &t : bp.tasks)
+    for (uint32_t j = 0; j < t.n_items; j++) {
+      b->item_kind[t.first_item + j] = t.kind;
+      b->item_phase[t.first_item + j] = t.phase;
+    }
+  if (!b->staging.empty()) {
+    st = check_hip(hipMemcpyAsync(ws + bp.off_tables, b->staging.data(), b->staging.size(), hipMemcpyHostToDevice,
                                   reinterpret_cast<hipStream_t>(stream)),
                    "task table copy");
     if (st != PT_OK) {
@@ -1410,18 +1458,14 @@ pt_status pt_batch_prepare_async(uint32_t n_problems, const pt_problem *problems
   }
   if (hipGetDevice(&b->device) != hipSuccess) b->device = 0;
   b->ws = ws;
-  if (bp.entries_cap > 0) {
-    b->scratch.hist = reinterpret_cast<uint32_t *>(ws + bp.off_hist);
-    b->scratch.hist_groups = bp.hist_groups;
-    b->scratch.totals = reinterpret_cast<uint64_t *>(ws + bp.off_totals);
-    b->scratch.starts = reinterpret_cast<uint64_t *>(ws + bp.off_starts);
-    b->scratch.entries = reinterpret_cast<uint32_t *>(ws + bp.off_entries);
-    b->scratch.entries_cap = bp.entries_cap;
-  }
-  b->off_counts = bp.off_counts;
-  b->n_counts = bp.n_counts;
+  b->kernel = bp.kernel;
+  b->grid = static_cast<uint32_t>(device_info().n_cu);
+  b->lds_bytes = lds_bytes;
+  b->zero_bytes = bp.zero_bytes;
   b->rows_probed = bp.rows_probed;
-  for (const LaunchDraft &d : bp.drafts) b->launches.push_back(d.l);
+  b->bytes_moved = bp.bytes_moved;
+  b->n_tasks = static_cast<uint32_t>(bp.tasks.size());
+  b->n_phases = static_cast<uint32_t>(bp.phase_items.size());
   *out = b;
   return PT_OK;
 }
@@ -1451,9 +1495,31 @@ pt_status pt_batch_run(pt_batch *b, pt_stream stream, uint32_t flags) {
   return check_hip(hipGraphLaunch(b->exec, s), "graph launch");
 }
 
+pt_status pt_batch_timeline(const pt_batch *b, uint64_t *out, uint32_t max_items, uint32_t *n_items,
+                            uint32_t *ticks_per_ms) {
+  if (!b || !n_items) return fail(PT_EINVAL, "batch or n_items is NULL");
+  if (!b->args.timeline) return fail(PT_EUNSUPPORTED, "the batch was prepared without PT_BATCH_TIMELINE=1");
+  const uint32_t n = std::min<uint32_t>(max_items, b->args.n_items);
+  if (n > 0 && !out) return fail(PT_EINVAL, "out is NULL");
+  std::vector<uint64_t> se(2ull * n);
+  pt_status st = check_hip(hipDeviceSynchronize(), "timeline wait");
+  if (st == PT_OK && n)
+    st = check_hip(hipMemcpy(se.data(), b->args.timeline, se.size() * 8, hipMemcpyDeviceToHost), "timeline read");
+  if (st != PT_OK) return st;
+  for (uint32_t i = 0; i < n; i++) {
+    out[4ull * i] = se[2ull * i];
+    out[4ull * i + 1] = se[2ull * i + 1];
+    out[4ull * i + 2] = b->item_kind[i];
+    out[4ull * i + 3] = b->item_phase[i];
+  }
+  *n_items = n;
+  if (ticks_per_ms) *ticks_per_ms = b->rate_khz;
+  return PT_OK;
+}
+
 pt_status pt_batch_info(const pt_batch *b, uint32_t *n_launches, uint64_t *rows_probed) {
   if (!b) return fail(PT_EINVAL, "batch is NULL");
-  if (n_launches) *n_launches = static_cast<uint32_t>(b->launches.size());
+  if (n_launches) *n_launches = 2;  // the counter reset and the persistent kernel
   if (rows_probed) *rows_probed = b->rows_probed;
   return PT_OK;
 }

@@ -27,10 +27,6 @@ constexpr int kProbeThreads = 1024;  // probe: sixteen waves per workgroup
 constexpr int kWideThreads = 1024;   // kernels that count: one workgroup (one atomic) per CU
 constexpr int kProbeWaves = kProbeThreads / kWave;
 
-constexpr uint32_t log2_of(int b) {
-  return b == 32 ? 5 : b == 64 ? 6 : b == 128 ? 7 : b == 256 ? 8 : b == 512 ? 9 : b == 1024 ? 10 : 0;
-}
-
 // log2 of the block bits: the compile-time value of a specialised kernel
 // (B > 0), else the run-time argument.
 template <int B>

@@ -10,6 +10,11 @@
 namespace pt {
 
 constexpr int kWave = 64;
+
+// log2 of a filter's block bits (0 for a size the filter does not allow).
+constexpr uint32_t log2_of(int b) {
+  return b == 32 ? 5 : b == 64 ? 6 : b == 128 ? 7 : b == 256 ? 8 : b == 512 ? 9 : b == 1024 ? 10 : 0;
+}
 constexpr int kMaxFilters = 8;  // filters handled by one build launch
 constexpr int kMaxProbe = 4;    // filters handled by one probe launch (their keys stay in registers)
 constexpr int kMaxPreds = 8;    // predicates handled by one local-filter launch
@@ -184,16 +189,45 @@ hipError_t launch_part_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_
 // Buckets a partitioned build aims for: its fill kernel runs one workgroup
 // per (filter, tile) bucket.
 constexpr uint64_t kTargetBuckets = 1024;
+// The same for the builds of a batch: few and large tiles, since many builds
+// share the device.
+constexpr uint32_t kBatchTargetBuckets = 16;
 
-// ------------------------------------------------------------ batched steps
+// ---------------------------------------------------------------- batches
 //
-// A batched launch runs the same step for many tables of many problems. Its
-// tasks live in device memory; task i owns workgroups [first[i], first[i+1])
-// of the launch (first has n + 1 entries, first[n] = the grid size, then
-// one entry per workgroup: the task it belongs to).
+// A batch of independent transfer problems runs as one persistent kernel
+// over a list of tasks: one task is one step of one table of one problem
+// (local filter, probe, build, ...), split into work items of one workgroup
+// each. A task's phase is its depth in the dependency graph (one more than
+// the deepest task it depends on), and the list is ordered by phase.
+// Workgroups take items in list order from a device counter; the first
+// item a workgroup takes in a phase waits until every item of the previous
+// phase has finished (per-phase completion counters), so each task runs
+// after all the tasks it depends on.
 
-// Local predicates of one table (no predicates: every row).
-struct LocalTask {
+enum BatchKind : uint32_t {
+  kBLocal = 0,  // local predicates of a table (every row when it has none)
+  kBProbe,      // probe up to kMaxProbe filters on a table
+  kBBuild,      // private LDS copies of a table's outgoing filters (small filters)
+  kBReduce,     // OR of those copies into the filters
+  kBZero,       // zero filters a partitioned build may fill with atomics
+  kBCount,      // partitioned build: bucket histogram of a row tile
+  kBScan,       // partitioned build: entry ranges of every (tile, bucket)
+  kBScatter,    // partitioned build: entries of a row tile
+  kBFill,       // partitioned build: one filter tile per item
+  kBCopy,       // final counts to the caller's arrays
+};
+
+struct BTask {
+  uint32_t kind;        // BatchKind
+  uint32_t n_items;     // work items, one workgroup each
+  uint32_t first_item;  // global index of item 0
+  uint32_t phase;       // depth in the dependency graph
+  uint32_t arg;         // index into the argument array of the kind
+  uint32_t n_arg;       // kBCopy: number of count pairs
+};
+
+struct BLocal {
   PredSet ps;
   uint64_t n_rows;
   uint64_t *bitmap;
@@ -202,32 +236,32 @@ struct LocalTask {
   uint32_t pad;
 };
 
-// Size one filter from its builder's count and zero its blocks.
-struct SizeTask {
-  FilterRef f;
-  const uint64_t *count;
-  uint64_t n_rows;
-  uint32_t block_bits;
-  uint32_t bits_per_key;
-};
-
-// Build up to kMaxProbe filters of one table from its selected rows.
-struct BuildTask {
-  FilterSet fs;
-  uint64_t n_rows;
-  const uint64_t *bitmap;
-  uint32_t seg_words;
-  uint32_t pad;
-};
-
-// Probe up to kMaxProbe filters on one table.
-struct ProbeTask {
+struct BProbe {
   FilterSet fs;
   uint64_t n_rows;
   uint64_t *bitmap;
-  uint64_t *count;
-  uint32_t input_all;
-  uint32_t pad;
+  uint64_t *count;  // NULL except for the last probe of the table in its pass
+  uint32_t k, lg;
+};
+
+// The outgoing filters of one table in one pass (at most kMaxFilters),
+// with the scratch of whichever build they take.
+struct BBuild {
+  FilterSet fs;  // keys: the builder's columns
+  uint64_t n_rows;
+  const uint64_t *bitmap;
+  const uint64_t *count;  // the builder's selected rows after this pass's probes
+  uint32_t k, lg, bits_per_key, seg_words;
+  // LDS build: n_parts private copies of copy_words words each
+  uint32_t *copies;
+  uint32_t copy_words, n_parts;
+  // partitioned build: hist_rows x hist_cols counters, totals, starts, entries
+  uint32_t *hist;
+  uint32_t hist_cols, hist_rows;
+  uint64_t *totals;
+  uint64_t *starts;
+  uint32_t *entries;
+  uint64_t entries_cap;
 };
 
 struct CopyPair {
@@ -235,26 +269,37 @@ struct CopyPair {
   uint64_t *dst;
 };
 
-constexpr int kBatchThreads = 1024;  // every batched kernel: sixteen waves per workgroup
+struct BatchArgs {
+  const BTask *tasks;
+  const uint32_t *item_task;    // task of every item
+  const uint32_t *phase_items;  // items of every phase
+  const BLocal *locals;
+  const BProbe *probes;
+  const BBuild *builds;
+  const CopyPair *pairs;
+  uint32_t *head;        // next item to take
+  uint32_t *phase_done;  // finished items of every phase
+  uint32_t *status;      // the batch's status word
+  uint32_t n_items;
+  uint32_t n_phases;
+  uint32_t lds_filter_words;  // probe: LDS words for staged filters
+  uint32_t pad;
+  uint64_t spin_limit;        // longest wait for a phase, in wall-clock ticks
+  uint64_t *timeline;         // NULL, or the start and end (wall clock) of every item
+};
 
-hipError_t launch_local_batch(const LocalTask *tasks, const uint32_t *first, uint32_t n, uint32_t grid,
-                              hipStream_t s);
-hipError_t launch_size_batch(const SizeTask *tasks, const uint32_t *first, uint32_t n, uint32_t grid,
-                             uint32_t *status, hipStream_t s);
-// lds_words: LDS words per workgroup for private filter copies (a task whose
-// filters need more inserts with global atomics).
-hipError_t launch_build_batch(uint32_t block_bits, uint32_t k, const BuildTask *tasks, const uint32_t *first,
-                              uint32_t n, uint32_t grid, uint32_t lds_words, uint32_t *status, hipStream_t s);
-// lds_filter_words: LDS words per workgroup for staged filters.
-hipError_t launch_probe_batch(uint32_t block_bits, uint32_t k, const ProbeTask *tasks,
-                              const uint32_t *first, uint32_t n, uint32_t grid, uint32_t lds_filter_words,
-                              uint32_t *status, hipStream_t s);
-hipError_t launch_copy_pairs(const CopyPair *pairs, uint32_t n, hipStream_t s);
+constexpr int kBatchThreads = 1024;    // the batch kernel: sixteen waves per workgroup
+constexpr uint32_t kReduceWords = 16384;  // filter words one reduce or zero item of a batch covers
+
+// k_batch*.hip: the persistent kernel for B = 512 and k = 3 or 2, or generic.
+// grid: workgroups (all resident); lds_bytes: dynamic LDS per workgroup.
+hipError_t launch_batch_512_k3(const BatchArgs &a, uint32_t grid, uint64_t lds_bytes, hipStream_t s);
+hipError_t launch_batch_512_k2(const BatchArgs &a, uint32_t grid, uint64_t lds_bytes, hipStream_t s);
+hipError_t launch_batch_generic(const BatchArgs &a, uint32_t grid, uint64_t lds_bytes, hipStream_t s);
+// Raise the batch kernels' LDS limit (before a capture).
+hipError_t prepare_batch_kernels();
+hipError_t prepare_batch_512();
 // Bytes of LDS a probe workgroup needs besides its staged filters.
 uint64_t probe_queue_bytes();
-// Kernels whose LDS limit must be raised before a batch is captured.
-hipError_t prepare_batch_kernels(uint32_t block_bits, uint32_t k);
-hipError_t prepare_probe_batch_kernel(uint32_t block_bits, uint32_t k);
-hipError_t prepare_build_batch_kernel(uint32_t block_bits, uint32_t k);
 
 }  // namespace pt

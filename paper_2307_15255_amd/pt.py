@@ -108,6 +108,7 @@ def _load() -> C.CDLL:
         "pt_batch_prepare_async": ([u32, C.POINTER(pt_problem), vp, C.c_size_t, vp, C.POINTER(vp)], st),
         "pt_batch_run": ([vp, vp, u32], st),
         "pt_batch_info": ([vp, C.POINTER(u32), C.POINTER(u64)], st),
+        "pt_batch_timeline": ([vp, C.POINTER(u64), u32, C.POINTER(u32), C.POINTER(u32)], st),
         "pt_batch_free": ([vp], None),
         "pt_transfer_batch": ([u32, C.POINTER(pt_problem), vp, C.c_size_t, vp], st),
         "pt_profile_enable": ([C.c_int], st),
@@ -125,7 +126,7 @@ EXPORTS = ("pt_version", "pt_last_error", "pt_check_status", "pt_local_filter", 
            "pt_bloom_probe", "pt_compact_workspace_size", "pt_compact", "pt_compact_noalloc", "pt_transfer_workspace_size",
            "pt_transfer", "pt_transfer_filter", "pt_batch_workspace_size", "pt_batch_prepare",
            "pt_batch_prepare_async", "pt_batch_run",
-           "pt_batch_info", "pt_batch_free", "pt_transfer_batch", "pt_profile_enable", "pt_profile_read")
+           "pt_batch_info", "pt_batch_timeline", "pt_batch_free", "pt_transfer_batch", "pt_profile_enable", "pt_profile_read")
 PT_BATCH_EAGER = 1
 
 
@@ -417,6 +418,16 @@ class Batch:
         n, rows = C.c_uint32(), C.c_uint64()
         _check(_lib.pt_batch_info(self._h, C.byref(n), C.byref(rows)))
         return n.value, rows.value
+
+    def timeline(self) -> tuple[np.ndarray, int]:
+        """Per item (start, end, kind, phase) of the last run, and the wall
+        clock's ticks per millisecond (batches prepared with
+        PT_BATCH_TIMELINE=1 in the environment)."""
+        n_items, _ = self.info()
+        buf = (C.c_uint64 * (4 * 1_000_000))()
+        n, rate = C.c_uint32(), C.c_uint32()
+        _check(_lib.pt_batch_timeline(self._h, buf, 1_000_000, C.byref(n), C.byref(rate)))
+        return np.frombuffer(buf, dtype=np.uint64, count=4 * n.value).reshape(n.value, 4).copy(), rate.value
 
     def bitmap(self, i: int, t: int) -> np.ndarray:
         return self.bitmaps[i][t].cpu().numpy().view(np.uint64)
