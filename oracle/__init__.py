@@ -125,6 +125,8 @@ def lib(path: str | None = None) -> C.CDLL:
         L.ptor_compact.argtypes = [u64p, C.c_uint64, u32p, u64p]
         L.ptor_transfer.argtypes = [C.POINTER(_Problem), C.POINTER(_Params),
                                     C.POINTER(C.POINTER(C.c_uint64)), u64p, C.POINTER(_Dump)]
+        L.ptor_join.argtypes = [C.POINTER(_Problem), C.c_uint32, C.POINTER(u64p), u32p, u32p, u32p,
+                                C.c_uint64, u64p]
         _lib = L
     return _lib
 
@@ -246,13 +248,9 @@ class TransferResult:
         self.edge_src: dict[tuple[int, int], int] = {}
 
 
-def transfer(problem, block_bits: int = 512, k: int = 3, bits_per_key: int = 10,
-             kind: int = BLOOM, n_passes: int = 2, variant: int = 0,
-             dump_filters: bool = False) -> TransferResult:
-    """Run the transfer phase on a `workloads.Problem`."""
-    L = lib()
+def _problem(problem, keep: list) -> _Problem:
+    """The C view of a `workloads.Problem` (arrays kept alive in `keep`)."""
     n_t, n_e = problem.n_tables, len(problem.edges)
-    keep = []
     tables = (_Table * max(1, n_t))()
     for t in range(n_t):
         cols = [np.ascontiguousarray(a) for a in problem.columns[t].values()]
@@ -269,7 +267,18 @@ def transfer(problem, block_bits: int = 512, k: int = 3, bits_per_key: int = 10,
         orient_arr = np.array(problem.orient, np.int8)
         keep.append(orient_arr)
         orient = _ptr(orient_arr, C.c_int8)
-    prob = _Problem(n_t, n_e, tables, edges, orient, preds, len(problem.preds), 0)
+    keep += [tables, edges, preds]
+    return _Problem(n_t, n_e, tables, edges, orient, preds, len(problem.preds), 0)
+
+
+def transfer(problem, block_bits: int = 512, k: int = 3, bits_per_key: int = 10,
+             kind: int = BLOOM, n_passes: int = 2, variant: int = 0,
+             dump_filters: bool = False) -> TransferResult:
+    """Run the transfer phase on a `workloads.Problem`."""
+    L = lib()
+    n_t, n_e = problem.n_tables, len(problem.edges)
+    keep: list = []
+    prob = _problem(problem, keep)
     par = _Params(block_bits, k, bits_per_key, kind, n_passes, variant)
 
     res = TransferResult()
@@ -313,3 +322,33 @@ def transfer(problem, block_bits: int = 512, k: int = 3, bits_per_key: int = 10,
             if words:
                 res.filters[(p, e)] = words[s][:int(nb[s]) * (block_bits // 32)].copy()
     return res
+
+
+def join(problem, bitmaps: list | None = None, root: int = 0) -> tuple[list[int], np.ndarray]:
+    """Join phase (Sec. 3.3) on the tables reduced to `bitmaps` (None: every
+    row; a None entry: every row of that table): the tables of root's
+    connected component in ascending order, and every tuple of their row ids
+    that satisfies all the component's edges, one tuple per row, sorted."""
+    L = lib()
+    keep: list = []
+    prob = _problem(problem, keep)
+    n_t = problem.n_tables
+    bm = (C.POINTER(C.c_uint64) * max(1, n_t))()
+    if bitmaps is not None:
+        for t, b in enumerate(bitmaps):
+            if b is not None:
+                b = np.ascontiguousarray(b, dtype=np.uint64)
+                keep.append(b)
+                bm[t] = _ptr(b, C.c_uint64)
+    comp = np.zeros(max(1, n_t), np.uint32)
+    n_comp, n_out = C.c_uint32(), C.c_uint64()
+    cap = 1 << 12
+    while True:
+        out = np.zeros(cap * max(1, n_t), np.uint32)
+        _check(L.ptor_join(C.byref(prob), root, bm, _ptr(comp, C.c_uint32), C.byref(n_comp),
+                           _ptr(out, C.c_uint32), cap, C.byref(n_out)), "join")
+        if n_out.value <= cap:
+            break
+        cap = n_out.value
+    w = n_comp.value
+    return [int(t) for t in comp[:w]], out[:n_out.value * w].reshape(n_out.value, w).copy()

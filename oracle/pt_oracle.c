@@ -424,3 +424,201 @@ out:
   free(rev_order);
   return rc;
 }
+
+/* ------------------------------------------------------------------ */
+/* Join phase (Sec. 3.3)                                                */
+/* ------------------------------------------------------------------ */
+
+/* The join result is defined without reference to any join algorithm: all
+ * combinations of selected rows, one per table of the component, that agree
+ * on every edge. It is enumerated one table at a time in breadth-first
+ * order from the root, so each table joins a prefix it is connected to; the
+ * rows of the new table whose key matches one edge to the prefix are found
+ * in a key-sorted list of its selected rows, and every edge between the new
+ * table and the prefix (the cycle-closing ones and the other halves of a
+ * composite key included) is then checked on each candidate. */
+
+typedef struct {
+  int64_t key;
+  uint32_t row;
+} keyed_row;
+
+static int cmp_keyed(const void *a, const void *b) {
+  const keyed_row *x = (const keyed_row *)a, *y = (const keyed_row *)b;
+  if (x->key != y->key) return (x->key > y->key) - (x->key < y->key);
+  return (x->row > y->row) - (x->row < y->row);
+}
+
+static _Thread_local uint32_t tuple_width; /* ids per tuple, for cmp_tuple */
+
+static int cmp_tuple(const void *a, const void *b) {
+  const uint32_t *x = (const uint32_t *)a, *y = (const uint32_t *)b;
+  for (uint32_t c = 0; c < tuple_width; c++)
+    if (x[c] != y[c]) return (x[c] > y[c]) - (x[c] < y[c]);
+  return 0;
+}
+
+static int row_selected(const uint64_t *const *bitmaps, uint32_t t, uint64_t r) {
+  return !bitmaps || !bitmaps[t] || bit_get(bitmaps[t], r);
+}
+
+int ptor_join(const ptor_problem *p, uint32_t root, const uint64_t *const *bitmaps, uint32_t *comp,
+              uint32_t *n_comp, uint32_t *out, uint64_t cap, uint64_t *n_out) {
+  if (!p || root >= p->n_tables || !comp || !n_comp || !n_out || (cap && !out)) return PTOR_EINVAL;
+  const uint32_t n = p->n_tables, m = p->n_edges;
+  for (uint32_t e = 0; e < m; e++) /* a join edge links two different tables */
+    if (p->edges[e].u >= n || p->edges[e].v >= n || p->edges[e].u == p->edges[e].v) return PTOR_EINVAL;
+  int rc = PTOR_OK;
+  uint32_t *order = malloc(n * sizeof(uint32_t));
+  int32_t *slot = malloc(n * sizeof(int32_t)); /* position of a table in the tuples, -1: not placed */
+  uint32_t *cur = NULL, *next = NULL;
+  keyed_row *index = NULL;
+  if (!order || !slot) {
+    rc = PTOR_ENOMEM;
+    goto done;
+  }
+
+  /* Breadth-first order of root's component (edges in index order). */
+  for (uint32_t t = 0; t < n; t++) slot[t] = -1;
+  uint32_t w = 0;
+  order[w++] = root;
+  slot[root] = 0;
+  for (uint32_t head = 0; head < w; head++) {
+    const uint32_t t = order[head];
+    for (uint32_t e = 0; e < m; e++) {
+      const ptor_edge *ed = &p->edges[e];
+      uint32_t other;
+      if (ed->u == t) other = ed->v;
+      else if (ed->v == t) other = ed->u;
+      else continue;
+      if (slot[other] < 0) {
+        slot[other] = (int32_t)w;
+        order[w++] = other;
+      }
+    }
+  }
+
+  /* The root's selected rows are the first prefix. */
+  uint64_t n_cur = 0;
+  const uint64_t root_rows = p->tables[root].n_rows;
+  cur = malloc((root_rows ? root_rows : 1) * sizeof(uint32_t));
+  if (!cur) {
+    rc = PTOR_ENOMEM;
+    goto done;
+  }
+  for (uint64_t r = 0; r < root_rows; r++)
+    if (row_selected(bitmaps, root, r)) cur[n_cur++] = (uint32_t)r;
+
+  for (uint32_t i = 1; i < w; i++) {
+    const uint32_t v = order[i];
+    /* The lowest-indexed edge from v to a table placed before it. */
+    uint32_t e0 = m;
+    for (uint32_t e = 0; e < m && e0 == m; e++) {
+      const ptor_edge *ed = &p->edges[e];
+      if ((ed->u == v && (uint32_t)slot[ed->v] < i) || (ed->v == v && (uint32_t)slot[ed->u] < i))
+        e0 = e;
+    }
+    const ptor_edge *ed0 = &p->edges[e0];
+    const uint32_t v_col = ed0->u == v ? ed0->u_col : ed0->v_col;
+    const uint32_t u = ed0->u == v ? ed0->v : ed0->u;
+    const uint32_t u_col = ed0->u == v ? ed0->v_col : ed0->u_col;
+
+    /* v's selected rows sorted by their key on e0. */
+    const uint64_t v_rows = p->tables[v].n_rows;
+    free(index);
+    index = malloc((v_rows ? v_rows : 1) * sizeof(keyed_row));
+    if (!index) {
+      rc = PTOR_ENOMEM;
+      goto done;
+    }
+    uint64_t n_index = 0;
+    for (uint64_t r = 0; r < v_rows; r++) {
+      if (!row_selected(bitmaps, v, r)) continue;
+      index[n_index].key = column_value(&p->tables[v].cols[v_col], r);
+      index[n_index].row = (uint32_t)r;
+      n_index++;
+    }
+    qsort(index, n_index, sizeof(keyed_row), cmp_keyed);
+
+    /* Every prefix tuple extended by every matching row of v. */
+    uint64_t n_next = 0, cap_next = n_cur ? n_cur : 1;
+    next = malloc(cap_next * (i + 1) * sizeof(uint32_t));
+    if (!next) {
+      rc = PTOR_ENOMEM;
+      goto done;
+    }
+    for (uint64_t j = 0; j < n_cur; j++) {
+      const uint32_t *tup = cur + j * i;
+      const int64_t key = column_value(&p->tables[u].cols[u_col], tup[slot[u]]);
+      uint64_t lo = 0, hi = n_index; /* first entry with index key >= key */
+      while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (index[mid].key < key) lo = mid + 1;
+        else hi = mid;
+      }
+      for (uint64_t x = lo; x < n_index && index[x].key == key; x++) {
+        const uint32_t r = index[x].row;
+        int ok = 1;
+        for (uint32_t e = 0; e < m && ok; e++) {
+          const ptor_edge *ed = &p->edges[e];
+          uint32_t v_c, b_t, b_c; /* v's column; the other table and its column */
+          if (ed->u == v) {
+            v_c = ed->u_col; b_t = ed->v; b_c = ed->v_col;
+          } else if (ed->v == v) {
+            v_c = ed->v_col; b_t = ed->u; b_c = ed->u_col;
+          } else {
+            continue;
+          }
+          if ((uint32_t)slot[b_t] >= i) continue; /* joined later */
+          if (column_value(&p->tables[v].cols[v_c], r) !=
+              column_value(&p->tables[b_t].cols[b_c], tup[slot[b_t]]))
+            ok = 0;
+        }
+        if (!ok) continue;
+        if (n_next == cap_next) {
+          cap_next *= 2;
+          uint32_t *grown = realloc(next, cap_next * (i + 1) * sizeof(uint32_t));
+          if (!grown) {
+            rc = PTOR_ENOMEM;
+            goto done;
+          }
+          next = grown;
+        }
+        memcpy(next + n_next * (i + 1), tup, i * sizeof(uint32_t));
+        next[n_next * (i + 1) + i] = r;
+        n_next++;
+      }
+    }
+    free(cur);
+    cur = next;
+    next = NULL;
+    n_cur = n_next;
+  }
+
+  /* Columns in ascending table order, tuples sorted. */
+  uint32_t c = 0;
+  for (uint32_t t = 0; t < n; t++)
+    if (slot[t] >= 0) comp[c++] = t;
+  *n_comp = w;
+  uint32_t *sorted = malloc((n_cur ? n_cur : 1) * w * sizeof(uint32_t));
+  if (!sorted) {
+    rc = PTOR_ENOMEM;
+    goto done;
+  }
+  for (uint64_t j = 0; j < n_cur; j++)
+    for (uint32_t q = 0; q < w; q++) sorted[j * w + q] = cur[j * w + slot[comp[q]]];
+  tuple_width = w;
+  qsort(sorted, n_cur, w * sizeof(uint32_t), cmp_tuple);
+  const uint64_t n_copy = n_cur < cap ? n_cur : cap;
+  if (n_copy) memcpy(out, sorted, n_copy * w * sizeof(uint32_t));
+  *n_out = n_cur;
+  free(sorted);
+
+done:
+  free(order);
+  free(slot);
+  free(cur);
+  free(next);
+  free(index);
+  return rc;
+}

@@ -15,6 +15,7 @@
  *             (forward pass in topological order, then a backward pass on
  *             the reversed edges), filter type (precise filter = semi-join)
  *   Sec. 2.1  Bloom filter: no false negatives, possible false positives
+ *   Sec. 3.3  join phase: regular joins on the reduced tables
  *
  * The paper fixes no hash function, filter layout or filter size. This
  * oracle implements the filter specification that the GPU library also
@@ -160,6 +161,21 @@ int ptor_compact(const uint64_t *bitmap, uint64_t n_rows, uint32_t *idx, uint64_
  * counts[t] its popcount. */
 int ptor_transfer(const ptor_problem *p, const ptor_params *params, uint64_t *const *bitmaps,
                   uint64_t *counts, const ptor_dump *dump);
+
+/* Join phase (Sec. 3.3): the joins run on the tables as the transfer phase
+ * reduced them. Returns every tuple of row ids, one row of each table of
+ * root's connected component, whose rows are all selected (bitmaps[t] NULL:
+ * every row of t) and whose key columns satisfy every edge between tables of
+ * the component (keys compared as int64).
+ *   comp     receives the component's tables in ascending index order,
+ *            *n_comp their number
+ *   out      room for cap tuples of *n_comp ids, row-major: the id of table
+ *            comp[c] in tuple j is out[j * n_comp + c]; tuples are sorted
+ *            ascending, comparing ids in comp order
+ *   n_out    the number of tuples; when it exceeds cap only the first cap
+ *            are written */
+int ptor_join(const ptor_problem *p, uint32_t root, const uint64_t *const *bitmaps, uint32_t *comp,
+              uint32_t *n_comp, uint32_t *out, uint64_t cap, uint64_t *n_out);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,7 @@ import numpy as np  # noqa: E402
 
 import oracle  # noqa: E402
 import test_oracle_filter as F  # noqa: E402
+import test_oracle_join as J  # noqa: E402
 import test_oracle_transfer as T  # noqa: E402
 
 
@@ -30,6 +31,9 @@ def checks():
     yield lambda: T.test_local_filter_ops(None)
     yield lambda: T.test_compact(None)
     yield lambda: T.test_bloom_join_is_one_hop_transfer(None)
+    for shape in ("tree", "cycle"):
+        yield lambda shape=shape: J.test_join_matches_brute_force(None, shape)
+    yield lambda: J.test_join_edge_cases(None)
 
 
 def main():

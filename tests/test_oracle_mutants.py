@@ -36,6 +36,12 @@ MUTANTS = {
     "build_before_probe": None,  # handled below: outgoing filters built before incoming probes
     "no_backward_pass": ("if (pa->n_passes == 2) {", "if (pa->n_passes == 3) {"),
     "local_preds_ignored": ("if (pr->table == t && !predicate_holds", "if (pr->table == t + 1 && !predicate_holds"),
+    "join_skips_closing_edge": ("if ((uint32_t)slot[b_t] >= i) continue;",
+                                "if ((uint32_t)slot[b_t] >= i || b_t != u) continue;"),
+    "join_upper_bound": ("if (index[mid].key < key) lo = mid + 1;", "if (index[mid].key <= key) lo = mid + 1;"),
+    "join_ignores_bitmap": ("if (!row_selected(bitmaps, v, r)) continue;", "(void)0;"),
+    "join_columns_in_bfs_order": ("sorted[j * w + q] = cur[j * w + slot[comp[q]]];",
+                                  "sorted[j * w + q] = cur[j * w + q];"),
 }
 
 
