@@ -92,6 +92,9 @@ typedef enum pt_status {
  *                     the steps it depends on and ran without them (the
  *                     batch's results are then not to be trusted) */
 #define PT_STATUS_WAIT_TIMEOUT 4u
+/*   JOIN_OVERFLOW     a join produced more tuples than the caller's out_cap
+ *                     (pt_join: the tuples are incomplete) */
+#define PT_STATUS_JOIN_OVERFLOW 8u
 
 typedef enum pt_dtype { PT_I32 = 0, PT_I64 = 1 } pt_dtype;
 
@@ -302,6 +305,43 @@ pt_status pt_transfer_workspace_size(const pt_graph *graph, const pt_table *tabl
 pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pred *preds,
                       uint32_t n_preds, const pt_params *params, void *d_ws, size_t ws_bytes,
                       uint64_t *const *d_bitmaps, uint64_t *d_counts, pt_stream stream);
+
+/* Bytes of workspace pt_join needs for the component of `root` in this
+ * graph, these tables' row counts and out_cap tuples. */
+pt_status pt_join_workspace_size(const pt_graph *graph, const pt_table *tables, uint32_t root,
+                                 uint64_t out_cap, size_t *bytes);
+
+/* The join phase (Sec. 3.3): the joins of the query run on the tables as
+ * the transfer phase reduced them. Produces every tuple of row ids, one row
+ * of each table of root's connected component, whose rows are all selected
+ * and whose key columns agree on every edge between tables of the
+ * component (keys compared as int64 values). The root is the table the
+ * join starts from: the other tables are added one at a time in
+ * breadth-first order from it, each through a hash table over its selected
+ * rows that the tuples so far probe, so the root is best the largest table
+ * (the tables added are the build sides).
+ *   d_bitmaps  NULL (every row of every table selected), or graph->n_tables
+ *              device pointers: d_bitmaps[t] selects table t's rows (the
+ *              bitmaps pt_transfer wrote), NULL for every row of t
+ *   d_out      graph->n_tables pointers; for each table t of the component,
+ *              d_out[t] has room for out_cap uint32 row ids (others unused)
+ *   out_cap    tuples that fit in the d_out columns (and in the workspace's
+ *              intermediate tuples)
+ *   d_n_out    device uint64: the number of tuples (see overflow below)
+ *   d_ws       workspace of at least pt_join_workspace_size bytes, 256-byte
+ *              aligned; its first 4 bytes are the call's status word
+ * Tuple i is (d_out[t][i] for t in the component). The tuples come out in
+ * no particular order (their set is fixed, their order depends on
+ * scheduling). When a step produces more than out_cap tuples, only out_cap
+ * of them are kept, PT_STATUS_JOIN_OVERFLOW is set in the status word
+ * (pt_check_status on d_ws), the result is incomplete and *d_n_out holds
+ * the largest number of tuples a step reached (more than out_cap): call
+ * again with at least that out_cap (a later step may then need more). Edges with flags other than 0 are rejected with
+ * PT_EUNSUPPORTED, as are components of more than 32 tables or a table with
+ * more than 9 edges to the tables added before it. */
+pt_status pt_join(const pt_graph *graph, const pt_table *tables, uint32_t root,
+                  const uint64_t *const *d_bitmaps, uint32_t *const *d_out, uint64_t out_cap,
+                  uint64_t *d_n_out, void *d_ws, size_t ws_bytes, pt_stream stream);
 
 /* Where pt_transfer left the filter that `edge` carried in `pass` (1 forward,
  * 2 backward) inside d_ws, and which table built it (*builder). */

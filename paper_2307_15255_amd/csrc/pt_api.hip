@@ -461,10 +461,11 @@ pt_status pt_check_status(const void *d_status, pt_stream stream) {
   if (st == PT_OK) st = check_hip(hipStreamSynchronize(s), "status wait");
   if (st != PT_OK) return st;
   if (word == 0) return PT_OK;
-  return fail(PT_EOVERFLOW, "device status 0x%x:%s%s%s", word,
+  return fail(PT_EOVERFLOW, "device status 0x%x:%s%s%s%s", word,
               (word & PT_STATUS_FILTER_OVERFLOW) ? " a filter needed more blocks than its capacity (clamped)" : "",
               (word & PT_STATUS_ENTRIES_OVERFLOW) ? " a partitioned build met more keys than its count" : "",
-              (word & PT_STATUS_WAIT_TIMEOUT) ? " a batch item ran without the steps it waited for" : "");
+              (word & PT_STATUS_WAIT_TIMEOUT) ? " a batch item ran without the steps it waited for" : "",
+              (word & PT_STATUS_JOIN_OVERFLOW) ? " a join produced more tuples than out_cap (incomplete)" : "");
 }
 
 pt_status pt_profile_enable(int on) {
@@ -1541,6 +1542,255 @@ pt_status pt_transfer_batch(uint32_t n_problems, const pt_problem *problems, voi
   if (st == PT_OK) st = check_hip(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)), "batch wait");
   pt_batch_free(b);
   return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- join phase
+
+namespace {
+
+// The join phase's plan: the component's tables in breadth-first order from
+// the root, for each added table its lookup edge (the lowest-indexed edge to
+// a table added before it) and the other edges to those tables, and the
+// workspace layout.
+struct JoinPlan {
+  std::vector<uint32_t> order;
+  std::vector<int> pos;  // place of each table in the tuples, -1 outside the component
+  std::vector<uint32_t> lookup;
+  std::vector<std::vector<uint32_t>> checks;
+  std::vector<uint32_t> lg_cap;
+  std::vector<uint64_t> off_ids, off_keys, off_heads, off_next;
+  uint64_t off_counts = 0, off_partials = 0, off_tuples[2] = {0, 0}, total = 0;
+};
+
+uint32_t ceil_log2(uint64_t x) {
+  uint32_t lg = 0;
+  while ((1ull << lg) < x) lg++;
+  return lg;
+}
+
+pt_status make_join_plan(const pt_graph *g, const pt_table *tables, uint32_t root, uint64_t out_cap,
+                         JoinPlan &jp) {
+  if (!g) return fail(PT_EINVAL, "graph is NULL");
+  if (g->n_tables > kMaxTables) return fail(PT_EINVAL, "%u tables (limit %u)", g->n_tables, kMaxTables);
+  if (root >= g->n_tables) return fail(PT_EINVAL, "root %u: the graph has %u tables", root, g->n_tables);
+  if (!tables) return fail(PT_EINVAL, "tables is NULL");
+  if (g->n_edges > 0 && !g->edges) return fail(PT_EINVAL, "edges is NULL");
+  if (out_cap > (1ull << 36)) return fail(PT_EINVAL, "out_cap %llu (limit 2^36)", (unsigned long long)out_cap);
+  for (uint32_t t = 0; t < g->n_tables; t++) {
+    pt_status st = check_table(&tables[t], t);
+    if (st != PT_OK) return st;
+  }
+  for (uint32_t e = 0; e < g->n_edges; e++) {
+    const pt_edge &ed = g->edges[e];
+    if (ed.u >= g->n_tables || ed.v >= g->n_tables) return fail(PT_EINVAL, "edge %u: table out of range", e);
+    if (ed.u == ed.v) return fail(PT_EINVAL, "edge %u joins table %u with itself", e, ed.u);
+    if (ed.flags != 0) return fail(PT_EUNSUPPORTED, "edge %u: flags 0x%x (only inner joins, flags = 0)", e, ed.flags);
+    if (ed.u_col >= tables[ed.u].n_cols || ed.v_col >= tables[ed.v].n_cols)
+      return fail(PT_EINVAL, "edge %u: column out of range", e);
+  }
+  // Breadth-first order of root's component, edges in index order.
+  jp.pos.assign(g->n_tables, -1);
+  jp.order.assign(1, root);
+  jp.pos[root] = 0;
+  for (size_t head = 0; head < jp.order.size(); head++) {
+    const uint32_t t = jp.order[head];
+    for (uint32_t e = 0; e < g->n_edges; e++) {
+      const pt_edge &ed = g->edges[e];
+      const uint32_t other = ed.u == t ? ed.v : ed.v == t ? ed.u : t;
+      if (other != t && jp.pos[other] < 0) {
+        jp.pos[other] = static_cast<int>(jp.order.size());
+        jp.order.push_back(other);
+      }
+    }
+  }
+  const uint32_t w = static_cast<uint32_t>(jp.order.size());
+  if (w > kMaxJoinWidth)
+    return fail(PT_EUNSUPPORTED, "root %u's component has %u tables (limit %u)", root, w, kMaxJoinWidth);
+  jp.lookup.assign(w, 0);
+  jp.checks.assign(w, {});
+  for (uint32_t i = 1; i < w; i++) {
+    const uint32_t v = jp.order[i];
+    bool found = false;
+    for (uint32_t e = 0; e < g->n_edges; e++) {
+      const pt_edge &ed = g->edges[e];
+      if (ed.u != v && ed.v != v) continue;
+      const uint32_t other = ed.u == v ? ed.v : ed.u;
+      if (static_cast<uint32_t>(jp.pos[other]) >= i) continue;  // added later
+      if (!found) {
+        jp.lookup[i] = e;
+        found = true;
+      } else {
+        jp.checks[i].push_back(e);
+      }
+    }
+    if (jp.checks[i].size() > kMaxJoinChecks)
+      return fail(PT_EUNSUPPORTED, "table %u has %zu edges to the tables joined before it (limit %u)", v,
+                  jp.checks[i].size() + 1, kMaxJoinChecks + 1);
+  }
+  // Workspace: status word, counts (selected rows per table, tuples per
+  // step), compaction partials, each table's selected ids, each added
+  // table's hash table, two buffers of intermediate tuples.
+  uint64_t off = 256;
+  jp.off_counts = off;
+  off = align256(off + 2ull * w * 8);
+  uint64_t max_rows = 0;
+  for (uint32_t t : jp.order) max_rows = std::max<uint64_t>(max_rows, tables[t].n_rows);
+  jp.off_partials = off;
+  off = align256(off + (compact_partials(max_rows) + 1) * 8);
+  jp.off_ids.assign(w, 0);
+  jp.off_keys.assign(w, 0);
+  jp.off_heads.assign(w, 0);
+  jp.off_next.assign(w, 0);
+  jp.lg_cap.assign(w, 0);
+  for (uint32_t i = 0; i < w; i++) {
+    const uint64_t n = tables[jp.order[i]].n_rows;
+    jp.off_ids[i] = off;
+    off = align256(off + std::max<uint64_t>(n, 1) * 4);
+    if (i == 0) continue;
+    jp.lg_cap[i] = std::max<uint32_t>(6, ceil_log2(2 * n));
+    const uint64_t slots = (1ull << jp.lg_cap[i]) + 1;
+    jp.off_keys[i] = off;
+    off = align256(off + slots * 8);
+    jp.off_heads[i] = off;
+    off = align256(off + slots * 4);
+    jp.off_next[i] = off;
+    off = align256(off + std::max<uint64_t>(n, 1) * 4);
+  }
+  for (int b = 0; b < 2; b++) {
+    jp.off_tuples[b] = off;
+    if (w >= 3) off = align256(off + static_cast<uint64_t>(w - 1) * out_cap * 4);
+  }
+  jp.total = off;
+  return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pt_status pt_join_workspace_size(const pt_graph *graph, const pt_table *tables, uint32_t root, uint64_t out_cap,
+                                 size_t *bytes) {
+  if (!bytes) return fail(PT_EINVAL, "bytes is NULL");
+  JoinPlan jp;
+  pt_status st = make_join_plan(graph, tables, root, out_cap, jp);
+  if (st != PT_OK) return st;
+  *bytes = jp.total;
+  return PT_OK;
+}
+
+pt_status pt_join(const pt_graph *graph, const pt_table *tables, uint32_t root, const uint64_t *const *d_bitmaps,
+                  uint32_t *const *d_out, uint64_t out_cap, uint64_t *d_n_out, void *d_ws, size_t ws_bytes,
+                  pt_stream stream) {
+  JoinPlan jp;
+  pt_status st = make_join_plan(graph, tables, root, out_cap, jp);
+  if (st != PT_OK) return st;
+  if (!d_ws) return fail(PT_EINVAL, "d_ws is NULL");
+  if ((reinterpret_cast<uintptr_t>(d_ws) & 255) != 0) return fail(PT_EINVAL, "d_ws is not 256-byte aligned");
+  if (ws_bytes < jp.total)
+    return fail(PT_ENOMEM, "workspace %zu < %llu bytes", ws_bytes, (unsigned long long)jp.total);
+  if (!d_n_out) return fail(PT_EINVAL, "d_n_out is NULL");
+  const uint32_t w = static_cast<uint32_t>(jp.order.size());
+  if (out_cap > 0) {
+    if (!d_out) return fail(PT_EINVAL, "d_out is NULL");
+    for (uint32_t t : jp.order)
+      if (!d_out[t]) return fail(PT_EINVAL, "d_out[%u] is NULL (table %u is in root's component)", t, t);
+  }
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *ws = static_cast<char *>(d_ws);
+  uint32_t *status = reinterpret_cast<uint32_t *>(ws);
+  uint64_t *counts = reinterpret_cast<uint64_t *>(ws + jp.off_counts);  // [w] selected rows, [w] step tuples
+  auto ids_of = [&](uint32_t i) { return reinterpret_cast<uint32_t *>(ws + jp.off_ids[i]); };
+  {
+    Timed tm("zero", 0, 0, 0, jp.off_counts + 2ull * w * 8, s);
+    st = check_hip(launch_zero_u64(reinterpret_cast<uint64_t *>(ws), (jp.off_counts + 2ull * w * 8) / 8, s),
+                   "zero counters");
+    if (st == PT_OK) st = check_hip(launch_zero_u64(d_n_out, 1, s), "zero count");
+    if (st != PT_OK) return st;
+  }
+  // The selected rows of every table of the component, ascending.
+  for (uint32_t i = 0; i < w; i++) {
+    const uint32_t t = jp.order[i];
+    const uint64_t n = tables[t].n_rows;
+    const uint64_t *bm = d_bitmaps ? d_bitmaps[t] : nullptr;
+    Timed tm("join ids", t, 0, n, (n + 63) / 64 * 8 + n * 4, s);
+    st = check_hip(launch_join_ids(bm, n, ids_of(i), counts + i, reinterpret_cast<uint64_t *>(ws + jp.off_partials),
+                                   s),
+                   "join ids");
+    if (st != PT_OK) return st;
+  }
+  if (w == 1) {
+    Timed tm("join copy", root, 0, tables[root].n_rows, 0, s);
+    return check_hip(launch_join_copy(ids_of(0), counts, out_cap, out_cap ? d_out[root] : nullptr, d_n_out, status, s),
+                     "join copy");
+  }
+  auto key_of = [&](uint32_t e, uint32_t t, const void *&data, uint32_t &key64) {
+    const pt_column &c = tables[t].cols[col_at(graph, e, t)];
+    data = c.data;
+    key64 = c.dtype == PT_I64 ? 1u : 0u;
+  };
+  for (uint32_t i = 1; i < w; i++) {
+    const uint32_t v = jp.order[i];
+    const uint32_t e0 = jp.lookup[i];
+    const pt_edge &ed0 = graph->edges[e0];
+    const uint32_t u = ed0.u == v ? ed0.v : ed0.u;
+    JoinStep js{};
+    JoinHash &h = js.h;
+    h.keys = reinterpret_cast<unsigned long long *>(ws + jp.off_keys[i]);
+    h.heads = reinterpret_cast<uint32_t *>(ws + jp.off_heads[i]);
+    h.next = reinterpret_cast<uint32_t *>(ws + jp.off_next[i]);
+    h.ids = ids_of(i);
+    h.count = counts + i;
+    key_of(e0, v, h.key, h.key64);
+    h.lg_cap = jp.lg_cap[i];
+    h.n_rows = tables[v].n_rows;
+    {
+      Timed tm("join build", v, 0, h.n_rows, h.n_rows * 4, s);
+      st = check_hip(launch_join_build(h, s), "join build");
+      if (st != PT_OK) return st;
+    }
+    key_of(e0, u, js.u_key, js.u64);
+    js.u_pos = static_cast<uint32_t>(jp.pos[u]);
+    js.width = i;
+    js.n_checks = static_cast<uint32_t>(jp.checks[i].size());
+    for (uint32_t c = 0; c < js.n_checks; c++) {
+      const uint32_t e = jp.checks[i][c];
+      const pt_edge &ed = graph->edges[e];
+      const uint32_t other = ed.u == v ? ed.v : ed.u;
+      JoinCheck &ck = js.checks[c];
+      key_of(e, v, ck.v_col, ck.v64);
+      key_of(e, other, ck.p_col, ck.p64);
+      ck.pos = static_cast<uint32_t>(jp.pos[other]);
+    }
+    const bool last = i + 1 == w;
+    if (i == 1) {
+      js.in[0] = ids_of(0);
+      js.n_in = counts;
+      js.in_cap = tables[root].n_rows;
+    } else {
+      const uint32_t *buf = reinterpret_cast<const uint32_t *>(ws + jp.off_tuples[(i - 2) % 2]);
+      for (uint32_t c = 0; c < i; c++) js.in[c] = buf + static_cast<uint64_t>(c) * out_cap;
+      js.n_in = counts + w + (i - 1);
+      js.in_cap = out_cap;
+    }
+    if (last) {
+      for (uint32_t c = 0; c <= i; c++) js.out[c] = out_cap ? d_out[jp.order[c]] : nullptr;
+      js.n_out = d_n_out;
+    } else {
+      uint32_t *buf = reinterpret_cast<uint32_t *>(ws + jp.off_tuples[(i - 1) % 2]);
+      for (uint32_t c = 0; c <= i; c++) js.out[c] = buf + static_cast<uint64_t>(c) * out_cap;
+      js.n_out = counts + w + i;
+    }
+    js.cap = out_cap;
+    js.status = status;
+    Timed tm("join step", v, 0, 0, 0, s);
+    st = check_hip(launch_join_step(js, s), "join step");
+    if (st != PT_OK) return st;
+  }
+  if (w >= 3) return check_hip(launch_join_finish(counts + w + 1, w - 2, out_cap, d_n_out, s), "join finish");
+  return PT_OK;
 }
 
 }  // extern "C"

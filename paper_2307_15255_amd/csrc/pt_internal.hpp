@@ -302,4 +302,73 @@ hipError_t prepare_batch_512();
 // Bytes of LDS a probe workgroup needs besides its staged filters.
 uint64_t probe_queue_bytes();
 
+// ---------------------------------------------------------- join phase
+// (k_join.hip) Hash joins on the reduced tables: each table added to the
+// join gets a hash table over its selected rows; the tuples built so far
+// probe it and are extended by every match.
+
+constexpr uint32_t kMaxJoinWidth = 32;  // tables in one join
+constexpr uint32_t kMaxJoinChecks = 8;  // edges checked per added table besides the lookup edge
+constexpr uint32_t kJoinNone = 0xFFFFFFFFu;
+
+// Hash table of one table's selected rows: open addressing on the keys,
+// each key's rows chained through `next`. Its used size follows the number
+// of selected rows (twice that, rounded up to a power of two, at least 64,
+// at most the capacity 2^lg_cap).
+struct JoinHash {
+  unsigned long long *keys;  // 2^lg_cap + 1 slots; the last one belongs to kJoinEmptyKey
+  uint32_t *heads;           // 2^lg_cap + 1: first entry of the slot's chain, kJoinNone if none
+  uint32_t *next;            // one per selected row: next entry with the same key, kJoinNone at the end
+  const uint32_t *ids;       // the table's selected row ids
+  const uint64_t *count;     // their number
+  const void *key;           // the key column the table is looked up by
+  uint32_t key64;
+  uint32_t lg_cap;
+  uint64_t n_rows;           // the table's rows (bounds *count and next[])
+};
+
+// One more edge between the added table and a table already joined.
+struct JoinCheck {
+  const void *v_col;  // the added table's column
+  const void *p_col;  // the joined table's column
+  uint32_t v64, p64;
+  uint32_t pos;  // the joined table's place in the tuples
+  uint32_t pad;
+};
+
+// One join step: tuples of `width` row ids (columns in[0..width)) probe the
+// hash table of the added table by the key of the joined table at place
+// u_pos; every match that passes the checks becomes a tuple of width + 1
+// ids in out[0..width] (the added table's id last).
+struct JoinStep {
+  JoinHash h;
+  const void *u_key;
+  uint32_t u64;
+  uint32_t u_pos;
+  uint32_t width;
+  uint32_t n_checks;
+  JoinCheck checks[kMaxJoinChecks];
+  const uint32_t *in[kMaxJoinWidth];
+  uint32_t *out[kMaxJoinWidth];
+  const uint64_t *n_in;  // tuples in (at most in_cap are read)
+  uint64_t *n_out;       // tuples produced (only the first cap are written)
+  uint64_t in_cap;
+  uint64_t cap;
+  uint32_t *status;
+};
+
+constexpr unsigned long long kJoinEmptyKey = 0x8000000000000000ull;  // INT64_MIN marks a free slot
+
+hipError_t launch_join_ids(const uint64_t *bitmap, uint64_t n_rows, uint32_t *ids, uint64_t *count,
+                           uint64_t *partials, hipStream_t s);
+hipError_t launch_join_build(const JoinHash &h, hipStream_t s);
+hipError_t launch_join_step(const JoinStep &st, hipStream_t s);
+// *n_out = the largest of step_counts[0..n_steps) and *n_out when one of
+// step_counts exceeds cap (an intermediate step overflowed).
+hipError_t launch_join_finish(const uint64_t *step_counts, uint32_t n_steps, uint64_t cap, uint64_t *n_out,
+                              hipStream_t s);
+// dst[i] = src[i] for i < min(*n, cap); *n_out = *n (a one-table join).
+hipError_t launch_join_copy(const uint32_t *src, const uint64_t *n, uint64_t cap, uint32_t *dst, uint64_t *n_out,
+                            uint32_t *status, hipStream_t s);
+
 }  // namespace pt

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpt_hip.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EUNSUPPORTED, PT_EOVERFLOW = 0, 1, 2, 3, 4, 5
-PT_STATUS_FILTER_OVERFLOW, PT_STATUS_ENTRIES_OVERFLOW = 1, 2
+PT_STATUS_FILTER_OVERFLOW, PT_STATUS_ENTRIES_OVERFLOW, PT_STATUS_WAIT_TIMEOUT, PT_STATUS_JOIN_OVERFLOW = 1, 2, 4, 8
 PT_PROBE_SELECTIVE, PT_PROBE_GIVEN = 0, 1
 PT_I32, PT_I64 = 0, 1
 OPS = {"lt": 0, "le": 1, "gt": 2, "ge": 3, "eq": 4, "ne": 5, "between": 6}
@@ -111,6 +111,9 @@ def _load() -> C.CDLL:
         "pt_batch_timeline": ([vp, C.POINTER(u64), u32, C.POINTER(u32), C.POINTER(u32)], st),
         "pt_batch_free": ([vp], None),
         "pt_transfer_batch": ([u32, C.POINTER(pt_problem), vp, C.c_size_t, vp], st),
+        "pt_join_workspace_size": ([C.POINTER(pt_graph), C.POINTER(pt_table), u32, u64, sizep], st),
+        "pt_join": ([C.POINTER(pt_graph), C.POINTER(pt_table), u32, C.POINTER(vp), C.POINTER(vp), u64, vp, vp,
+                     C.c_size_t, vp], st),
         "pt_profile_enable": ([C.c_int], st),
         "pt_profile_read": ([C.POINTER(pt_kernel_time), u32, C.POINTER(u32)], st),
     }
@@ -126,7 +129,8 @@ EXPORTS = ("pt_version", "pt_last_error", "pt_check_status", "pt_local_filter", 
            "pt_bloom_probe", "pt_compact_workspace_size", "pt_compact", "pt_compact_noalloc", "pt_transfer_workspace_size",
            "pt_transfer", "pt_transfer_filter", "pt_batch_workspace_size", "pt_batch_prepare",
            "pt_batch_prepare_async", "pt_batch_run",
-           "pt_batch_info", "pt_batch_timeline", "pt_batch_free", "pt_transfer_batch", "pt_profile_enable", "pt_profile_read")
+           "pt_batch_info", "pt_batch_timeline", "pt_batch_free", "pt_transfer_batch", "pt_join_workspace_size",
+           "pt_join", "pt_profile_enable", "pt_profile_read")
 PT_BATCH_EAGER = 1
 
 
@@ -359,6 +363,70 @@ class Transfer:
         n = nb * (self.params.block_bits // 32)
         words = self.ws[off:off + 4 * n].cpu().numpy().view(np.uint32)
         return words, nb, builder
+
+
+def pt_join_workspace_size(dp: DeviceProblem, root: int, out_cap: int) -> int:
+    out = C.c_size_t()
+    _check(_lib.pt_join_workspace_size(C.byref(dp.graph), dp.tables, root, out_cap, C.byref(out)))
+    return out.value
+
+
+def pt_join(dp: DeviceProblem, root: int, bitmaps: list | None, out: list, out_cap: int, n_out: torch.Tensor,
+            ws: torch.Tensor, stream=None) -> None:
+    """bitmaps: None, or per table a bitmap tensor (None: every row); out:
+    per table a uint32 tensor of out_cap ids (None outside root's
+    component)."""
+    n = max(1, dp.n_tables)
+    bm = None
+    if bitmaps is not None:
+        bm = (C.c_void_p * n)(*[b.data_ptr() if b is not None and b.numel() else None for b in bitmaps])
+    op = (C.c_void_p * n)(*[o.data_ptr() if o is not None else None for o in out])
+    _check(_lib.pt_join(C.byref(dp.graph), dp.tables, root, bm, op, out_cap, _ptr(n_out), _ptr(ws), ws.numel(),
+                        _stream(stream)))
+
+
+def component_of(problem, root: int) -> list[int]:
+    """Tables connected to root through join edges, ascending."""
+    seen, todo = {root}, [root]
+    while todo:
+        t = todo.pop()
+        for u, _, v, _ in problem.edges:
+            for a, b in ((u, v), (v, u)):
+                if a == t and b not in seen:
+                    seen.add(b)
+                    todo.append(b)
+    return sorted(seen)
+
+
+class Join:
+    """Workspace and outputs of the join phase (pt_join) on one problem: row
+    ids of every tuple, one uint32 column per table of root's component."""
+
+    def __init__(self, dp: DeviceProblem, root: int | None = None, out_cap: int = 1 << 20, device="cuda"):
+        self.dp = dp
+        if root is None:  # start from the largest table: the added tables are the build sides
+            root = max(range(dp.n_tables), key=lambda t: (dp.n_rows[t], -t))
+        self.root = root
+        self.comp = component_of(dp.problem, root)
+        self.out_cap = out_cap
+        self.ws = torch.empty(pt_join_workspace_size(dp, root, out_cap), dtype=torch.uint8, device=device)
+        self.out = [torch.empty(max(1, out_cap), dtype=torch.int32, device=device) if t in self.comp else None
+                    for t in range(dp.n_tables)]
+        self.n_out = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def run(self, bitmaps: list | None = None, stream=None) -> None:
+        pt_join(self.dp, self.root, bitmaps, self.out, self.out_cap, self.n_out, self.ws, stream)
+
+    def check_status(self, stream=None) -> None:
+        pt_check_status(self.ws, stream)
+
+    def tuples(self) -> np.ndarray:
+        """The tuples of the last run (columns: self.comp), sorted."""
+        n = int(self.n_out.item())
+        n = min(n, self.out_cap)
+        cols = [self.out[t][:n].cpu().numpy().view(np.uint32) for t in self.comp]
+        arr = np.stack(cols, axis=1) if cols else np.zeros((n, 0), np.uint32)
+        return arr[np.lexsort(arr.T[::-1])] if n else arr
 
 
 def pt_batch_workspace_size(dps: list[DeviceProblem], ps: list[pt_params]) -> int:

@@ -146,3 +146,57 @@ def test_compact_noalloc_rejects_inputs_beyond_its_scratch(ptlib):
     assert lib.pt_compact_noalloc(None, (1 << 31) + 1, None, None, None) == ptlib.PT_EINVAL
     assert "2^31" in lib.pt_last_error().decode()
     assert lib.pt_compact_noalloc(None, 10, None, None, None) == ptlib.PT_EINVAL  # NULL count
+
+
+def _join_ws(ptlib, prob, root, cap):
+    out = C.c_size_t()
+    st = ptlib.lib().pt_join_workspace_size(C.byref(prob.graph), prob.tables, root, cap, C.byref(out))
+    return st, out.value
+
+
+def test_join_planner_validation(ptlib):
+    """pt_join's host checks and workspace sizing (no kernel runs)."""
+    chain = _HostProblem(ptlib, [10, 100, 1000], [(0, 0, 1, 0), (1, 1, 2, 0)])
+    st, size = _join_ws(ptlib, chain, 2, 4096)
+    assert st == ptlib.PT_OK
+    # ids of three tables, hash tables of the two added ones (at least twice
+    # their rows in 8-byte keys), two buffers of two-column intermediate tuples
+    assert size >= 4 * 1110 + 12 * (2 * 10 + 2 * 100) + 2 * 2 * 4096 * 4
+    assert _join_ws(ptlib, chain, 2, 8192)[1] > size  # intermediates grow with out_cap
+    two = _HostProblem(ptlib, [10, 100], [(0, 0, 1, 0)])
+    assert _join_ws(ptlib, two, 1, 1 << 30)[1] < 1 << 20  # a two-table join has no intermediates
+    lone = _HostProblem(ptlib, [10, 100, 7], [(0, 0, 1, 0)])
+    assert _join_ws(ptlib, lone, 2, 100)[0] == ptlib.PT_OK  # a table with no edge joins alone
+    assert _join_ws(ptlib, chain, 3, 100)[0] == ptlib.PT_EINVAL  # root out of range
+    assert _join_ws(ptlib, _HostProblem(ptlib, [10, 100], [(0, 0, 0, 1)]), 0, 100)[0] == ptlib.PT_EINVAL
+    assert _join_ws(ptlib, _HostProblem(ptlib, [10, 100], [(0, 0, 1, 5)]), 0, 100)[0] == ptlib.PT_EINVAL
+    assert _join_ws(ptlib, _HostProblem(ptlib, [10, 100], [(0, 0, 1, 0, 1)]), 0, 100)[0] == ptlib.PT_EUNSUPPORTED
+    assert _join_ws(ptlib, chain, 0, (1 << 36) + 1)[0] == ptlib.PT_EINVAL
+    # more than 32 tables in one component
+    big = _HostProblem(ptlib, [5] * 33, [(i, 0, i + 1, 0) for i in range(32)])
+    assert _join_ws(ptlib, big, 0, 100)[0] == ptlib.PT_EUNSUPPORTED
+    # ten edges from one table to the tables before it
+    par = _HostProblem(ptlib, [5, 5], [(0, 0, 1, 0)] * 10)
+    assert _join_ws(ptlib, par, 0, 100)[0] == ptlib.PT_EUNSUPPORTED
+    assert _join_ws(ptlib, _HostProblem(ptlib, [5, 5], [(0, 0, 1, 0)] * 9), 0, 100)[0] == ptlib.PT_OK
+
+
+def test_join_rejects_bad_buffers(ptlib):
+    lib = ptlib.lib()
+    chain = _HostProblem(ptlib, [10, 100, 1000], [(0, 0, 1, 0), (1, 1, 2, 0)])
+    st, size = _join_ws(ptlib, chain, 2, 16)
+    n_out = C.c_uint64()
+    outs = (C.c_void_p * 3)(1 << 12, 1 << 12, 1 << 12)
+    # NULL workspace, misaligned workspace, short workspace, NULL count, NULL output column
+    assert lib.pt_join(C.byref(chain.graph), chain.tables, 2, None, outs, 16, C.byref(n_out), None, size,
+                       None) == ptlib.PT_EINVAL
+    assert lib.pt_join(C.byref(chain.graph), chain.tables, 2, None, outs, 16, C.byref(n_out), 4096 + 8, size,
+                       None) == ptlib.PT_EINVAL
+    assert lib.pt_join(C.byref(chain.graph), chain.tables, 2, None, outs, 16, C.byref(n_out), 4096, size - 1,
+                       None) == ptlib.PT_ENOMEM
+    assert lib.pt_join(C.byref(chain.graph), chain.tables, 2, None, outs, 16, None, 4096, size,
+                       None) == ptlib.PT_EINVAL
+    outs[1] = None
+    assert lib.pt_join(C.byref(chain.graph), chain.tables, 2, None, outs, 16, C.byref(n_out), 4096, size,
+                       None) == ptlib.PT_EINVAL
+    assert "d_out[1]" in lib.pt_last_error().decode()
