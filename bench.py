@@ -43,6 +43,7 @@ def parse():
                     help="builds rescan the table instead of reading keys appended by its probe")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-join", action="store_true", help="star: skip the join-phase timing")
     ap.add_argument("--check", action="store_true", help="compare the result with the oracle")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without the per-kernel HIP events (no roofline figure)")
@@ -97,8 +98,14 @@ def host_cpu() -> str:
                     break
     except OSError:
         pass
-    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    return f"{n} logical CPUs available ({os.cpu_count()} online), {model}"
+    return f"{host_cores()} logical CPUs available ({os.cpu_count()} online), {model}"
+
+
+def host_cores() -> int:
+    """Logical CPUs this process may run on, at most 16 (the share of the
+    host one GPU comes with)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return max(1, min(16, n))
 
 
 def rows_probed(prob, order_src_dst) -> int:
@@ -236,6 +243,9 @@ def main():
         "kernel_ms": breakdown,
     }
 
+    if args.workload == "star" and not args.no_join:
+        out["join"] = bench_join(args, torch, pt, prob, dp, tr)
+
     if args.calibrate_copy:
         out["calibration_copy_bytes"] = 1 << 30
     traffic, source = measured_traffic(args.workload, dom_key)
@@ -245,27 +255,74 @@ def main():
 
     if args.check or not args.no_cpu_baseline:
         import oracle
-        # the whole workload, repeated until about 10 s of oracle work (at
-        # least once); the median run is reported
-        runs = []
-        while not runs or (sum(runs) < 10 and len(runs) < 5):
-            t = time.perf_counter()
-            ref = oracle.transfer(prob, 512, 3, bpk)
-            runs.append(time.perf_counter() - t)
-        cpu_s = float(np.median(runs))
+
+        def median_run(threads):
+            # the whole workload, repeated until about 8 s of oracle work (at
+            # least once); the median run and the last result
+            runs = []
+            while not runs or (sum(runs) < 8 and len(runs) < 5):
+                t = time.perf_counter()
+                res = oracle.transfer(prob, 512, 3, bpk, threads=threads)
+                runs.append(time.perf_counter() - t)
+            return float(np.median(runs)), len(runs), res
+
+        cpu_s, n_runs, ref = median_run(1)
         if not args.no_cpu_baseline:
+            # the oracle's row split over every available core (whole bitmap
+            # words per thread, private filter copies OR-ed): bit-exact with
+            # the one-thread run, checked here
+            cores = host_cores()
+            all_s, all_runs, ref_all = median_run(cores)
+            same = all(np.array_equal(a, b) for a, b in zip(ref.bitmaps, ref_all.bitmaps))
             out["cpu_baseline"] = {
-                "value": round(n_probed / cpu_s / 1e9, 4),
+                "value": round(n_probed / all_s / 1e9, 4),
                 "unit": "G rows/s",
-                "cores": 1,
+                "cores": cores,
                 "kind": "oracle",
-                "sample": f"the whole workload ({n_probed} rows probed), median of {len(runs)} runs of "
-                          f"{cpu_s:.2f} s, single thread; host: {host_cpu()}",
+                "sample": f"the whole workload ({n_probed} rows probed), median of {all_runs} runs of "
+                          f"{all_s:.2f} s on {cores} threads; host: {host_cpu()}",
+                "bit_exact_with_single_thread": bool(same),
+                "single_thread": {"value": round(n_probed / cpu_s / 1e9, 4), "cores": 1,
+                                  "sample": f"median of {n_runs} runs of {cpu_s:.2f} s"},
             }
         if args.check:
             ok = all(np.array_equal(tr.bitmap(t), ref.bitmaps[t]) for t in range(prob.n_tables))
             out["check"] = "bit-exact" if ok else "MISMATCH"
     print(json.dumps(out), flush=True)
+
+
+def bench_join(args, torch, pt, prob, dp, tr) -> dict:
+    """The join phase (Sec. 3.3) on the star, from the fact table, timed
+    with HIP events apart from the transfer steps: on the tables the
+    transfer phase reduced, and on the tables reduced by their local
+    predicates only (the plan without predicate transfer), which hands the
+    join every fact row."""
+    local = []
+    for t in range(prob.n_tables):
+        bm = torch.empty(pt.bitmap_words(prob.n_rows(t)), dtype=torch.int64, device="cuda")
+        cols = list(dp.columns[t].values())
+        preds = [(prob.col_index(t, c), op, lo, hi) for tt, c, op, lo, hi in prob.preds if tt == t]
+        pt.pt_local_filter(cols, preds, prob.n_rows(t), bm)
+        local.append(bm)
+    j = pt.Join(dp, root=0, out_cap=1 << 22)
+    res = {}
+    for name, bitmaps in (("after_transfer", tr.bitmaps), ("after_local_filters_only", local)):
+        for _ in range(2):
+            j.run(bitmaps)
+        j.check_status()
+        times = []
+        for _ in range(max(3, min(args.steps, 20))):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            j.run(bitmaps)
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        j.check_status()
+        res[name] = {"ms": round(float(np.median(times)), 4), "tuples": int(j.n_out.item())}
+    res["tuples_equal"] = res["after_transfer"]["tuples"] == res["after_local_filters_only"]["tuples"]
+    res["root"] = "fact table; dimensions added in edge order as hash-table build sides"
+    return res
 
 
 def bench_batch(args, torch, pt, W):
@@ -349,20 +406,29 @@ def bench_batch(args, torch, pt, W):
     }
     if not args.no_cpu_baseline:
         import oracle
-        # a bounded sample: the first problems until about 10 s of oracle work
+        # a bounded sample: the first problems until about 8 s of oracle
+        # work, on every available core (the oracle's row split), then the
+        # same problems on one thread
+        cores = host_cores()
         t = time.perf_counter()
         rows = 0
         for i, prob in enumerate(probs):
             p = ps[i]
-            oracle.transfer(prob, p.block_bits, p.k, p.bits_per_key)
+            oracle.transfer(prob, p.block_bits, p.k, p.bits_per_key, threads=cores)
             rows += rows_probed(prob, orientation(prob))
-            if time.perf_counter() - t > 10:
+            if time.perf_counter() - t > 8:
                 break
         cpu_s = time.perf_counter() - t
-        out["cpu_baseline"] = {"value": round(rows / cpu_s / 1e9, 4), "unit": "G rows/s", "cores": 1,
+        t = time.perf_counter()
+        for prob, p in zip(probs[:i + 1], ps):
+            oracle.transfer(prob, p.block_bits, p.k, p.bits_per_key)
+        one_s = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(rows / cpu_s / 1e9, 4), "unit": "G rows/s", "cores": cores,
                                "kind": "oracle",
-                               "sample": f"the first {i + 1} problems ({rows} rows probed in {cpu_s:.2f} s, "
-                                         f"single thread)"}
+                               "sample": f"the first {i + 1} problems ({rows} rows probed in {cpu_s:.2f} s on "
+                                         f"{cores} threads); host: {host_cpu()}",
+                               "single_thread": {"value": round(rows / one_s / 1e9, 4), "cores": 1,
+                                                 "sample": f"the same problems in {one_s:.2f} s"}}
     print(json.dumps(out), flush=True)
 
 

@@ -57,7 +57,8 @@ class _Problem(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("block_bits", C.c_uint32), ("k", C.c_uint32), ("bits_per_key", C.c_uint32),
-                ("kind", C.c_uint32), ("n_passes", C.c_uint32), ("variant", C.c_uint32)]
+                ("kind", C.c_uint32), ("n_passes", C.c_uint32), ("variant", C.c_uint32),
+                ("threads", C.c_uint32), ("pad", C.c_uint32)]
 
 
 class _Dump(C.Structure):
@@ -71,11 +72,12 @@ class _Dump(C.Structure):
 
 def build(force: bool = True) -> str:
     """Compile pt_oracle.c with gcc into oracle/libpt_oracle.so (plain -O2,
-    single-threaded, no SIMD intrinsics)."""
+    no SIMD intrinsics; OpenMP only for the optional row split of the
+    transfer's scans, off unless threads > 1 is asked for)."""
     if not force and os.path.exists(_LIB_PATH):
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-fopenmp",
                            "-o", tmp, _SRC])
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -90,7 +92,7 @@ def build_variant(source_text: str, out_path: str) -> str:
     src = out_path + ".c"
     with open(src, "w") as f:
         f.write(source_text)
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-I", _HERE,
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-I", _HERE,
                            "-o", out_path, src])
     return out_path
 
@@ -273,13 +275,14 @@ def _problem(problem, keep: list) -> _Problem:
 
 def transfer(problem, block_bits: int = 512, k: int = 3, bits_per_key: int = 10,
              kind: int = BLOOM, n_passes: int = 2, variant: int = 0,
-             dump_filters: bool = False) -> TransferResult:
-    """Run the transfer phase on a `workloads.Problem`."""
+             dump_filters: bool = False, threads: int = 1) -> TransferResult:
+    """Run the transfer phase on a `workloads.Problem` (threads > 1: the row
+    scans split over that many threads, with the same results)."""
     L = lib()
     n_t, n_e = problem.n_tables, len(problem.edges)
     keep: list = []
     prob = _problem(problem, keep)
-    par = _Params(block_bits, k, bits_per_key, kind, n_passes, variant)
+    par = _Params(block_bits, k, bits_per_key, kind, n_passes, variant, threads, 0)
 
     res = TransferResult()
     res.bitmaps = [np.zeros(max(1, bitmap_words(problem.n_rows(t))), np.uint64) for t in range(n_t)]

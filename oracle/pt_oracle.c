@@ -3,7 +3,10 @@
  *
  * TEST INFRASTRUCTURE ONLY (see pt_oracle.h). Written for reading, not for
  * speed: one row at a time, one filter at a time, in the order the paper
- * describes the steps (Sec. 3.2).
+ * describes the steps (Sec. 3.2). The transfer's row scans can optionally be
+ * split over threads by whole bitmap words (params.threads), which changes
+ * no result: probes and predicates touch only their own rows' bits, and a
+ * Bloom filter is the OR of the copies built from disjoint rows.
  */
 #include "pt_oracle.h"
 
@@ -91,6 +94,15 @@ static uint64_t bitmap_words(uint64_t n_rows) { return (n_rows + 63) / 64; }
 static int bit_get(const uint64_t *bm, uint64_t r) { return (int)((bm[r / 64] >> (r % 64)) & 1u); }
 static void bit_set(uint64_t *bm, uint64_t r) { bm[r / 64] |= 1ULL << (r % 64); }
 static void bit_clear(uint64_t *bm, uint64_t r) { bm[r / 64] &= ~(1ULL << (r % 64)); }
+
+/* One past the last row of bitmap word w. */
+static uint64_t row_end(int64_t w, uint64_t n_rows) {
+  const uint64_t end = (uint64_t)w * 64 + 64;
+  return end < n_rows ? end : n_rows;
+}
+
+/* Threads of the row-split scans (params.threads; 0 means one). */
+static int n_threads(const ptor_params *pa) { return pa->threads > 1 ? (int)pa->threads : 1; }
 
 static uint64_t bitmap_popcount(const uint64_t *bm, uint64_t n_rows) {
   uint64_t c = 0;
@@ -200,13 +212,39 @@ static int filter_build(filter_t *f, const ptor_params *pa, const ptor_column *c
   uint64_t n_sel = bitmap_popcount(bitmap, n_rows);
   if (pa->kind == PTOR_BLOOM) {
     f->nb = ptor_filter_blocks(n_sel, pa->bits_per_key, pa->block_bits);
-    f->words = (uint32_t *)calloc(f->nb * (pa->block_bits / 32), sizeof(uint32_t));
+    const uint64_t n_fw = f->nb * (pa->block_bits / 32);
+    f->words = (uint32_t *)calloc(n_fw, sizeof(uint32_t));
     if (!f->words) return PTOR_ENOMEM;
-    for (uint64_t r = 0; r < n_rows; r++) {
-      if (bit_get(bitmap, r))
-        ptor_bloom_insert(f->words, f->nb, pa->block_bits, pa->k, column_value(col, r));
+    if (n_threads(pa) <= 1) {
+      for (uint64_t r = 0; r < n_rows; r++) {
+        if (bit_get(bitmap, r))
+          ptor_bloom_insert(f->words, f->nb, pa->block_bits, pa->k, column_value(col, r));
+      }
+      return PTOR_OK;
     }
-    return PTOR_OK;
+    /* Row split: each thread inserts its rows into a private copy; OR is
+     * order-free, so OR-ing the copies gives the filter bit for bit. */
+    const int64_t n_words = (int64_t)bitmap_words(n_rows);
+    int failed = 0;
+#pragma omp parallel num_threads(n_threads(pa))
+    {
+      uint32_t *mine = (uint32_t *)calloc(n_fw, sizeof(uint32_t));
+#pragma omp for schedule(static)
+      for (int64_t w = 0; w < n_words; w++) {
+        const uint64_t end = row_end(w, n_rows);
+        for (uint64_t r = (uint64_t)w * 64; r < end && mine; r++) {
+          if (bit_get(bitmap, r)) ptor_bloom_insert(mine, f->nb, pa->block_bits, pa->k, column_value(col, r));
+        }
+      }
+#pragma omp critical
+      {
+        if (!mine) failed = 1;
+        else
+          for (uint64_t i = 0; i < n_fw; i++) f->words[i] |= mine[i];
+      }
+      free(mine);
+    }
+    return failed ? PTOR_ENOMEM : PTOR_OK;
   }
   f->keys = (int64_t *)malloc((n_sel ? n_sel : 1) * sizeof(int64_t));
   if (!f->keys) return PTOR_ENOMEM;
@@ -322,9 +360,14 @@ static int run_pass(const ptor_problem *p, const ptor_params *pa, uint32_t pass,
       uint32_t e = reverse_probe ? m - 1 - j : j;
       if (dst[e] != v) continue;
       const ptor_column *col = edge_column(p, e, v);
-      for (uint64_t r = 0; r < t->n_rows; r++) {
-        if (bit_get(bitmaps[v], r) && !filter_contains(&filters[e], pa, column_value(col, r)))
-          bit_clear(bitmaps[v], r);
+      const int64_t n_words = (int64_t)bitmap_words(t->n_rows);
+      uint64_t *bm = bitmaps[v];
+#pragma omp parallel for num_threads(n_threads(pa)) schedule(static) if (n_threads(pa) > 1)
+      for (int64_t w = 0; w < n_words; w++) {
+        const uint64_t end = row_end(w, t->n_rows);
+        for (uint64_t r = (uint64_t)w * 64; r < end; r++) {
+          if (bit_get(bm, r) && !filter_contains(&filters[e], pa, column_value(col, r))) bit_clear(bm, r);
+        }
       }
     }
     for (uint32_t e = 0; e < m; e++) {
@@ -373,15 +416,22 @@ int ptor_transfer(const ptor_problem *p, const ptor_params *pa, uint64_t *const 
 
   /* Local predicates first: each table starts from its own filtered rows. */
   for (uint32_t t = 0; t < n; t++) {
-    memset(bitmaps[t], 0, bitmap_words(p->tables[t].n_rows) * sizeof(uint64_t));
-    for (uint64_t r = 0; r < p->tables[t].n_rows; r++) {
-      int keep = 1;
-      for (uint32_t i = 0; i < p->n_preds; i++) {
-        const ptor_pred *pr = &p->preds[i];
-        if (pr->table == t && !predicate_holds(pr, column_value(&p->tables[t].cols[pr->col], r)))
-          keep = 0;
+    const uint64_t n_rows = p->tables[t].n_rows;
+    const int64_t n_words = (int64_t)bitmap_words(n_rows);
+    uint64_t *bm = bitmaps[t];
+    memset(bm, 0, (uint64_t)n_words * sizeof(uint64_t));
+#pragma omp parallel for num_threads(n_threads(pa)) schedule(static) if (n_threads(pa) > 1)
+    for (int64_t w = 0; w < n_words; w++) {
+      const uint64_t end = row_end(w, n_rows);
+      for (uint64_t r = (uint64_t)w * 64; r < end; r++) {
+        int keep = 1;
+        for (uint32_t i = 0; i < p->n_preds; i++) {
+          const ptor_pred *pr = &p->preds[i];
+          if (pr->table == t && !predicate_holds(pr, column_value(&p->tables[t].cols[pr->col], r)))
+            keep = 0;
+        }
+        if (keep) bit_set(bm, r);
       }
-      if (keep) bit_set(bitmaps[t], r);
     }
   }
 

@@ -105,6 +105,11 @@ typedef struct {
   uint32_t variant;      /* bit 0: visit ready nodes largest id first;
                             bit 1: probe incoming filters in reverse edge order.
                             Neither may change any result. */
+  uint32_t threads;      /* threads splitting the row scans (0 or 1: one);
+                            each takes whole 64-row bitmap words, Bloom builds
+                            fill private copies that are OR-ed together, so
+                            the result does not depend on the count */
+  uint32_t pad;
 } ptor_params;
 
 /* Optional outputs for inspection. Any pointer may be NULL.

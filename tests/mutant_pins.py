@@ -12,6 +12,7 @@ import numpy as np  # noqa: E402
 import oracle  # noqa: E402
 import test_oracle_filter as F  # noqa: E402
 import test_oracle_join as J  # noqa: E402
+import test_oracle_threads as TH  # noqa: E402
 import test_oracle_transfer as T  # noqa: E402
 
 
@@ -34,6 +35,7 @@ def checks():
     for shape in ("tree", "cycle"):
         yield lambda shape=shape: J.test_join_matches_brute_force(None, shape)
     yield lambda: J.test_join_edge_cases(None)
+    yield lambda: TH.test_threads_tiny(None, "tree")
 
 
 def main():

@@ -27,8 +27,9 @@ MUTANTS = {
                            "u_first = (nu < nv) || (nu == nv && u > v);"),
     "backward_not_reversed": ("rc = run_pass(p, pa, 1, dst, src, rev_order",
                               "rc = run_pass(p, pa, 1, src, dst, order"),
-    "probe_never_clears": ("bit_clear(bitmaps[v], r);\n      }\n    }",
-                           "(void)0;\n      }\n    }"),
+    "probe_never_clears": ("column_value(col, r))) bit_clear(bm, r);", "column_value(col, r))) (void)0;"),
+    "threads_merge_overwrites": ("f->words[i] |= mine[i];", "f->words[i] = mine[i];"),
+    "threads_split_drops_tail": ("const uint64_t end = (uint64_t)w * 64 + 64;", "const uint64_t end = (uint64_t)w * 64 + 63;"),
     "between_exclusive": ("p->lo <= v && v <= p->hi", "p->lo <= v && v < p->hi"),
     "lt_as_le": ("case PTOR_LT: return v < p->lo;", "case PTOR_LT: return v <= p->lo;"),
     "zero_extend_int32": ("return (int64_t)((const int32_t *)c->data)[r];",
