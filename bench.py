@@ -485,6 +485,7 @@ def bench_served(args, torch, pt, W):
             "served": {"p50_ms": round(srv.percentile(50) * 1e3, 3), "p99_ms": round(srv.percentile(99) * 1e3, 3),
                        "G_rows_probed_per_s": round(rows / srv.wall / 1e9, 3), "batches": len(srv.batches),
                        "mean_batch": round(len(qs) / len(srv.batches), 2),
+                       "rejected": len(srv.rejected), "timed_out": len(srv.timed_out),
                        "peak_admitted_GB": round(srv.peak_bytes / 2**30, 2)},
             "one_at_a_time": {"p50_ms": round(fifo.percentile(50) * 1e3, 3),
                               "p99_ms": round(fifo.percentile(99) * 1e3, 3),

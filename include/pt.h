@@ -170,7 +170,7 @@ typedef struct pt_params {
   uint32_t block_bits;   /* B: 32, 64, 128, 256, 512 or 1024 */
   uint32_t k;            /* 1..16 */
   uint32_t bits_per_key; /* 1..64 */
-  uint32_t flags;        /* 0 or PT_FLAG_NO_APPEND */
+  uint32_t flags;        /* PT_FLAG_* bits */
   uint32_t hash_version;
   uint32_t lds_budget;
   uint32_t tile_rows;
@@ -186,6 +186,17 @@ typedef struct pt_params {
  * a table once). With this flag the builds scan the table's selected rows
  * again and the workspace holds no appended keys. The bits are the same. */
 #define PT_FLAG_NO_APPEND 1u
+
+/* In a batch, the probes of problems with this flag that scan tables of the
+ * same rows through the same key columns (a resident table they all join)
+ * are grouped into shared scans (at most 16 problems and 4 key columns per
+ * group): one pass over the table reads each key column once and tests the
+ * filters of every grouped problem whose filters fit in LDS with the
+ * others', each problem keeping its own bitmap; the other problems of the
+ * group are probed one after the other on the same rows. The bits are the
+ * same either way. It pays when the key reads dominate (small filters); when
+ * filters are read from global memory the separate probes are faster. */
+#define PT_FLAG_SHARED_SCAN 2u
 
 /* A Bloom filter in device memory. `words` holds cap_words uint32 words; the
  * filter in use is its first nb * B/32 words, where nb is the uint64 at

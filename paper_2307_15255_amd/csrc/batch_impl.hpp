@@ -146,8 +146,8 @@ __device__ __forceinline__ void zero_body(const BBuild &b, uint32_t lg, uint32_t
   if (part_geo(b.fs, lg, b.bits_per_key, b.count, b.n_rows, b.entries_cap, true, kBatchTargetBuckets).ok) return;
   const uint64_t n_sel = load_shared_u64(b.count);
   filter_offsets(b, lg, n_sel, s_off);
-  const uint64_t w0 = static_cast<uint64_t>(vg.block) * kReduceWords;
-  const uint64_t w1 = min(w0 + kReduceWords, static_cast<uint64_t>(s_off[b.fs.n]));
+  const uint64_t w0 = static_cast<uint64_t>(vg.block) * kZeroWords;
+  const uint64_t w1 = min(w0 + kZeroWords, static_cast<uint64_t>(s_off[b.fs.n]));
   for (uint64_t w = w0 + threadIdx.x; w < w1; w += blockDim.x) {
     uint32_t i = 0;
     while (i + 1 < b.fs.n && w >= s_off[i + 1]) i++;
@@ -183,6 +183,175 @@ __device__ __forceinline__ void scan_body(const BBuild &b, uint32_t lg, uint64_t
     carry += total;
   }
   if (threadIdx.x == 0) b.starts[buckets] = carry;
+}
+
+// One item of a shared scan. The members whose filters fit in LDS together
+// (taken in member order) are staged there and probed in one pass: each
+// wave takes groups of four bitmap words (256 rows), loads and hashes the
+// rows' keys of every column once, and tests each of those members' filters
+// on them (most selective first, only rows still alive). The other members
+// are then probed one after the other.
+static_assert(kMaxSharedMembers * 4 <= kWave, "a shared scan loads every member's bitmap words in one wave load");
+
+template <int B, int K>
+__device__ __forceinline__ void shared_probe_body(const BatchArgs &a, const BShared &sh, uint32_t *lds,
+                                                  const VGrid &vg) {
+  constexpr int U = 4;
+  __shared__ uint32_t s_off[kMaxSharedMembers][kMaxProbe];
+  __shared__ uint32_t s_nb[kMaxSharedMembers][kMaxProbe];
+  __shared__ uint32_t s_ord[kMaxSharedMembers][kMaxProbe];  // member m's j-th filter to test
+  __shared__ unsigned long long s_cnt[kMaxSharedMembers];
+  const uint32_t n_m = sh.n_members;
+  const BProbe *mem = a.probes + sh.first_probe;
+  const uint32_t lg = block_log2<B>(mem[0].lg);
+  const uint32_t W = 1u << (lg - 5);
+  if (threadIdx.x < n_m) {
+    // Member m's filters, most selective first (builder rows kept / rows,
+    // as in the single probe; the order changes no bit), then staged in
+    // that order by thread 0 below.
+    const uint32_t m = threadIdx.x;
+    const FilterSet &fs = mem[m].fs;
+    uint64_t sel[kMaxProbe], rows[kMaxProbe];
+    for (uint32_t j = 0; j < fs.n; j++) {
+      s_ord[m][j] = j;
+      sel[j] = (fs.f[j].sel && fs.f[j].rows) ? *fs.f[j].sel : 1;
+      rows[j] = (fs.f[j].sel && fs.f[j].rows) ? fs.f[j].rows : 1;
+    }
+    for (uint32_t x = 1; x < fs.n; x++) {
+      for (uint32_t y = x; y > 0; y--) {
+        const uint32_t p = s_ord[m][y - 1], q = s_ord[m][y];
+        if (sel[q] * rows[p] < sel[p] * rows[q]) {
+          s_ord[m][y - 1] = q;
+          s_ord[m][y] = p;
+        } else {
+          break;
+        }
+      }
+    }
+    s_cnt[m] = 0;
+  }
+  __syncthreads();
+  __shared__ uint32_t s_in;  // bit m: member m's filters are all staged (it joins the shared pass)
+  if (threadIdx.x == 0) {
+    uint32_t used = 0, in = 0;
+    for (uint32_t m = 0; m < n_m; m++) {
+      uint64_t need = 0;
+      for (uint32_t j = 0; j < mem[m].fs.n; j++) {
+        const FilterRef &f = mem[m].fs.f[j];
+        s_nb[m][j] = clamp_blocks(*f.nb, f.cap_words / W, a.status);
+        need += static_cast<uint64_t>(s_nb[m][j]) * W;
+      }
+      if (used + need > a.lds_filter_words) continue;
+      for (uint32_t j = 0; j < mem[m].fs.n; j++) {
+        s_off[m][j] = used;
+        used += s_nb[m][j] * W;
+      }
+      in |= 1u << m;
+    }
+    s_in = in;
+  }
+  __syncthreads();
+  const uint32_t in = __builtin_amdgcn_readfirstlane(s_in);
+  for (uint32_t m = 0; m < n_m; m++) {
+    if (!((in >> m) & 1)) continue;
+    for (uint32_t j = 0; j < mem[m].fs.n; j++) {
+      const uint32_t off = s_off[m][j];
+      const uint32_t n = s_nb[m][j] * W;
+      const uint32_t *src = mem[m].fs.f[j].words;
+      for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) lds[off + i] = src[i];
+    }
+  }
+  __syncthreads();
+
+  const uint32_t lane = lane_id();
+  const uint64_t n_rows = sh.n_rows;
+  const uint64_t n_words = (n_rows + 63) / 64;
+  const uint32_t n_cols = sh.n_cols;
+  for (uint64_t w0 = global_wave(vg) * U; in && w0 < n_words; w0 += wave_count(vg) * U) {
+    // every column's keys of the group, loaded and hashed once
+    uint32_t h1[kMaxSharedCols][U], h2[kMaxSharedCols][U];
+#pragma unroll
+    for (int c = 0; c < kMaxSharedCols; c++) {
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        h1[c][u] = h2[c][u] = 0;
+        if (c < static_cast<int>(n_cols)) {
+          const uint64_t row = min(w0 * 64 + u * 64 + lane, n_rows - 1);
+          hash_key(load_key(sh.cols[c], sh.key64[c], row), h1[c][u], h2[c][u]);
+        }
+      }
+    }
+    // every member's bitmap words of the group in one load: lane 4 m + u
+    // holds member m's word w0 + u
+    uint64_t all_bits = 0;
+    {
+      const uint32_t m = lane / U, u = lane % U;
+      if (m < n_m && w0 + u < n_words) all_bits = mem[m].bitmap[w0 + u];
+    }
+    for (uint32_t m = 0; m < n_m; m++) {
+      if (!((in >> m) & 1)) continue;
+      const BProbe &p = mem[m];
+      const uint32_t n_f = p.fs.n;
+      uint64_t word[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const uint32_t b_hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(all_bits >> 32), m * U + u);
+        const uint32_t b_lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(all_bits), m * U + u);
+        word[u] = tail_mask(w0 + u, n_words, n_rows) & ((static_cast<uint64_t>(b_hi) << 32) | b_lo);
+      }
+      // Filter by filter; the four words' filter reads are issued together
+      // (they come from L2 or beyond when the filter is not in LDS).
+      for (uint32_t jj = 0; jj < n_f; jj++) {
+        if ((word[0] | word[1] | word[2] | word[3]) == 0) break;
+        const uint32_t j = __builtin_amdgcn_readfirstlane(s_ord[m][jj]);
+        const uint32_t c = sh.col_of[m][j];
+        const uint32_t nb = __builtin_amdgcn_readfirstlane(s_nb[m][j]);
+        const uint32_t off = __builtin_amdgcn_readfirstlane(s_off[m][j]);
+        const uint32_t *words = lds + off;  // every filter is staged here
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          uint32_t x1 = h1[0][u], x2 = h2[0][u];
+#pragma unroll
+          for (int cc = 1; cc < kMaxSharedCols; cc++) {
+            if (c == static_cast<uint32_t>(cc)) {
+              x1 = h1[cc][u];
+              x2 = h2[cc][u];
+            }
+          }
+          // only rows still alive read the filter
+          ok[u] = ((word[u] >> lane) & 1) &&
+                  block_has<K>(words + (static_cast<uint64_t>(block_of(x1, nb)) << (lg - 5)), x2, p.k, lg);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) word[u] &= __ballot(ok[u]);
+      }
+      uint64_t mine = 0;
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        mine = lane == static_cast<uint32_t>(u) ? word[u] : mine;
+        cnt += static_cast<uint32_t>(__popcll(word[u]));
+      }
+      if (lane < U && w0 + lane < n_words) p.bitmap[w0 + lane] = mine;
+      if (lane == 0 && cnt) atomicAdd(&s_cnt[m], static_cast<unsigned long long>(cnt));
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < n_m && ((in >> threadIdx.x) & 1) && mem[threadIdx.x].count && s_cnt[threadIdx.x])
+    atomicAdd(reinterpret_cast<unsigned long long *>(mem[threadIdx.x].count), s_cnt[threadIdx.x]);
+  // Members whose filters did not fit: their filter reads, not the key
+  // reads, are the cost, so each is probed on the item's rows by the
+  // single-problem probe (most selective filter first, survivors
+  // compacted), which reads the keys again.
+  const AppendSet none{};
+  for (uint32_t m = 0; m < n_m; m++) {
+    if ((in >> m) & 1) continue;
+    __syncthreads();
+    const BProbe &p = mem[m];
+    probe_body<B, K, false>(p.fs, p.k, p.lg, p.n_rows, p.bitmap, reinterpret_cast<unsigned long long *>(p.count),
+                            a.lds_filter_words, 0, 0, a.status, none, vg);
+  }
 }
 
 template <int B, int K>
@@ -251,6 +420,9 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const BTask &task, 
                         vg.block, vg.blocks, true, kBatchTargetBuckets);
       break;
     }
+    case kBShared:
+      shared_probe_body<B, K>(a, a.shared[task.arg], lds, vg);
+      break;
     case kBCopy: {
       for (uint32_t i = threadIdx.x; i < task.n_arg; i += blockDim.x) {
         const CopyPair &c = a.pairs[task.arg + i];
@@ -310,7 +482,7 @@ hipError_t launch_batch_kernel(const BatchArgs &a, uint32_t grid, uint64_t lds_b
 template <int B, int K>
 hipError_t prepare_batch_kernel() {
   return allow_lds(reinterpret_cast<const void *>(k_batch<B, K>),
-                   static_cast<uint64_t>(device_info().max_lds_block) - 1024);
+                   static_cast<uint64_t>(device_info().max_lds_block) - 2048);  // as the launch (static LDS < 2 KB)
 }
 
 }  // namespace pt

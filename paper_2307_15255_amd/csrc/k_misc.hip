@@ -3,6 +3,7 @@
 // base tables), filter sizing, ordered compaction (the reduced row sets
 // handed to the join phase, Sec. 3.3), counters, and the launch helpers the
 // other kernel units share.
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -167,7 +168,11 @@ hipError_t allow_lds(const void *kern, uint64_t bytes) {
   std::lock_guard<std::mutex> lock(mu);
   uint64_t &g = granted[{dev, kern}];
   if (bytes <= g) return hipSuccess;
-  const uint64_t want = static_cast<uint64_t>(device_info().max_lds_block) - 1024;
+  // as much as the kernel's static LDS leaves (set once per kernel)
+  hipFuncAttributes attr{};
+  uint64_t static_bytes = 1024;
+  if (hipFuncGetAttributes(&attr, kern) == hipSuccess) static_bytes = std::max<uint64_t>(attr.sharedSizeBytes, 256);
+  const uint64_t want = static_cast<uint64_t>(device_info().max_lds_block) - ((static_bytes + 255) & ~uint64_t(255));
   hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      static_cast<int>(bytes > want ? bytes : want));
   if (e == hipSuccess) g = bytes > want ? bytes : want;

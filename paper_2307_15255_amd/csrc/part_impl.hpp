@@ -33,6 +33,29 @@ __device__ __forceinline__ uint32_t pack_entry(uint32_t blk_in_tile, uint32_t h2
 __device__ __forceinline__ uint32_t entry_block(uint32_t v, uint32_t lg) { return v >> (2 * lg); }
 __device__ __forceinline__ uint32_t entry_h2(uint32_t v, uint32_t lg) { return v << (32 - 2 * lg); }
 
+// Adds n to counter[b] for every active lane: the lanes whose b equals the
+// first active lane's add together with one atomic (keys with few distinct
+// values, a skewed foreign key, would otherwise serialise on one counter),
+// the others one by one. Returns each lane's previous count plus its rank
+// among the lanes that added to the same counter together.
+template <typename T>
+__device__ __forceinline__ T wave_counter_add(T *counter, uint32_t b) {
+  const uint32_t b0 = __builtin_amdgcn_readfirstlane(b);
+  const uint64_t same = __ballot(b == b0);
+  if (b != b0) return atomicAdd(&counter[b], T(1));
+  const uint32_t rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(same >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(same), 0));
+  T base = 0;
+  if (rank == 0) base = atomicAdd(&counter[b0], static_cast<T>(__popcll(same)));
+  // the first active lane of this branch is the rank-0 lane
+  if constexpr (sizeof(T) == 8)
+    base = (static_cast<T>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(base >> 32))) << 32) |
+           static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(base)));
+  else
+    base = static_cast<T>(__builtin_amdgcn_readfirstlane(static_cast<uint32_t>(base)));
+  return base + rank;
+}
+
 // Histogram of this workgroup's keys over the buckets, stored to hist_row.
 template <bool APP>
 __device__ __forceinline__ void part_count_body(const FilterSet &fs, const AppendSet &app, uint32_t lg,
@@ -52,7 +75,7 @@ __device__ __forceinline__ void part_count_body(const FilterSet &fs, const Appen
     const uint32_t nb = part_blocks(f, lg, bits_per_key, geo.n_sel, from_count);
     uint32_t *mine = s_hist + base;
     for_each_key<APP>(f, app, n_rows, bitmap, seg_words, vg,
-                      [&](uint32_t h1, uint32_t) { atomicAdd(&mine[block_of(h1, nb) / tb], 1u); });
+                      [&](uint32_t h1, uint32_t) { wave_counter_add(mine, block_of(h1, nb) / tb); });
     base += (nb + tb - 1) / tb;
   }
   __syncthreads();
@@ -93,7 +116,7 @@ __device__ __forceinline__ void part_scatter_body(const FilterSet &fs, const App
     unsigned long long *cur = reinterpret_cast<unsigned long long *>(s_cur) + base;
     for_each_key<APP>(f, app, n_rows, bitmap, seg_words, vg, [&](uint32_t h1, uint32_t h2) {
       const uint32_t blk = block_of(h1, nb);
-      const uint64_t pos = atomicAdd(&cur[blk / tb], 1ull);
+      const uint64_t pos = wave_counter_add(cur, blk / tb);
       if (pos < entries_cap)  // always true while *count is the bitmap's popcount
         entries[pos] = pack_entry(blk % tb, h2, lg);
       else
@@ -132,13 +155,22 @@ __device__ __forceinline__ void part_fill_body(const FilterSet &fs, uint32_t k, 
     for (uint32_t j = threadIdx.x; j < n_blocks * W; j += blockDim.x) tile[j] = 0;
     __syncthreads();
     const uint64_t e0 = min(starts[b], entries_cap), e1 = min(starts[b + 1], entries_cap);
-    for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-      const uint32_t v = entries[e];
-      // the entry names its block inside the tile; with nb = 1 and h1 = 0,
-      // insert_lds sets the key's k bits in the block it is pointed at
+    // the entry names its block inside the tile; with nb = 1 and h1 = 0,
+    // insert_lds sets the key's k bits in the block it is pointed at
+    auto insert = [&](uint32_t v) {
       const uint32_t blk = min(entry_block(v, lg), n_blocks - 1);
       insert_lds<K>(tile + blk * W, 1, k, 0, entry_h2(v, lg), lg);
+    };
+    uint64_t e = e0 + threadIdx.x;
+    // four entries per thread in flight (a bucket can hold millions)
+    for (; e + 3ull * blockDim.x < e1; e += 4ull * blockDim.x) {
+      uint32_t v[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) v[q] = entries[e + static_cast<uint64_t>(q) * blockDim.x];
+#pragma unroll
+      for (int q = 0; q < 4; q++) insert(v[q]);
     }
+    for (; e < e1; e += blockDim.x) insert(entries[e]);
     __syncthreads();
     uint32_t *out = fs.f[f].words + static_cast<uint64_t>(first) * W;
     for (uint32_t j = threadIdx.x; j < n_blocks * W; j += blockDim.x) out[j] = tile[j];

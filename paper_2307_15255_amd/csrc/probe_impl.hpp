@@ -9,8 +9,8 @@
 //   - orders the filters by their estimated pass rate (builder rows kept /
 //     builder rows), most selective first - the order cannot change the
 //     result, only the work;
-//   - copies all filters into its LDS when they fit together, else reads
-//     all of them from global memory (L2 / Infinity Cache / HBM).
+//   - copies the filters into its LDS in that order while they fit; the
+//     others are read from global memory (L2 / Infinity Cache / HBM).
 // Each wave then takes groups of kGroupWords bitmap words (1024 rows):
 //   - it streams the first filter's key column for the group (coalesced,
 //     the next group's keys already in flight while this one is tested) and
@@ -36,12 +36,22 @@ struct Slot {
 
 constexpr int kGroupWords = 16;  // bitmap words (64 rows each) per wave and group
 
+constexpr uint32_t kNotStaged = 0xFFFFFFFFu;  // a slot's filter is read from global memory
+
 template <int K, bool STAGED>
 __device__ __forceinline__ bool slot_has(const Slot &s, const uint32_t *lds_filter, uint32_t h1, uint32_t h2,
                                          uint32_t k, uint32_t lg) {
   const uint32_t blk = block_of(h1, s.nb);
   if (STAGED) return block_has<K>(lds_filter + (blk << (lg - 5)), h2, k, lg);
   return block_has<K>(s.words + (static_cast<uint64_t>(blk) << (lg - 5)), h2, k, lg);
+}
+
+// A later slot: staged or not is known at run time only (uniform branch).
+template <int K>
+__device__ __forceinline__ bool slot_has_any(const Slot &s, const uint32_t *lds_filters, uint32_t lds_off,
+                                             uint32_t h1, uint32_t h2, uint32_t k, uint32_t lg) {
+  if (lds_off != kNotStaged) return slot_has<K, true>(s, lds_filters + lds_off, h1, h2, k, lg);
+  return slot_has<K, false>(s, lds_filters, h1, h2, k, lg);
 }
 
 // 32-bit words of one wave's LDS slice: the compacted survivors' tags
@@ -216,7 +226,7 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const
               if (m[j]) {
                 uint32_t h1, h2;
                 hash_parts(xlo[j], xhi[j], sl[s].key64, h1, h2);
-                m[j] &= __ballot(slot_has<K, STAGED>(sl[s], lds_filters + lds_off[s], h1, h2, k, lg));
+                m[j] &= __ballot(slot_has_any<K>(sl[s], lds_filters, lds_off[s], h1, h2, k, lg));
                 mine = lane == u0 + j ? m[j] : mine;
               }
             }
@@ -257,7 +267,7 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const
         if (s < static_cast<int>(n_f)) {
           uint32_t h1, h2;
           hash_parts(klo[s], khi[s], sl[s].key64, h1, h2);
-          ok = ok && slot_has<K, STAGED>(sl[s], lds_filters + lds_off[s], h1, h2, k, lg);
+          ok = ok && slot_has_any<K>(sl[s], lds_filters, lds_off[s], h1, h2, k, lg);
         }
       }
       const uint64_t failed = __ballot(act && !ok);
@@ -326,7 +336,6 @@ __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint
   __shared__ uint32_t s_ord[kMaxProbe];
   __shared__ uint32_t s_nb[kMaxProbe];
   __shared__ uint32_t s_off[kMaxProbe];
-  __shared__ uint32_t s_staged;
   __shared__ unsigned long long s_cnt;
 
   __shared__ uint64_t s_sel[kMaxProbe];
@@ -364,29 +373,34 @@ __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint
         }
       }
     }
+    // In probe order, every filter that still fits goes to LDS; the rest
+    // are read from global memory.
     uint64_t need = 0;
     for (uint32_t j = 0; j < n_f; j++) {
       const FilterRef &f = fs.f[ord[j]];
       const uint32_t nb = clamp_blocks(s_nb_raw[ord[j]], f.cap_words / W, status);
       s_ord[j] = ord[j];
       s_nb[j] = nb;
-      s_off[j] = static_cast<uint32_t>(need);
-      need += static_cast<uint64_t>(nb) * W;
+      const uint64_t words = static_cast<uint64_t>(nb) * W;
+      if (need + words <= lds_filter_words) {
+        s_off[j] = static_cast<uint32_t>(need);
+        need += words;
+      } else {
+        s_off[j] = kNotStaged;
+      }
     }
-    s_staged = need <= lds_filter_words;
     s_cnt = 0;
   }
   __syncthreads();
-  const bool staged = s_staged != 0;
-  if (staged) {
-    for (uint32_t j = 0; j < n_f; j++) {
-      const uint32_t n = s_nb[j] * W;
-      const uint32_t *src = fs.f[__builtin_amdgcn_readfirstlane(s_ord[j])].words;
-      uint32_t *dst = lds + s_off[j];
-      for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
-    }
+  for (uint32_t j = 0; j < n_f; j++) {
+    if (s_off[j] == kNotStaged) continue;
+    const uint32_t n = s_nb[j] * W;
+    const uint32_t *src = fs.f[__builtin_amdgcn_readfirstlane(s_ord[j])].words;
+    uint32_t *dst = lds + s_off[j];
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
   }
   __syncthreads();
+  const bool staged = s_off[0] != kNotStaged;  // the filter every row is tested against
 
   // Slot j is filter s_ord[j]; slots past n_f repeat slot 0 (never tested).
   Slot sl[kMaxProbe];
@@ -416,6 +430,7 @@ __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint
   // each slice's 64-bit failure masks stay 8-byte aligned.
   uint32_t *slice = lds + lds_filter_words + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) * kSliceWords;
   int64_t cnt;
+  if (!staged) off[0] = 0;  // slot 0 takes the global path by template
   if (sl[0].key64) {
     if (staged)
       cnt = probe_loop<K, true, true, APPEND>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,

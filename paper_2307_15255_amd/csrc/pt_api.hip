@@ -127,7 +127,8 @@ pt_status check_params(const pt_params *p) {
   if (p->k < 1 || p->k > 16) return fail(PT_EINVAL, "k %u outside [1, 16]", p->k);
   if (p->bits_per_key < 1 || p->bits_per_key > 64)
     return fail(PT_EINVAL, "bits_per_key %u outside [1, 64]", p->bits_per_key);
-  if ((p->flags & ~PT_FLAG_NO_APPEND) != 0) return fail(PT_EINVAL, "params.flags: unknown bits 0x%x", p->flags);
+  if ((p->flags & ~(PT_FLAG_NO_APPEND | PT_FLAG_SHARED_SCAN)) != 0)
+    return fail(PT_EINVAL, "params.flags: unknown bits 0x%x", p->flags);
   if (p->hash_version > 1)
     return fail(PT_EUNSUPPORTED, "hash_version %u (this library implements version 1)", p->hash_version);
   if (p->tile_rows != 0 && (p->tile_rows % 4096 != 0 || p->tile_rows > (1u << 24)))
@@ -948,6 +949,7 @@ struct BatchPlan {
   std::vector<BProbe> probes;
   std::vector<BBuild> builds;
   std::vector<CopyPair> pairs;
+  std::vector<BShared> shared;
   uint64_t off_counts = 0, n_counts = 0, off_done = 0, zero_bytes = 0;
   uint32_t n_items = 0;
   uint64_t off_tables = 0, off_timeline = 0, total = 0;
@@ -1152,6 +1154,100 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
       for (uint32_t v : lvl[p][i]) max_lvl = std::max(max_lvl, v);
     }
   }
+  // A probe a shared scan may take: the only probe of a large table in its
+  // pass (tasks are created once the level's candidates are grouped).
+  struct ProbeCand {
+    uint32_t i, v;
+    BProbe pt;
+    std::vector<uint32_t> deps;
+    uint64_t n_words, bytes;
+  };
+  auto emit_probe = [&](const ProbeCand &c) {
+    // Every item first copies the filters into its LDS when they fit
+    // there: give it at least eight times their size in keys.
+    uint64_t filter_words = 0;
+    for (uint32_t j = 0; j < c.pt.fs.n; j++) filter_words += c.pt.fs.f[j].cap_words;
+    const uint64_t staged = filter_words <= lds_filter_words ? filter_words : 0;
+    const uint64_t probe_words = std::max<uint64_t>(words_per_item, staged * 4 * 8 / (64 * 4));
+    bp.bytes_moved += c.bytes;
+    writer[c.i][c.v] = add_task(kBProbe, div_up32(c.n_words, probe_words), c.deps,
+                                static_cast<uint32_t>(bp.probes.size()));
+    readers[c.i][c.v].clear();
+    bp.probes.push_back(c.pt);
+  };
+  // Groups probes of one level that scan tables of the same rows with the
+  // same filter shape, as long as their key columns (pointer and width)
+  // number at most kMaxSharedCols together; a group of one is a plain probe.
+  auto emit_shared = [&](std::vector<ProbeCand> &cands) {
+    struct Group {
+      std::vector<size_t> members;
+      std::vector<std::pair<const void *, uint32_t>> cols;
+    };
+    std::vector<Group> done;
+    std::map<std::tuple<uint64_t, uint32_t, uint32_t>, Group> open;
+    for (size_t ci = 0; ci < cands.size(); ci++) {
+      const ProbeCand &c = cands[ci];
+      const auto key = std::make_tuple(c.pt.n_rows, c.pt.k, c.pt.lg);
+      Group &g = open[key];
+      auto cols = g.cols;
+      for (uint32_t j = 0; j < c.pt.fs.n; j++) {
+        const auto col = std::make_pair(c.pt.fs.f[j].keys, c.pt.fs.f[j].key64);
+        if (std::find(cols.begin(), cols.end(), col) == cols.end()) cols.push_back(col);
+      }
+      if (!g.members.empty() &&
+          (cols.size() > static_cast<size_t>(kMaxSharedCols) || g.members.size() >= static_cast<size_t>(kMaxSharedMembers))) {
+        done.push_back(std::move(g));
+        g = Group{};
+        cols.clear();
+        for (uint32_t j = 0; j < c.pt.fs.n; j++) {
+          const auto col = std::make_pair(c.pt.fs.f[j].keys, c.pt.fs.f[j].key64);
+          if (std::find(cols.begin(), cols.end(), col) == cols.end()) cols.push_back(col);
+        }
+      }
+      g.members.push_back(ci);
+      g.cols = std::move(cols);
+    }
+    for (auto &kv : open)
+      if (!kv.second.members.empty()) done.push_back(std::move(kv.second));
+    std::sort(done.begin(), done.end(), [](const Group &x, const Group &y) { return x.members[0] < y.members[0]; });
+    for (const Group &g : done) {
+      if (g.members.size() == 1) {
+        emit_probe(cands[g.members[0]]);
+        continue;
+      }
+      BShared sh{};
+      const ProbeCand &c0 = cands[g.members[0]];
+      sh.n_rows = c0.pt.n_rows;
+      sh.n_members = static_cast<uint32_t>(g.members.size());
+      sh.n_cols = static_cast<uint32_t>(g.cols.size());
+      sh.first_probe = static_cast<uint32_t>(bp.probes.size());
+      for (uint32_t c = 0; c < sh.n_cols; c++) {
+        sh.cols[c] = g.cols[c].first;
+        sh.key64[c] = g.cols[c].second;
+        bp.bytes_moved += sh.n_rows * (g.cols[c].second ? 8 : 4);
+      }
+      std::vector<uint32_t> deps;
+      for (uint32_t m = 0; m < sh.n_members; m++) {
+        const ProbeCand &c = cands[g.members[m]];
+        for (uint32_t j = 0; j < c.pt.fs.n; j++) {
+          const auto col = std::make_pair(c.pt.fs.f[j].keys, c.pt.fs.f[j].key64);
+          sh.col_of[m][j] = static_cast<uint8_t>(std::find(g.cols.begin(), g.cols.end(), col) - g.cols.begin());
+        }
+        deps.insert(deps.end(), c.deps.begin(), c.deps.end());
+        bp.probes.push_back(c.pt);
+        bp.bytes_moved += 2 * c.n_words * 8;
+      }
+      const uint32_t id = add_task(kBShared, div_up32(c0.n_words, words_per_item), deps,
+                                   static_cast<uint32_t>(bp.shared.size()));
+      bp.shared.push_back(sh);
+      for (size_t ci : g.members) {
+        writer[cands[ci].i][cands[ci].v] = id;
+        readers[cands[ci].i][cands[ci].v].clear();
+      }
+    }
+    cands.clear();
+  };
+  std::vector<ProbeCand> cands;
   for (uint32_t p = 0; p < 2; p++) {
     for (uint32_t L = 0; L <= max_lvl; L++) {
       for (uint32_t i = 0; i < n_problems; i++) {
@@ -1167,9 +1263,9 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
           bp.rows_probed += pr.tables[v].n_rows;
           const uint64_t n_rows = pr.tables[v].n_rows, n_words = (n_rows + 63) / 64;
           for (uint32_t c0 = 0; c0 < in.size(); c0 += kMaxProbe) {
-            BProbe pt{};
-            std::vector<uint32_t> deps{writer[i][v]};
-            deps.insert(deps.end(), readers[i][v].begin(), readers[i][v].end());
+            ProbeCand c{i, v, BProbe{}, {writer[i][v]}, n_words, 2 * n_words * 8};
+            BProbe &pt = c.pt;
+            c.deps.insert(c.deps.end(), readers[i][v].begin(), readers[i][v].end());
             for (uint32_t j = c0; j < in.size() && pt.fs.n < static_cast<uint32_t>(kMaxProbe); j++) {
               const uint32_t e = in[j];
               const uint32_t from = p == 0 ? pl.src[e] : pl.dst[e];
@@ -1178,10 +1274,10 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
                 r.sel = count_ptr(i, cur[i][from], from);
                 r.rows = pr.tables[from].n_rows;
               }
-              bp.bytes_moved += n_rows * (r.key64 ? 8 : 4);
+              c.bytes += n_rows * (r.key64 ? 8 : 4);
               pt.fs.f[pt.fs.n++] = r;
               missing_filter = missing_filter || final_of[i][p * pl.n_e + e] == kNoTask;
-              deps.push_back(final_of[i][p * pl.n_e + e]);
+              c.deps.push_back(final_of[i][p * pl.n_e + e]);
             }
             const bool last = c0 + kMaxProbe >= in.size();
             pt.n_rows = n_rows;
@@ -1189,20 +1285,21 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
             pt.count = last ? count_ptr(i, p + 1, v) : nullptr;
             pt.k = pr.params.k;
             pt.lg = lg;
-            bp.bytes_moved += 2 * n_words * 8;
-            // Every item first copies the filters into its LDS when they fit
-            // there: give it at least eight times their size in keys.
-            uint64_t filter_words = 0;
-            for (uint32_t j = 0; j < pt.fs.n; j++) filter_words += pt.fs.f[j].cap_words;
-            const uint64_t staged = filter_words <= lds_filter_words ? filter_words : 0;
-            const uint64_t probe_words = std::max<uint64_t>(words_per_item, staged * 4 * 8 / (64 * 4));
-            writer[i][v] = add_task(kBProbe, div_up32(n_words, probe_words), deps,
-                                    static_cast<uint32_t>(bp.probes.size()));
-            readers[i][v].clear();
-            bp.probes.push_back(pt);
+            // The only probe of a large table may join a shared scan.
+            if (in.size() <= static_cast<size_t>(kMaxProbe) && n_rows >= kSharedMinRows &&
+                (pr.params.flags & PT_FLAG_SHARED_SCAN))
+              cands.push_back(std::move(c));
+            else
+              emit_probe(c);
           }
           cur[i][v] = p + 1;
         }
+      }
+      emit_shared(cands);
+      for (uint32_t i = 0; i < n_problems; i++) {
+        const Plan &pl = bp.plans[i];
+        const pt_problem &pr = probs[i];
+        const uint32_t lg = log2_of(static_cast<int>(pr.params.block_bits));
         for (uint32_t v = 0; v < pl.n_t; v++) {
           if (lvl[p][i][v] != L) continue;
           std::vector<uint32_t> out;
@@ -1256,7 +1353,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
               // and built with atomics.
               uint32_t first_dep = writer[i][v];
               if (n_rows * b.fs.n > b.entries_cap || b.hist_cols >= kMaxBuckets)
-                first_dep = add_task(kBZero, div_up32(cap_words, kReduceWords), {writer[i][v]}, arg);
+                first_dep = add_task(kBZero, div_up32(cap_words, kZeroWords), {writer[i][v]}, arg);
               const uint32_t count = add_task(kBCount, tiles, {writer[i][v], first_dep}, arg);
               const uint32_t scan = add_task(kBScan, 1, {count}, arg);
               const uint32_t scatter = add_task(kBScatter, tiles, {scan}, arg);
@@ -1330,7 +1427,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
   off += table_bytes(bp.tasks.size(), sizeof(BTask)) + table_bytes(bp.item_task.size(), 4) +
          table_bytes(bp.phase_items.size(), 4) + table_bytes(bp.locals.size(), sizeof(BLocal)) +
          table_bytes(bp.probes.size(), sizeof(BProbe)) + table_bytes(bp.builds.size(), sizeof(BBuild)) +
-         table_bytes(bp.pairs.size(), sizeof(CopyPair));
+         table_bytes(bp.pairs.size(), sizeof(CopyPair)) + table_bytes(bp.shared.size(), sizeof(BShared));
   // PT_BATCH_TIMELINE=1 (profiling): room for every item's start and end.
   if (const char *tl = std::getenv("PT_BATCH_TIMELINE"); tl && std::strcmp(tl, "1") == 0) {
     bp.off_timeline = off;
@@ -1427,6 +1524,7 @@ pt_status pt_batch_prepare_async(uint32_t n_problems, const pt_problem *problems
   a.probes = reinterpret_cast<const BProbe *>(put(bp.probes.data(), bp.probes.size(), sizeof(BProbe)));
   a.builds = reinterpret_cast<const BBuild *>(put(bp.builds.data(), bp.builds.size(), sizeof(BBuild)));
   a.pairs = reinterpret_cast<const CopyPair *>(put(bp.pairs.data(), bp.pairs.size(), sizeof(CopyPair)));
+  a.shared = reinterpret_cast<const BShared *>(put(bp.shared.data(), bp.shared.size(), sizeof(BShared)));
   a.status = reinterpret_cast<uint32_t *>(ws);
   a.head = reinterpret_cast<uint32_t *>(ws + 4);
   a.phase_done = reinterpret_cast<uint32_t *>(ws + bp.off_done);

@@ -259,25 +259,6 @@ __device__ __forceinline__ void insert_bits(uint32_t *words, uint32_t nb, uint32
   }
 }
 
-// Sets the k bits of (h1, h2) with atomic OR alone (no read first); in LDS
-// or in global memory.
-template <int K>
-__device__ __forceinline__ void or_bits(uint32_t *words, uint32_t nb, uint32_t k, uint32_t h1, uint32_t h2,
-                                        uint32_t lg) {
-  uint32_t *blk = words + (static_cast<uint64_t>(block_of(h1, nb)) << (lg - 5));
-  uint32_t g1, g2;
-  probe_terms(h2, lg, g1, g2);
-  const uint32_t mask = (1u << lg) - 1;
-  uint32_t pos = g1;
-  const uint32_t kk = K > 0 ? static_cast<uint32_t>(K) : k;
-#pragma unroll
-  for (uint32_t i = 0; i < kk; i++) {
-    const uint32_t p = pos & mask;
-    atomicOr(blk + (p >> 5), 1u << (p & 31));
-    pos += g2;
-  }
-}
-
 // The same in a filter held in LDS (32-bit offsets).
 template <int K>
 __device__ __forceinline__ void insert_lds(uint32_t *filter, uint32_t nb, uint32_t k, uint32_t h1, uint32_t h2,
@@ -291,7 +272,10 @@ __device__ __forceinline__ void insert_lds(uint32_t *filter, uint32_t nb, uint32
 #pragma unroll
   for (uint32_t i = 0; i < kk; i++) {
     const uint32_t p = pos & mask;
-    atomicOr(blk + (p >> 5), 1u << (p & 31));
+    // A bit already set needs no atomic: repeated keys (a foreign key with
+    // few distinct values) would otherwise serialise on one LDS word.
+    const uint32_t bit = 1u << (p & 31);
+    if (!(blk[p >> 5] & bit)) atomicOr(blk + (p >> 5), bit);
     pos += g2;
   }
 }

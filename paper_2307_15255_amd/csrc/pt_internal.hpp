@@ -216,6 +216,7 @@ enum BatchKind : uint32_t {
   kBScatter,    // partitioned build: entries of a row tile
   kBFill,       // partitioned build: one filter tile per item
   kBCopy,       // final counts to the caller's arrays
+  kBShared,     // one scan of a table probed by several problems (shared scan)
 };
 
 struct BTask {
@@ -269,6 +270,25 @@ struct CopyPair {
   uint64_t *dst;
 };
 
+// A shared scan: the probes of several problems over one table of the same
+// rows (a resident table that every problem joins). Each row group's keys
+// are read once per column of the union (at most four columns) and hashed
+// once; every member's filters are then tested on them and every member
+// writes its own bitmap.
+constexpr int kMaxSharedMembers = 16;
+constexpr int kMaxSharedCols = 4;
+constexpr uint64_t kSharedMinRows = 1ull << 20;  // smaller tables are probed one problem at a time
+struct BShared {
+  uint64_t n_rows;
+  uint32_t n_members;
+  uint32_t n_cols;
+  uint32_t first_probe;  // members: probes[first_probe, first_probe + n_members)
+  uint32_t pad;
+  const void *cols[kMaxSharedCols];
+  uint32_t key64[kMaxSharedCols];
+  uint8_t col_of[kMaxSharedMembers][kMaxProbe];  // member m's filter j reads cols[col_of[m][j]]
+};
+
 struct BatchArgs {
   const BTask *tasks;
   const uint32_t *item_task;    // task of every item
@@ -277,6 +297,7 @@ struct BatchArgs {
   const BProbe *probes;
   const BBuild *builds;
   const CopyPair *pairs;
+  const BShared *shared;
   uint32_t *head;        // next item to take
   uint32_t *phase_done;  // finished items of every phase
   uint32_t *status;      // the batch's status word
@@ -289,7 +310,8 @@ struct BatchArgs {
 };
 
 constexpr int kBatchThreads = 1024;    // the batch kernel: sixteen waves per workgroup
-constexpr uint32_t kReduceWords = 16384;  // filter words one reduce or zero item of a batch covers
+constexpr uint32_t kReduceWords = 16384;   // filter words one reduce item of a batch covers
+constexpr uint32_t kZeroWords = 1u << 20;  // filter words one zero item covers (usually it has nothing to do)
 
 // k_batch*.hip: the persistent kernel for B = 512 and k = 3 or 2, or generic.
 // grid: workgroups (all resident); lds_bytes: dynamic LDS per workgroup.

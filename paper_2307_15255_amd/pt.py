@@ -160,6 +160,7 @@ def column(t: torch.Tensor) -> pt_column:
 
 
 PT_FLAG_NO_APPEND = 1
+PT_FLAG_SHARED_SCAN = 2
 
 
 def params(block_bits: int = 512, k: int = 3, bits_per_key: int = 10, flags: int = 0, *, hash_version: int = 1,

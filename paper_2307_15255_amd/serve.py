@@ -8,9 +8,13 @@ on the GPU and runs a request loop:
   admission   queries wait in arrival order; the head is admitted when the
               memory its filters, bitmaps and task tables need fits in what
               the in-flight batches leave of the budget (a ledger of bytes);
+              a query that could never fit is rejected on its own (out of
+              memory) and one that waits longer than its timeout is dropped,
+              without holding up the others;
   batching    every admitted query that is waiting when a launch slot is
-              free goes into one batch (pt_batch: one launch per step and
-              schedule level for all of its queries);
+              free goes into one batch (pt_batch: one persistent launch for
+              all of its queries, whose probes of the resident fact table
+              share one scan of its key columns);
   overlap     up to `slots` batches are in flight at once, each on its own
               stream: queries that arrive while others run are admitted and
               launched as soon as a slot and memory free up.
@@ -107,26 +111,29 @@ class Report:
     service: dict = field(default_factory=dict)    # qid -> seconds from launch to results ready (alone)
     finish: dict = field(default_factory=dict)     # qid -> seconds after start
     batches: list = field(default_factory=list)    # (launch time, [qid], bytes)
+    rejected: dict = field(default_factory=dict)   # qid -> reason (needs more memory than a batch may hold)
+    timed_out: dict = field(default_factory=dict)  # qid -> seconds waited when it was dropped
     peak_bytes: int = 0
     wall: float = 0.0
 
     def percentile(self, p: float) -> float:
+        """Latency percentile over the queries that completed."""
         return float(np.percentile(np.array(list(self.latency.values())), p))
 
 
 def serve(queries: list[Query], executor, budget_bytes: int, slots: int = 2, max_batch: int = 64,
-          batch_bytes: int | None = None, clock=time.perf_counter, idle=lambda: time.sleep(50e-6)) -> Report:
+          batch_bytes: int | None = None, timeout: float | None = None, clock=time.perf_counter,
+          idle=lambda: time.sleep(50e-6)) -> Report:
     """Runs the request loop over `queries` (sorted by arrival) on
     `executor` and reports every query's latency. budget_bytes bounds the
     memory of all batches in flight, batch_bytes (default: the budget) that
-    of one batch. A query needing more than either is rejected with
-    ValueError before the loop starts."""
+    of one batch. A query needing more than either is rejected when it
+    arrives (Report.rejected, the library's out-of-memory case); a query
+    still waiting `timeout` seconds after its arrival is dropped
+    (Report.timed_out). Neither stops the others."""
     rep = Report()
     cap = budget_bytes if batch_bytes is None else min(batch_bytes, budget_bytes)
     need = {q.qid: executor.mem_need(q) for q in queries}
-    for q in queries:
-        if need[q.qid] > cap:
-            raise ValueError(f"query {q.qid} needs {need[q.qid]} bytes, over the limit of {cap}")
     pending = collections.deque(sorted(queries, key=lambda q: q.arrival))
     waiting: collections.deque[Query] = collections.deque()
     inflight = []  # (handle, queries, bytes, slot)
@@ -136,7 +143,15 @@ def serve(queries: list[Query], executor, budget_bytes: int, slots: int = 2, max
     while pending or waiting or inflight:
         now = clock() - t0
         while pending and pending[0].arrival <= now:
-            waiting.append(pending.popleft())
+            q = pending.popleft()
+            if need[q.qid] > cap:
+                rep.rejected[q.qid] = f"out of memory: needs {need[q.qid]} bytes, a batch may hold {cap}"
+            else:
+                waiting.append(q)
+        if timeout is not None:
+            while waiting and now - waiting[0].arrival > timeout:
+                q = waiting.popleft()
+                rep.timed_out[q.qid] = now - q.arrival
         progressed = False
         for item in list(inflight):
             handle, qs, nbytes, slot = item
@@ -193,15 +208,19 @@ def one_at_a_time(queries: list[Query], executor, clock=time.perf_counter,
 
 
 class GpuExecutor:
-    """Runs batches with pt_batch on `slots` streams and single queries with
-    pt_transfer. Each slot owns a workspace arena of `arena_bytes` allocated
-    once (a batch's workspace is a prefix of its slot's arena; serve with
-    batch_bytes <= arena_bytes), and single queries share one more arena, so
-    the loop itself allocates nothing but the queries' bitmaps. Keeps every
-    query's bitmaps and counts when `keep`."""
+    """Runs batches on `slots` streams: a batch's small queries as one
+    pt_batch (one persistent launch), its large ones (at least large_rows
+    rows in their tables, which fill the GPU by themselves) as pt_transfer
+    calls one after the other on the same stream. Single queries run with
+    pt_transfer on a stream of their own. Each slot owns a workspace arena of
+    `arena_bytes` allocated once (the workspace of whatever runs on the slot
+    is a prefix of it; serve with batch_bytes <= arena_bytes), and single
+    queries share one more arena, so the loop itself allocates nothing but
+    the queries' bitmaps. Keeps every query's bitmaps and counts when
+    `keep`."""
 
     def __init__(self, resident: ResidentStar, params=None, slots: int = 2, keep: bool = False,
-                 arena_bytes: int = 1 << 30, single_arena_bytes: int = 0):
+                 arena_bytes: int = 1 << 30, single_arena_bytes: int = 0, large_rows: int = 8_000_000):
         import torch
         from . import pt
         self.torch, self.pt = torch, pt
@@ -213,6 +232,7 @@ class GpuExecutor:
         self.single_arena = (torch.empty(single_arena_bytes, dtype=torch.uint8, device="cuda")
                              if single_arena_bytes else None)
         self.keep = keep
+        self.large_rows = large_rows
         self.results: dict[int, tuple[list, object]] = {}
         self._dp_cache: dict[int, object] = {}
 
@@ -230,20 +250,38 @@ class GpuExecutor:
 
     def mem_need(self, q: Query) -> int:
         dp = self.device_problem(q)
-        ws = self.pt.pt_batch_workspace_size([dp], [self.params])
+        ws = max(self.pt.pt_batch_workspace_size([dp], [self.params]), self.single_need(q))
         bitmaps = sum(8 * self.pt.bitmap_words(n) for n in dp.n_rows) + 8 * dp.n_tables
         return ws + bitmaps
 
+    def is_large(self, q: Query) -> bool:
+        """A query whose tables hold at least large_rows rows: its own
+        launches already fill the GPU, so it runs as its own transfer (the
+        persistent batch kernel pays off for many small problems)."""
+        return sum(self.device_problem(q).n_rows) >= self.large_rows
+
     def launch(self, qs: list[Query], slot: int):
+        """One batch on the slot's stream: its small queries as one pt_batch,
+        then its large queries one transfer after the other (the arena is
+        their shared workspace: they run in stream order)."""
         torch = self.torch
         s = self.streams[slot]
-        dps = [self.device_problem(q) for q in qs]
+        small = [q for q in qs if not self.is_large(q)]
+        large = [q for q in qs if self.is_large(q)]
+        parts = []
         with torch.cuda.stream(s):
-            bt = self.pt.Batch(dps, [self.params] * len(dps), stream=s, ws=self.arenas[slot])
-            bt.run(stream=s, eager=True)
+            if small:
+                dps = [self.device_problem(q) for q in small]
+                bt = self.pt.Batch(dps, [self.params] * len(dps), stream=s, ws=self.arenas[slot])
+                bt.run(stream=s, eager=True)
+                parts.append(("batch", bt, small))
+            for q in large:
+                tr = self.pt.Transfer(self.device_problem(q), self.params, ws=self.arenas[slot])
+                tr.run(stream=s)
+                parts.append(("single", tr, [q]))
             ev = torch.cuda.Event()
             ev.record(s)
-        return ("batch", bt, ev, qs, s)
+        return (parts, ev, qs, s)
 
     def launch_single(self, q: Query):
         torch = self.torch
@@ -253,22 +291,23 @@ class GpuExecutor:
             tr.run(stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
-        return ("single", tr, ev, [q], s)
+        return ([("single", tr, [q])], ev, [q], s)
 
     def done(self, h) -> bool:
-        return h[2].query()
+        return h[1].query()
 
     def finish(self, h) -> None:
-        kind, obj, _, qs, stream = h
-        if self.keep:
-            # Copied on the stream the results were made on: their blocks go
-            # back to that stream's pool when `obj` is dropped, so the next
-            # launch there cannot reuse them before the copies have run.
-            with self.torch.cuda.stream(stream):
-                if kind == "batch":
-                    for i, q in enumerate(qs):
-                        self.results[q.qid] = ([b.clone() for b in obj.bitmaps[i]], obj.counts[i].clone())
-                else:
-                    self.results[qs[0].qid] = ([b.clone() for b in obj.bitmaps], obj.counts.clone())
-        if kind == "batch":
-            obj.close()
+        parts, _, _, stream = h
+        for kind, obj, qs in parts:
+            if self.keep:
+                # Copied on the stream the results were made on: their blocks
+                # go back to that stream's pool when `obj` is dropped, so the
+                # next launch there cannot reuse them before the copies ran.
+                with self.torch.cuda.stream(stream):
+                    if kind == "batch":
+                        for i, q in enumerate(qs):
+                            self.results[q.qid] = ([b.clone() for b in obj.bitmaps[i]], obj.counts[i].clone())
+                    else:
+                        self.results[qs[0].qid] = ([b.clone() for b in obj.bitmaps], obj.counts.clone())
+            if kind == "batch":
+                obj.close()

@@ -2,6 +2,7 @@
 ends with the bitmaps and counts the oracle computes for it alone, whether
 the batch runs eagerly or as its captured graph, replayed several times with
 other GPU work in between."""
+import os
 import time
 
 import numpy as np
@@ -25,11 +26,11 @@ def pt():
     return ptmod
 
 
-def check_against_oracle(pt, bt, probs, params, which=None):
+def check_against_oracle(pt, bt, probs, params, which=None, threads=1):
     counts = [c.cpu().numpy() for c in bt.counts]
     for i in (range(len(probs)) if which is None else which):
         p = params[i]
-        ref = oracle.transfer(probs[i], p.block_bits, p.k, p.bits_per_key)
+        ref = oracle.transfer(probs[i], p.block_bits, p.k, p.bits_per_key, threads=threads)
         for t in range(probs[i].n_tables):
             assert_bitmaps_equal(bt.bitmap(i, t), ref.bitmaps[t], f"problem {i} ({probs[i].label}) table {t}")
             assert counts[i][t] == ref.counts[t], (i, t)
@@ -98,10 +99,11 @@ def test_batch_equals_single_transfers(pt):
 
 
 @pytest.mark.timeout(400)
-def test_full_batch_sampled(pt):
+def test_full_batch(pt):
     """256 problems with tables of 10 k to 5 M rows (677 M rows in all), as
-    one graph launch: eight problems checked against the oracle, every
-    problem's counts against pt_transfer on its own."""
+    one persistent launch: every problem's bitmaps and counts against the
+    oracle (its row split over the host's cores, bit-exact with one
+    thread), and every problem's counts against pt_transfer on its own."""
     t0 = time.time()
     probs = W.batch(seed=1)
     say("full batch generated", round(time.time() - t0, 1), "s")
@@ -110,9 +112,9 @@ def test_full_batch_sampled(pt):
     bt.run()
     torch.cuda.synchronize()
     say("full batch ran", round(time.time() - t0, 1), "s")
-    sample = [0, 1, 2, 3, 101, 130, 254, 255]
-    check_against_oracle(pt, bt, probs, bt.params, which=sample)
-    say("full batch oracle sample ok", round(time.time() - t0, 1), "s")
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    check_against_oracle(pt, bt, probs, bt.params, threads=threads)
+    say("full batch oracle ok", round(time.time() - t0, 1), "s")
     for i, dp in enumerate(dps):
         tr = pt.Transfer(dp)
         tr.run()
@@ -120,3 +122,42 @@ def test_full_batch_sampled(pt):
         assert torch.equal(bt.counts[i], tr.counts), i
         del tr
     say("full batch counts ok", round(time.time() - t0, 1), "s")
+
+
+@pytest.mark.parametrize("sel_hi", [0.5, 0.02])
+def test_shared_scans(pt, sel_hi):
+    """Forty queries joining one resident 2 M-row fact table through int32
+    and int64 key columns, in one batch: their fact probes run as shared
+    scans (groups of at most sixteen problems and four key columns; the
+    timeline shows shared items) and every problem ends with the oracle's
+    bits, as it does without them. With predicates keeping
+    up to 50 % some groups' filters exceed LDS (members probed one by one);
+    with at most 2 % every group's filters fit (one pass for the group)."""
+    from paper_2307_15255_amd import serve as S
+    res = S.ResidentStar(seed=6, n_fact=2_000_000, dims=(300_000, 20_000, 1_000, 25))
+    rng = np.random.default_rng(3)
+    probs, dps = [], []
+    for i in range(40):
+        prob, dev = res.problem(S.random_query(rng, i, sel_hi=sel_hi))
+        probs.append(prob)
+        dps.append(pt.DeviceProblem(prob, columns=dev))
+    os.environ["PT_BATCH_TIMELINE"] = "1"
+    try:
+        bt = pt.Batch(dps, [pt.params(flags=pt.PT_FLAG_SHARED_SCAN)] * len(dps))
+    finally:
+        del os.environ["PT_BATCH_TIMELINE"]
+    say("shared batch")
+    bt.run(eager=True)
+    torch.cuda.synchronize()
+    bt.check_status()
+    tl, _ = bt.timeline()
+    shared_kind = 10
+    assert int((tl[:, 2] == shared_kind).sum()) > 0
+    check_against_oracle(pt, bt, probs, bt.params)
+    solo = pt.Batch(dps, [pt.params()] * len(dps))
+    solo.run()
+    torch.cuda.synchronize()
+    for i in range(len(dps)):
+        for t in range(dps[i].n_tables):
+            assert torch.equal(bt.bitmaps[i][t], solo.bitmaps[i][t]), (i, t)
+        assert torch.equal(bt.counts[i], solo.counts[i]), i

@@ -89,10 +89,36 @@ def test_batches_overlap_and_beat_one_at_a_time():
     assert alone.percentile(50) >= 3e-3 - 1e-9  # every lone query takes fixed + per-query time
 
 
-def test_oversized_query_is_rejected():
+def test_oversized_query_is_rejected_alone():
+    """A query that can never fit the memory limit is rejected by itself;
+    the others are served."""
     clock = Clock()
-    with pytest.raises(ValueError):
-        S.serve(make_queries(5, 100), HostExecutor(clock), budget_bytes=50, clock=clock, idle=clock.idle)
+    qs = make_queries(40, 500)
+    ex = HostExecutor(clock)
+    limit = 100 + 50 * 3  # queries with four dimensions need more
+    rep = S.serve(qs, ex, budget_bytes=limit, clock=clock, idle=clock.idle)
+    big = {q.qid for q in qs if ex.mem_need(q) > limit}
+    assert big and set(rep.rejected) == big
+    assert all("out of memory" in r for r in rep.rejected.values())
+    assert set(rep.latency) == {q.qid for q in qs} - big
+    assert rep.peak_bytes <= limit
+
+
+def test_queries_time_out_while_waiting():
+    """Under an overload with one slot, queries still waiting after the
+    timeout are dropped; every query is either served or dropped, and no
+    served query waited past the timeout before its launch."""
+    clock = Clock()
+    qs = make_queries(200, qps=5000)
+    rep = S.serve(qs, HostExecutor(clock, fixed=5e-3), 10_000, slots=1, max_batch=4, timeout=0.02, clock=clock,
+                  idle=clock.idle)
+    assert rep.timed_out and rep.latency
+    assert set(rep.timed_out) | set(rep.latency) == {q.qid for q in qs}
+    assert not set(rep.timed_out) & set(rep.latency)
+    assert all(w > 0.02 for w in rep.timed_out.values())
+    arrival = {q.qid: q.arrival for q in qs}
+    for t, ids, _ in rep.batches:
+        assert all(t - arrival[i] <= 0.02 + 1e-9 for i in ids)
 
 
 def test_queries_are_valid_problems(oracle_lib):
