@@ -191,6 +191,10 @@ __device__ __forceinline__ void scan_body(const BBuild &b, uint32_t lg, uint64_t
 // rows' keys of every column once, and tests each of those members' filters
 // on them (most selective first, only rows still alive). The other members
 // are then probed one after the other.
+// Bitmap words per wave and group in the batch's probes: fewer than the
+// single probe's, so the whole persistent kernel fits its registers.
+constexpr int kBatchProbeWords = 8;
+
 static_assert(kMaxSharedMembers * 4 <= kWave, "a shared scan loads every member's bitmap words in one wave load");
 
 template <int B, int K>
@@ -349,8 +353,9 @@ __device__ __forceinline__ void shared_probe_body(const BatchArgs &a, const BSha
     if ((in >> m) & 1) continue;
     __syncthreads();
     const BProbe &p = mem[m];
-    probe_body<B, K, false>(p.fs, p.k, p.lg, p.n_rows, p.bitmap, reinterpret_cast<unsigned long long *>(p.count),
-                            a.lds_filter_words, 0, 0, a.status, none, vg);
+    probe_body<B, K, false, kBatchProbeWords>(p.fs, p.k, p.lg, p.n_rows, p.bitmap,
+                                              reinterpret_cast<unsigned long long *>(p.count), a.lds_filter_words, 0,
+                                              0, a.status, none, vg);
   }
 }
 
@@ -366,8 +371,9 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const BTask &task, 
     case kBProbe: {
       const BProbe &p = a.probes[task.arg];
       const AppendSet none{};
-      probe_body<B, K, false>(p.fs, p.k, p.lg, p.n_rows, p.bitmap, reinterpret_cast<unsigned long long *>(p.count),
-                              a.lds_filter_words, 0, 0, a.status, none, vg);
+      probe_body<B, K, false, kBatchProbeWords>(p.fs, p.k, p.lg, p.n_rows, p.bitmap,
+                                                reinterpret_cast<unsigned long long *>(p.count), a.lds_filter_words,
+                                                0, 0, a.status, none, vg);
       break;
     }
     case kBBuild: {

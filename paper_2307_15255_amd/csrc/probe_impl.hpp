@@ -75,14 +75,14 @@ __device__ __forceinline__ void gather_key(const void *col, uint32_t key64, uint
 
 // The group's first-column keys: lane l gets rows base + 64 u + l (clamped to
 // the last row, `last` rows past base), u < kGroupWords.
-template <bool KEY64>
+template <bool KEY64, int G>
 __device__ __forceinline__ void load_group(const void *col, uint64_t base, uint32_t last,
-                                           uint32_t (&lo)[kGroupWords], uint32_t (&hi)[KEY64 ? kGroupWords : 1]) {
+                                           uint32_t (&lo)[G], uint32_t (&hi)[KEY64 ? G : 1]) {
   const uint32_t lane = lane_id();
   if constexpr (KEY64) {
     const uint64_t *p = static_cast<const uint64_t *>(col) + base;
 #pragma unroll
-    for (int u = 0; u < kGroupWords; u++) {
+    for (int u = 0; u < G; u++) {
       const uint64_t x = p[min(static_cast<uint32_t>(u * 64) + lane, last)];
       lo[u] = static_cast<uint32_t>(x);
       hi[u] = static_cast<uint32_t>(x >> 32);
@@ -90,17 +90,18 @@ __device__ __forceinline__ void load_group(const void *col, uint64_t base, uint3
   } else {
     const uint32_t *p = static_cast<const uint32_t *>(col) + base;
 #pragma unroll
-    for (int u = 0; u < kGroupWords; u++) lo[u] = p[min(static_cast<uint32_t>(u * 64) + lane, last)];
+    for (int u = 0; u < G; u++) lo[u] = p[min(static_cast<uint32_t>(u * 64) + lane, last)];
   }
 }
 
-template <int K, bool KEY64, bool STAGED, bool APPEND>
+template <int K, bool KEY64, bool STAGED, bool APPEND, int G>
 __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const uint32_t (&lds_off)[kMaxProbe],
                                               uint32_t n_f, uint32_t k, uint32_t lg, uint64_t n_rows,
                                               uint64_t *bitmap, uint32_t input_all, const uint32_t *lds_filters,
                                               uint32_t *slice, const AppendSet &app,
                                               const int (&app_slot)[kMaxAppend], const VGrid &vg) {
-  constexpr int U = kGroupWords;
+  static_assert(G % 4 == 0 && G <= kGroupWords, "group of 4 to kGroupWords words");
+  constexpr int U = G;
   uint32_t *q_tag = slice;                                                     // [kWave]
   uint32_t *q_lo = slice + kWave;                                              // [kWave]
   uint32_t *q_hi = slice + 2 * kWave;                                          // [kWave]
@@ -120,7 +121,7 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const
   uint64_t nbits = 0;
   if (w0 < n_words) {
     const uint64_t left = n_rows - 1 - w0 * 64;
-    load_group<KEY64>(col0, w0 * 64, left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu, nlo, nhi);
+    load_group<KEY64, U>(col0, w0 * 64, left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu, nlo, nhi);
     if (!input_all) nbits = bitmap[min(w0 + (lane < U ? lane : 0), n_words - 1)];
   }
   for (; w0 < n_words; w0 += stride) {
@@ -134,7 +135,7 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const
     const uint64_t w_next = w0 + stride;
     if (w_next < n_words) {
       const uint64_t left = n_rows - 1 - w_next * 64;
-      load_group<KEY64>(col0, w_next * 64, left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu, nlo,
+      load_group<KEY64, U>(col0, w_next * 64, left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu, nlo,
                         nhi);
       if (!input_all) nbits = bitmap[min(w_next + (lane < U ? lane : 0), n_words - 1)];
     }
@@ -324,7 +325,7 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const
   return cnt;
 }
 
-template <int B, int K, bool APPEND>
+template <int B, int K, bool APPEND, int G = kGroupWords>
 __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint32_t lg_rt, uint64_t n_rows,
                                            uint64_t *__restrict__ bitmap, unsigned long long *count,
                                            uint32_t lds_filter_words, uint32_t input_all, uint32_t keep_order,
@@ -433,17 +434,17 @@ __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint
   if (!staged) off[0] = 0;  // slot 0 takes the global path by template
   if (sl[0].key64) {
     if (staged)
-      cnt = probe_loop<K, true, true, APPEND>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
+      cnt = probe_loop<K, true, true, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
                                               app_slot, vg);
     else
-      cnt = probe_loop<K, true, false, APPEND>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
+      cnt = probe_loop<K, true, false, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
                                                app_slot, vg);
   } else {
     if (staged)
-      cnt = probe_loop<K, false, true, APPEND>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
+      cnt = probe_loop<K, false, true, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
                                                app_slot, vg);
     else
-      cnt = probe_loop<K, false, false, APPEND>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
+      cnt = probe_loop<K, false, false, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
                                                 app_slot, vg);
   }
   block_count_add(cnt, &s_cnt, count);
