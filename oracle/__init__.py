@@ -40,7 +40,8 @@ class _Table(C.Structure):
 
 
 class _Edge(C.Structure):
-    _fields_ = [("u", C.c_uint32), ("u_col", C.c_uint32), ("v", C.c_uint32), ("v_col", C.c_uint32)]
+    _fields_ = [("u", C.c_uint32), ("u_col", C.c_uint32), ("v", C.c_uint32), ("v_col", C.c_uint32),
+                ("flags", C.c_uint32)]
 
 
 class _Pred(C.Structure):
@@ -260,8 +261,10 @@ def _problem(problem, keep: list) -> _Problem:
         cc = (_Column * max(1, len(cols)))(*[_column(a) for a in cols])
         keep.append(cc)
         tables[t] = _Table(problem.n_rows(t), len(cols), 0, cc)
+    flags = problem.edge_flags if problem.edge_flags is not None else [0] * n_e
     edges = (_Edge * max(1, n_e))(*[
-        _Edge(u, problem.col_index(u, uc), v, problem.col_index(v, vc)) for u, uc, v, vc in problem.edges])
+        _Edge(u, problem.col_index(u, uc), v, problem.col_index(v, vc), f)
+        for (u, uc, v, vc), f in zip(problem.edges, flags)])
     preds = (_Pred * max(1, len(problem.preds)))(*[
         _Pred(t, problem.col_index(t, c), OPS[op], 0, lo, hi) for t, c, op, lo, hi in problem.preds])
     orient = None

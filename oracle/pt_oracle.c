@@ -343,6 +343,18 @@ static void dump_filter(const ptor_dump *d, const ptor_problem *p, uint32_t pass
   }
 }
 
+/* Whether a filter may cross edge e from table `from` to table `to`
+ * (Sec. 3.4: an outer join blocks the direction towards its preserved side,
+ * a full outer join both). */
+static int edge_carries(const ptor_edge *ed, uint32_t from, uint32_t to) {
+  switch (ed->flags) {
+    case PTOR_INNER: return 1;
+    case PTOR_LEFT_OUTER: return from == ed->u && to == ed->v;
+    case PTOR_RIGHT_OUTER: return from == ed->v && to == ed->u;
+    default: return 0;
+  }
+}
+
 /* One pass over the predicate transfer graph. A table first collects every
  * incoming filter and probes it on its own join-key column (rows already
  * removed stay removed), then builds one outgoing filter per outgoing edge
@@ -358,7 +370,7 @@ static int run_pass(const ptor_problem *p, const ptor_params *pa, uint32_t pass,
     const ptor_table *t = &p->tables[v];
     for (uint32_t j = 0; j < m; j++) {
       uint32_t e = reverse_probe ? m - 1 - j : j;
-      if (dst[e] != v) continue;
+      if (dst[e] != v || !edge_carries(&p->edges[e], src[e], dst[e])) continue;
       const ptor_column *col = edge_column(p, e, v);
       const int64_t n_words = (int64_t)bitmap_words(t->n_rows);
       uint64_t *bm = bitmaps[v];
@@ -371,7 +383,7 @@ static int run_pass(const ptor_problem *p, const ptor_params *pa, uint32_t pass,
       }
     }
     for (uint32_t e = 0; e < m; e++) {
-      if (src[e] != v) continue;
+      if (src[e] != v || !edge_carries(&p->edges[e], src[e], dst[e])) continue;
       int rc = filter_build(&filters[e], pa, edge_column(p, e, v), t->n_rows, bitmaps[v]);
       if (rc != PTOR_OK) return rc;
       dump_filter(dump, p, pass, e, &filters[e], pa, v);
@@ -384,6 +396,7 @@ static int problem_valid(const ptor_problem *p) {
   for (uint32_t e = 0; e < p->n_edges; e++) {
     const ptor_edge *ed = &p->edges[e];
     if (ed->u >= p->n_tables || ed->v >= p->n_tables || ed->u == ed->v) return 0;
+    if (ed->flags > PTOR_FULL_OUTER) return 0;
     if (ed->u_col >= p->tables[ed->u].n_cols || ed->v_col >= p->tables[ed->v].n_cols) return 0;
     if (p->orient && p->orient[e] != 1 && p->orient[e] != -1) return 0;
   }

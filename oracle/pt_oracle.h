@@ -77,9 +77,16 @@ typedef struct {
   const ptor_column *cols;
 } ptor_table;
 
-/* One equi-join u.u_col = v.v_col (an undirected join-graph edge). */
+/* One equi-join u.u_col = v.v_col (an undirected join-graph edge) and its
+ * join type (Sec. 3.4): an outer join keeps every row of its preserved
+ * side, so a filter may cross the edge only towards the other side. */
+#define PTOR_INNER 0
+#define PTOR_LEFT_OUTER 1  /* u LEFT JOIN v: filters may go u -> v only */
+#define PTOR_RIGHT_OUTER 2 /* u RIGHT JOIN v: v -> u only */
+#define PTOR_FULL_OUTER 3  /* no filter crosses the edge */
 typedef struct {
   uint32_t u, u_col, v, v_col;
+  uint32_t flags;
 } ptor_edge;
 
 typedef struct {

@@ -36,6 +36,8 @@ class Problem:
     preds: list[tuple[int, str, str, int, int]] = field(default_factory=list)
     orient: list[int] | None = None
     label: str = ""
+    # per edge: 0 inner join, 1 u LEFT JOIN v, 2 u RIGHT JOIN v, 3 full outer
+    edge_flags: list[int] | None = None
 
     @property
     def n_tables(self) -> int:
@@ -181,13 +183,14 @@ def snowflake(seed: int = 1, scale: float = 1.0, zipf_s: float = 1.1) -> Problem
 
 def tiny_random(rng: np.random.Generator, shape: str = "tree", max_tables: int = 6,
                 max_rows: int = 40, domain: int = 8, pred_prob: float = 0.5,
-                allow_empty: bool = True) -> Problem:
+                allow_empty: bool = True, outer: float = 0.0) -> Problem:
     """A small random join problem for brute-force checks.
 
     shape: "chain", "star", "tree" (random tree), "cycle" (a tree plus one
     extra edge closing a cycle), "parallel" (a tree plus one edge that
     duplicates a pair on other columns), "forest" (two components and
-    possibly an isolated table).
+    possibly an isolated table). outer > 0 makes each edge an outer join
+    (left, right or full, uniformly) with that probability.
     """
     n_t = int(rng.integers(2, max_tables + 1))
     if shape == "cycle":
@@ -243,7 +246,11 @@ def tiny_random(rng: np.random.Generator, shape: str = "tree", max_tables: int =
             lo = int(rng.integers(0, 100))
             hi = int(rng.integers(lo, 101))
             preds.append((t, "x", op, lo, hi))
-    return Problem([f"T{t}" for t in range(n_t)], columns, edges, preds, label=f"tiny-{shape}")
+    flags = None
+    if outer > 0:
+        # each edge an outer join with probability `outer`: left, right or full
+        flags = [int(rng.integers(1, 4)) if rng.random() < outer else 0 for _ in edges]
+    return Problem([f"T{t}" for t in range(n_t)], columns, edges, preds, label=f"tiny-{shape}", edge_flags=flags)
 
 
 _ZIPF_CHUNK = 1 << 22

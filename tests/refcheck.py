@@ -314,3 +314,64 @@ def spec_slots(key: int, nb: int, block_bits: int, k: int) -> tuple[int, list[in
     g1 = h2 >> (32 - b)
     g2 = ((h2 >> (32 - 2 * b)) & (block_bits - 1)) | 1
     return blk, [(g1 + i * g2) % block_bits for i in range(k)]
+
+
+# ------------------------------------------------------- outer-join trees
+
+_HOW = {0: "inner", 3: "outer"}
+
+
+def outer_tree_result(problem, masks: list[np.ndarray], root: int) -> list[tuple]:
+    """The query of a join tree with inner and outer edges (Sec. 3.4),
+    evaluated bottom-up from `root`: each table joins the result of every
+    child subtree with its edge's join type (u LEFT JOIN v keeps every row of
+    u, RIGHT every row of v, FULL both). Rows are restricted to `masks`.
+    Returns the sorted row-id tuples (one column per table, ascending table
+    order; -1 where a row is null-extended). Null join keys never match."""
+    adj = defaultdict(list)
+    for e, (u, uc, v, vc) in enumerate(problem.edges):
+        adj[u].append((e, v))
+        adj[v].append((e, u))
+    flags = problem.edge_flags or [0] * len(problem.edges)
+    sentinel = [-(1 << 52)]  # below every key of the tests, exact in float64
+
+    def frame(t):
+        rows = np.nonzero(masks[t])[0]
+        df = pd.DataFrame({f"r{t}": rows.astype(np.float64)})
+        for name, col in problem.columns[t].items():
+            df[f"t{t}.{name}"] = col.astype(np.int64)[rows].astype(np.float64)
+        return df
+
+    def fill_null_keys(df, col):
+        # a null key must match nothing: give each null its own value
+        df = df.copy()
+        miss = df[col].isna().to_numpy()
+        n = int(miss.sum())
+        df.loc[miss, col] = np.arange(sentinel[0], sentinel[0] + n, dtype=np.float64)
+        sentinel[0] += n
+        return df
+
+    def build(t, parent_edge):
+        df = frame(t)
+        for e, c in adj[t]:
+            if e == parent_edge:
+                continue
+            sub = build(c, e)
+            u, uc, v, vc = problem.edges[e]
+            mine, theirs = (uc, vc) if u == t else (vc, uc)
+            f = flags[e]
+            if f in (1, 2):  # the preserved side: u for LEFT, v for RIGHT
+                preserved = u if f == 1 else v
+                how = "left" if preserved == t else "right"
+            else:
+                how = _HOW[f]
+            lk, rk = f"t{t}.{mine}", f"t{c}.{theirs}"
+            df = fill_null_keys(df, lk)
+            sub = fill_null_keys(sub, rk)
+            df = df.merge(sub, left_on=lk, right_on=rk, how=how)
+        return df
+
+    df = build(root, -1)
+    cols = sorted([c for c in df.columns if c.startswith("r")], key=lambda c: int(c[1:]))
+    out = df[cols].fillna(-1).astype(np.int64)
+    return sorted(map(tuple, out.itertuples(index=False, name=None)))

@@ -37,6 +37,10 @@ MUTANTS = {
     "build_before_probe": None,  # handled below: outgoing filters built before incoming probes
     "no_backward_pass": ("if (pa->n_passes == 2) {", "if (pa->n_passes == 3) {"),
     "local_preds_ignored": ("if (pr->table == t && !predicate_holds", "if (pr->table == t + 1 && !predicate_holds"),
+    "outer_left_reversed": ("case PTOR_LEFT_OUTER: return from == ed->u && to == ed->v;",
+                            "case PTOR_LEFT_OUTER: return from == ed->v && to == ed->u;"),
+    "outer_full_not_blocked": ("return from == ed->v && to == ed->u;\n    default: return 0;",
+                               "return from == ed->v && to == ed->u;\n    default: return 1;"),
     "join_skips_closing_edge": ("if ((uint32_t)slot[b_t] >= i) continue;",
                                 "if ((uint32_t)slot[b_t] >= i || b_t != u) continue;"),
     "join_upper_bound": ("if (index[mid].key < key) lo = mid + 1;", "if (index[mid].key <= key) lo = mid + 1;"),
@@ -49,7 +53,7 @@ MUTANTS = {
 def _mutate(text: str, name: str) -> str:
     if name == "build_before_probe":
         a = text.index("    for (uint32_t j = 0; j < m; j++) {\n      uint32_t e = reverse_probe")
-        b = text.index("    for (uint32_t e = 0; e < m; e++) {\n      if (src[e] != v) continue;")
+        b = text.index("    for (uint32_t e = 0; e < m; e++) {\n      if (src[e] != v || !edge_carries")
         c = text.index("  return PTOR_OK;\n}\n\nstatic int problem_valid")
         probe, build = text[a:b], text[b:c - len("  }\n")]
         return text[:a] + build + probe + text[c - len("  }\n"):]
