@@ -118,14 +118,23 @@ typedef struct pt_table {
   const pt_column *cols;
 } pt_table;
 
-/* One inner equi-join tables[u].cols[u_col] = tables[v].cols[v_col]
- * (Sec. 3.1). A composite key is several edges between the same tables.
- * flags: 0 (an inner join); other values are reserved for outer joins
- * (Sec. 3.4) and rejected with PT_EUNSUPPORTED. */
+/* One equi-join tables[u].cols[u_col] = tables[v].cols[v_col] (Sec. 3.1).
+ * A composite key is several edges between the same tables. flags is the
+ * join type (Sec. 3.4): PT_EDGE_INNER, or an outer join, which keeps every
+ * row of its preserved side, so no filter may reduce that side through this
+ * edge: tables[u] LEFT JOIN tables[v] transfers only u -> v (in whichever
+ * pass the edge runs that way), RIGHT only v -> u, FULL not at all. Other
+ * values are rejected with PT_EUNSUPPORTED. pt_transfer handles every type;
+ * pt_join only inner joins. */
 typedef struct pt_edge {
   uint32_t u, u_col, v, v_col;
   uint32_t flags;
 } pt_edge;
+
+#define PT_EDGE_INNER 0u
+#define PT_EDGE_LEFT_OUTER 1u
+#define PT_EDGE_RIGHT_OUTER 2u
+#define PT_EDGE_FULL_OUTER 3u
 
 /* The join graph. `orient` is NULL for the paper's rule (Sec. 3.2: each edge
  * points from the table with fewer rows to the one with more; equal sizes
@@ -355,7 +364,8 @@ pt_status pt_join(const pt_graph *graph, const pt_table *tables, uint32_t root,
                   uint64_t *d_n_out, void *d_ws, size_t ws_bytes, pt_stream stream);
 
 /* Where pt_transfer left the filter that `edge` carried in `pass` (1 forward,
- * 2 backward) inside d_ws, and which table built it (*builder). */
+ * 2 backward) inside d_ws, and which table built it (*builder); PT_EINVAL
+ * when an outer join kept the edge from carrying one in that pass. */
 pt_status pt_transfer_filter(const pt_graph *graph, const pt_table *tables,
                              const pt_params *params, void *d_ws, uint32_t pass, uint32_t edge,
                              pt_bloom *out, uint32_t *builder);

@@ -212,6 +212,13 @@ uint64_t key_bytes(const pt_column &c) { return c.dtype == PT_I64 ? 8 : 4; }
 struct Plan {
   uint32_t n_t = 0, n_e = 0;
   std::vector<uint32_t> src, dst;  // forward orientation of every edge
+  // [pass * n_e + e]: edge e carries a filter in that pass (an outer join
+  // blocks one direction or both, Sec. 3.4)
+  std::vector<uint8_t> active;
+  bool sends(uint32_t p, uint32_t e, uint32_t v) const { return active[p * n_e + e] && (p == 0 ? src : dst)[e] == v; }
+  bool receives(uint32_t p, uint32_t e, uint32_t v) const {
+    return active[p * n_e + e] && (p == 0 ? dst : src)[e] == v;
+  }
   std::vector<uint32_t> order;     // forward topological order
   uint64_t off_counts = 0;         // 3 * n_t uint64: local, forward, backward
   uint64_t off_nb = 0;             // 2 * n_e uint64: forward, backward filters
@@ -261,11 +268,10 @@ AppendPlan append_plan(const Plan &pl, const pt_graph *g, const pt_table *tables
                        uint32_t p, uint32_t v) {
   AppendPlan ap;
   if ((params.flags & PT_FLAG_NO_APPEND) || tables[v].n_rows == 0) return ap;
-  auto from = [&](uint32_t q, uint32_t e) { return q == 0 ? pl.src[e] : pl.dst[e]; };
   bool in = false, out = false;
   for (uint32_t e = 0; e < pl.n_e; e++) {
-    in = in || from(1 - p, e) == v;  // the edge ends at v in pass p
-    out = out || from(p, e) == v;
+    in = in || pl.receives(p, e, v);
+    out = out || pl.sends(p, e, v);
   }
   if (!in) return ap;
   uint32_t q;
@@ -276,7 +282,7 @@ AppendPlan append_plan(const Plan &pl, const pt_graph *g, const pt_table *tables
   else
     return ap;
   for (uint32_t e = 0; e < pl.n_e; e++) {
-    if (from(q, e) != v) continue;
+    if (!pl.sends(q, e, v)) continue;
     const uint32_t c = col_at(g, e, v);
     if (std::find(ap.cols.begin(), ap.cols.end(), c) == ap.cols.end()) ap.cols.push_back(c);
   }
@@ -314,11 +320,13 @@ pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *
   pl.n_e = g->n_edges;
   pl.src.assign(pl.n_e, 0);
   pl.dst.assign(pl.n_e, 0);
+  pl.active.assign(2ull * pl.n_e, 1);
   for (uint32_t e = 0; e < pl.n_e; e++) {
     const pt_edge &ed = g->edges[e];
     if (ed.u >= pl.n_t || ed.v >= pl.n_t) return fail(PT_EINVAL, "edge %u: table out of range", e);
     if (ed.u == ed.v) return fail(PT_EINVAL, "edge %u joins table %u with itself", e, ed.u);
-    if (ed.flags != 0) return fail(PT_EUNSUPPORTED, "edge %u: flags 0x%x (only inner joins, flags = 0)", e, ed.flags);
+    if (ed.flags > PT_EDGE_FULL_OUTER)
+      return fail(PT_EUNSUPPORTED, "edge %u: flags 0x%x (inner, left, right or full outer join)", e, ed.flags);
     if (ed.u_col >= tables[ed.u].n_cols || ed.v_col >= tables[ed.v].n_cols)
       return fail(PT_EINVAL, "edge %u: column out of range", e);
     bool u_first;
@@ -333,6 +341,18 @@ pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *
     }
     pl.src[e] = u_first ? ed.u : ed.v;
     pl.dst[e] = u_first ? ed.v : ed.u;
+    // Sec. 3.4: a left outer join keeps every row of its left table, so
+    // only the left table's filter may reduce the right one (u -> v); a
+    // right outer join the reverse; a full outer join blocks both. The edge
+    // then carries a filter only in the pass where it runs that way.
+    for (uint32_t p = 0; p < 2; p++) {
+      const uint32_t from = p == 0 ? pl.src[e] : pl.dst[e];
+      bool ok = true;
+      if (ed.flags == PT_EDGE_LEFT_OUTER) ok = from == ed.u;
+      else if (ed.flags == PT_EDGE_RIGHT_OUTER) ok = from == ed.v;
+      else if (ed.flags == PT_EDGE_FULL_OUTER) ok = false;
+      pl.active[p * pl.n_e + e] = ok ? 1 : 0;
+    }
   }
   // Kahn's algorithm; the lowest ready index first.
   std::vector<uint32_t> indeg(pl.n_t, 0);
@@ -377,7 +397,7 @@ pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *
       uint64_t w = 0;
       uint32_t in_launch = 0;
       for (uint32_t e = 0; e < pl.n_e; e++) {
-        if ((pass == 0 ? pl.src[e] : pl.dst[e]) != v) continue;
+        if (!pl.sends(pass, e, v)) continue;
         if (in_launch == kMaxFilters) {
           group_words = std::max(group_words, w);
           w = 0;
@@ -401,7 +421,7 @@ pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *
     for (uint32_t v = 0; v < pl.n_t; v++) {
       uint32_t f = 0;
       for (uint32_t e = 0; e < pl.n_e; e++)
-        if ((pass == 0 ? pl.src[e] : pl.dst[e]) == v) f++;
+        if (pl.sends(pass, e, v)) f++;
       group_entries = std::max<uint64_t>(group_entries, static_cast<uint64_t>(std::min<uint32_t>(f, kMaxFilters)) *
                                                             tables[v].n_rows);
     }
@@ -706,6 +726,8 @@ pt_status pt_transfer_filter(const pt_graph *graph, const pt_table *tables, cons
   if (st != PT_OK) return st;
   if (!out || !d_ws) return fail(PT_EINVAL, "out or d_ws is NULL");
   if (pass < 1 || pass > 2 || edge >= pl.n_e) return fail(PT_EINVAL, "pass %u / edge %u out of range", pass, edge);
+  if (!pl.active[(pass - 1) * pl.n_e + edge])
+    return fail(PT_EINVAL, "edge %u carries no filter in pass %u (an outer join blocks that direction)", edge, pass);
   char *ws = static_cast<char *>(d_ws);
   const uint64_t slot = (pass - 1) * pl.n_e + edge;
   out->words = reinterpret_cast<uint32_t *>(ws + pl.off_filter[slot]);
@@ -827,7 +849,7 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
       sel.clear();
       rows.clear();
       for (uint32_t e = 0; e < pl.n_e; e++) {
-        if (to[e] != v) continue;
+        if (!pl.receives(p, e, v)) continue;
         keys.push_back(tb.cols[col_at(graph, e, v)]);
         blooms.push_back(bloom_at(p * pl.n_e + e));
         sel.push_back(built_sel[p * pl.n_e + e]);
@@ -869,7 +891,7 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
       blooms.clear();
       app_idx.clear();
       for (uint32_t e = 0; e < pl.n_e; e++) {
-        if (from[e] != v) continue;
+        if (!pl.sends(p, e, v)) continue;
         const uint32_t c = col_at(graph, e, v);
         keys.push_back(tb.cols[c]);
         blooms.push_back(bloom_at(p * pl.n_e + e));
@@ -1258,7 +1280,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
           if (lvl[p][i][v] != L || pr.tables[v].n_rows == 0) continue;
           std::vector<uint32_t> in;
           for (uint32_t e = 0; e < pl.n_e; e++)
-            if ((p == 0 ? pl.dst[e] : pl.src[e]) == v) in.push_back(e);
+            if (pl.receives(p, e, v)) in.push_back(e);
           if (in.empty()) continue;
           bp.rows_probed += pr.tables[v].n_rows;
           const uint64_t n_rows = pr.tables[v].n_rows, n_words = (n_rows + 63) / 64;
@@ -1304,7 +1326,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
           if (lvl[p][i][v] != L) continue;
           std::vector<uint32_t> out;
           for (uint32_t e = 0; e < pl.n_e; e++)
-            if ((p == 0 ? pl.src[e] : pl.dst[e]) == v) out.push_back(e);
+            if (pl.sends(p, e, v)) out.push_back(e);
           const uint64_t n_rows = pr.tables[v].n_rows, n_words = (n_rows + 63) / 64;
           for (uint32_t c0 = 0; c0 < out.size(); c0 += kMaxFilters) {
             BBuild b{};

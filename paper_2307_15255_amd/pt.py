@@ -160,6 +160,7 @@ def column(t: torch.Tensor) -> pt_column:
 
 
 PT_FLAG_NO_APPEND = 1
+PT_EDGE_INNER, PT_EDGE_LEFT_OUTER, PT_EDGE_RIGHT_OUTER, PT_EDGE_FULL_OUTER = 0, 1, 2, 3
 PT_FLAG_SHARED_SCAN = 2
 
 
@@ -290,9 +291,10 @@ class DeviceProblem:
             cc = (pt_column * max(1, len(columns[t])))(*[column(a) for a in columns[t].values()])
             self._ccols.append(cc)
             self.tables[t] = pt_table(self.n_rows[t], len(columns[t]), 0, cc)
+        flags = problem.edge_flags if problem.edge_flags is not None else [0] * len(problem.edges)
         self.edges = (pt_edge * max(1, len(problem.edges)))(*[
-            pt_edge(u, problem.col_index(u, uc), v, problem.col_index(v, vc), 0)
-            for u, uc, v, vc in problem.edges])
+            pt_edge(u, problem.col_index(u, uc), v, problem.col_index(v, vc), f)
+            for (u, uc, v, vc), f in zip(problem.edges, flags)])
         self._orient = None
         orient_ptr = None
         if problem.orient is not None:

@@ -127,12 +127,13 @@ def test_layout_parameters_validation(ptlib):
         assert ei.value.status == status
 
 
-def test_edge_flags_are_reserved(ptlib):
+def test_edge_flags(ptlib):
+    """Join types 0-3 (inner, left, right, full outer) are planned; other
+    values are rejected."""
     p = ptlib.params()
-    prob = _HostProblem(ptlib, [10, 100], [(0, 0, 1, 0, 0)])
-    assert prob.ws(ptlib, p)[0] == ptlib.PT_OK
-    prob = _HostProblem(ptlib, [10, 100], [(0, 0, 1, 0, 1)])
-    assert prob.ws(ptlib, p)[0] == ptlib.PT_EUNSUPPORTED
+    for flags in (ptlib.PT_EDGE_INNER, ptlib.PT_EDGE_LEFT_OUTER, ptlib.PT_EDGE_RIGHT_OUTER, ptlib.PT_EDGE_FULL_OUTER):
+        assert _HostProblem(ptlib, [10, 100], [(0, 0, 1, 0, flags)]).ws(ptlib, p)[0] == ptlib.PT_OK
+    assert _HostProblem(ptlib, [10, 100], [(0, 0, 1, 0, 4)]).ws(ptlib, p)[0] == ptlib.PT_EUNSUPPORTED
     assert "flags" in ptlib.lib().pt_last_error().decode()
 
 

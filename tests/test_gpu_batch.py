@@ -54,6 +54,18 @@ def test_tiny_graphs_every_shape(pt):
     check_against_oracle(pt, bt, probs, ps)
 
 
+def test_outer_join_edges(pt):
+    """Random graphs of every shape with outer-join edges (Sec. 3.4), in one
+    batch: every problem gets the oracle's bits."""
+    probs = [W.tiny_random(np.random.default_rng(96_000 + s), SHAPES[s % 6], outer=0.6) for s in range(30)]
+    ps = [pt.params(512, 3, 6)] * len(probs)
+    bt = pt.Batch([pt.DeviceProblem(p) for p in probs], ps)
+    say("batch outer")
+    bt.run(eager=True)
+    torch.cuda.synchronize()
+    check_against_oracle(pt, bt, probs, ps)
+
+
 def test_graph_replays_match_eager(pt):
     """A batch of chains and stars of 1 k to 200 k rows: the eager run and
     three replays of the captured graph (with unrelated GPU work and a

@@ -40,6 +40,10 @@ def check_transfer(pt, prob, B=512, k=3, bpk=10, filters=True, runs=1, flags=0, 
         assert counts[t] == ref.counts[t], (prob.label, t)
     if filters:
         for (p, e), words in ref.filters.items():
+            if ref.edge_src[(p, e)] == 0xFFFFFFFF:  # an outer join blocks this edge in this pass
+                with pytest.raises(pt.PtError):
+                    tr.filter(p + 1, e)
+                continue
             g_words, g_nb, g_builder = tr.filter(p + 1, e)
             assert g_builder == ref.edge_src[(p, e)]
             assert g_nb == ref.filter_nb[(p, e)], (prob.label, p, e)
@@ -182,3 +186,14 @@ def test_build_paths(pt, monkeypatch, path, max_entries):
         check_transfer(pt, prob)
     say("build path", path, max_entries, "star")
     check_transfer(pt, W.star(seed=9, n_fact=300_000, dims=(60_000, 7_000, 500, 25), payload=0))
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_outer_join_edges(pt, shape):
+    """Random graphs whose edges are inner, left, right or full outer joins
+    (Sec. 3.4): bitmaps, counts and every filter equal the oracle's, and no
+    filter exists for a direction an outer join blocks."""
+    for s in range(15):
+        prob = W.tiny_random(np.random.default_rng(95_000 + 1000 * SHAPES.index(shape) + s), shape, outer=0.6)
+        say(prob.label, s, prob.edge_flags)
+        check_transfer(pt, prob, 512, 3, 4)
