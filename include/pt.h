@@ -207,6 +207,17 @@ typedef struct pt_params {
  * filters are read from global memory the separate probes are faster. */
 #define PT_FLAG_SHARED_SCAN 2u
 
+/* pt_transfer with precise filters instead of Bloom filters (Sec. 3.2,
+ * "Filter Type"): every filter is the set of distinct keys of its builder's
+ * selected rows, so each transfer is a semi-join and the reduced tables
+ * hold no false positives (Sec. 2.2: with every edge towards one root the
+ * two passes are the semi-join phase of Yannakakis). The sets are hash
+ * tables in the workspace (16 bytes per builder row at most, sized on the
+ * device from the selected rows); block_bits, k and bits_per_key are
+ * checked but unused. pt_bloom_*, pt_transfer_filter and batches reject
+ * this flag with PT_EUNSUPPORTED. */
+#define PT_FLAG_EXACT 4u
+
 /* A Bloom filter in device memory. `words` holds cap_words uint32 words; the
  * filter in use is its first nb * B/32 words, where nb is the uint64 at
  * device address `d_nb` (written by pt_bloom_build). `d_status` is NULL or

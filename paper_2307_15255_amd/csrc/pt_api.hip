@@ -127,7 +127,7 @@ pt_status check_params(const pt_params *p) {
   if (p->k < 1 || p->k > 16) return fail(PT_EINVAL, "k %u outside [1, 16]", p->k);
   if (p->bits_per_key < 1 || p->bits_per_key > 64)
     return fail(PT_EINVAL, "bits_per_key %u outside [1, 64]", p->bits_per_key);
-  if ((p->flags & ~(PT_FLAG_NO_APPEND | PT_FLAG_SHARED_SCAN)) != 0)
+  if ((p->flags & ~(PT_FLAG_NO_APPEND | PT_FLAG_SHARED_SCAN | PT_FLAG_EXACT)) != 0)
     return fail(PT_EINVAL, "params.flags: unknown bits 0x%x", p->flags);
   if (p->hash_version > 1)
     return fail(PT_EUNSUPPORTED, "hash_version %u (this library implements version 1)", p->hash_version);
@@ -223,6 +223,8 @@ struct Plan {
   uint64_t off_counts = 0;         // 3 * n_t uint64: local, forward, backward
   uint64_t off_nb = 0;             // 2 * n_e uint64: forward, backward filters
   std::vector<uint64_t> off_filter, cap_words;  // [pass * n_e + e]
+  std::vector<uint32_t> set_lg;                 // exact filters: log2 of each set's slot capacity
+  bool exact = false;
   uint64_t off_scratch = 0;                     // private filter copies of the builds
   uint64_t scratch_words = 0;
   uint64_t off_hist = 0, off_totals = 0, off_starts = 0, off_entries = 0;  // partitioned builds
@@ -267,7 +269,7 @@ struct AppendPlan {
 AppendPlan append_plan(const Plan &pl, const pt_graph *g, const pt_table *tables, const pt_params &params,
                        uint32_t p, uint32_t v) {
   AppendPlan ap;
-  if ((params.flags & PT_FLAG_NO_APPEND) || tables[v].n_rows == 0) return ap;
+  if ((params.flags & (PT_FLAG_NO_APPEND | PT_FLAG_EXACT)) || tables[v].n_rows == 0) return ap;
   bool in = false, out = false;
   for (uint32_t e = 0; e < pl.n_e; e++) {
     in = in || pl.receives(p, e, v);
@@ -380,10 +382,20 @@ pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *
   off = align256(off + 2ull * pl.n_e * 8);
   pl.off_filter.assign(2ull * pl.n_e, 0);
   pl.cap_words.assign(2ull * pl.n_e, 0);
+  pl.exact = (params->flags & PT_FLAG_EXACT) != 0;
+  pl.set_lg.assign(2ull * pl.n_e, 0);
   for (uint32_t pass = 0; pass < 2; pass++) {
     for (uint32_t e = 0; e < pl.n_e; e++) {
       const uint32_t builder = pass == 0 ? pl.src[e] : pl.dst[e];
-      const uint64_t cap = capacity_words(tables[builder].n_rows, *params);
+      uint64_t cap = capacity_words(tables[builder].n_rows, *params);
+      if (pl.exact) {
+        // an exact set: int64 slots, at least twice the builder's rows, and
+        // one word that records the key INT64_MIN
+        uint32_t lg = 6;
+        while ((1ull << lg) < 2 * tables[builder].n_rows) lg++;
+        pl.set_lg[pass * pl.n_e + e] = lg;
+        cap = ((1ull << lg) + 1) * 2;
+      }
       pl.off_filter[pass * pl.n_e + e] = off;
       pl.cap_words[pass * pl.n_e + e] = cap;
       off = align256(off + cap * 4);
@@ -409,6 +421,7 @@ pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *
       group_words = std::max(group_words, w);
     }
   }
+  if (pl.exact) group_words = 0;  // sets are built in place
   const uint64_t copy_words = std::min<uint64_t>(group_words, build_lds_words());
   pl.off_scratch = off;
   pl.scratch_words = copy_words * static_cast<uint64_t>(device_info().n_cu);
@@ -426,6 +439,7 @@ pt_status make_plan(const pt_graph *g, const pt_table *tables, const pt_params *
                                                             tables[v].n_rows);
     }
   }
+  if (pl.exact) group_entries = 0;
   const char *force = std::getenv("PT_BUILD_PATH");
   const bool force_part = force && std::strcmp(force, "part") == 0;
   if ((group_words > build_lds_words() || force_part) && group_entries > 0) {
@@ -622,6 +636,45 @@ static pt_status probe_filters(uint32_t n_filters, const pt_column *keys, const 
   return PT_OK;
 }
 
+// The exact set that edge e carries in pass p, read through table v's key
+// column (the builder's when building, the receiver's when probing).
+static SetRef set_at(const Plan &pl, const pt_graph *g, const pt_table *tables, char *ws, uint32_t p, uint32_t e,
+                     uint32_t v) {
+  const uint32_t slot = p * pl.n_e + e;
+  const pt_column &c = tables[v].cols[col_at(g, e, v)];
+  SetRef f{};
+  f.keys = reinterpret_cast<unsigned long long *>(ws + pl.off_filter[slot]);
+  f.lg = reinterpret_cast<uint64_t *>(ws + pl.off_nb) + slot;
+  f.col = c.data;
+  f.key64 = c.dtype == PT_I64 ? 1u : 0u;
+  f.lg_cap = pl.set_lg[slot];
+  return f;
+}
+
+// Probes every set table v receives in pass p, kMaxProbe per scan; the last
+// scan counts the rows left into *d_count (which holds zero).
+static pt_status probe_sets(const Plan &pl, const pt_graph *g, const pt_table *tables, char *ws, uint32_t p,
+                            uint32_t v, uint64_t *d_bitmap, uint64_t *d_count, bool input_all, hipStream_t s) {
+  std::vector<uint32_t> in;
+  for (uint32_t e = 0; e < pl.n_e; e++)
+    if (pl.receives(p, e, v)) in.push_back(e);
+  for (size_t c0 = 0; c0 < in.size(); c0 += kMaxProbe) {
+    SetProbe sp{};
+    uint64_t bytes = (c0 == 0 && input_all ? 1 : 2) * ((tables[v].n_rows + 63) / 64 * 8);
+    for (size_t j = c0; j < in.size() && sp.n < static_cast<uint32_t>(kMaxProbe); j++) {
+      sp.f[sp.n++] = set_at(pl, g, tables, ws, p, in[j], v);
+      bytes += tables[v].n_rows * key_bytes(tables[v].cols[col_at(g, in[j], v)]);
+    }
+    const bool last = c0 + kMaxProbe >= in.size();
+    Timed tm("probe", v, p + 1, tables[v].n_rows, bytes, s);
+    pt_status st = check_hip(launch_set_probe(sp, tables[v].n_rows, d_bitmap, last ? d_count : nullptr,
+                                              input_all && c0 == 0, s),
+                             "set probe launch");
+    if (st != PT_OK) return st;
+  }
+  return PT_OK;
+}
+
 pt_status pt_bloom_build(uint32_t n_filters, const pt_column *keys, const pt_bloom *filters,
                          uint64_t n_rows, const uint64_t *d_bitmap, const uint64_t *d_count,
                          pt_stream stream) {
@@ -635,6 +688,7 @@ pt_status pt_bloom_build(uint32_t n_filters, const pt_column *keys, const pt_blo
     st = check_filter(filters[i], filters[0].params, n_rows, i);
     if (st != PT_OK) return st;
   }
+  if (filters[0].params.flags & PT_FLAG_EXACT) return fail(PT_EUNSUPPORTED, "a pt_bloom is a Bloom filter (PT_FLAG_EXACT)");
   return build_filters(n_filters, keys, filters, n_rows, d_bitmap, d_bitmap ? d_count : nullptr,
                        nullptr, nullptr, nullptr, filters[0].d_status, reinterpret_cast<hipStream_t>(stream), 0,
                        0);
@@ -656,6 +710,8 @@ pt_status pt_bloom_probe(uint32_t n_filters, const pt_column *keys, const pt_blo
       return fail(PT_EINVAL, "filter %u: cap_words below one block", i);
     if (!same_filter(filters[i].params, filters[0].params))
       return fail(PT_EINVAL, "filter %u: parameters differ from filter 0", i);
+    if (filters[i].params.flags & PT_FLAG_EXACT)
+      return fail(PT_EUNSUPPORTED, "a pt_bloom is a Bloom filter (PT_FLAG_EXACT)");
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (n_filters == 0) {
@@ -726,6 +782,7 @@ pt_status pt_transfer_filter(const pt_graph *graph, const pt_table *tables, cons
   if (st != PT_OK) return st;
   if (!out || !d_ws) return fail(PT_EINVAL, "out or d_ws is NULL");
   if (pass < 1 || pass > 2 || edge >= pl.n_e) return fail(PT_EINVAL, "pass %u / edge %u out of range", pass, edge);
+  if (pl.exact) return fail(PT_EUNSUPPORTED, "exact filters are key sets, not pt_bloom filters");
   if (!pl.active[(pass - 1) * pl.n_e + edge])
     return fail(PT_EINVAL, "edge %u carries no filter in pass %u (an outer join blocks that direction)", edge, pass);
   char *ws = static_cast<char *>(d_ws);
@@ -871,10 +928,13 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
             dst += align256(append_capacity(tb.n_rows) * key_bytes(col));
           }
         }
-        st = probe_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), sel.data(),
-                           rows.data(), tb.n_rows, d_bitmaps[v], cnt, all_rows[v] != 0,
-                           /*count_zeroed=*/true, ap.cols.empty() ? nullptr : &app,
-                           append_capacity(tb.n_rows), status, s, v, p + 1);
+        if (pl.exact)
+          st = probe_sets(pl, graph, tables, ws, p, v, d_bitmaps[v], cnt, all_rows[v] != 0, s);
+        else
+          st = probe_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), sel.data(),
+                             rows.data(), tb.n_rows, d_bitmaps[v], cnt, all_rows[v] != 0,
+                             /*count_zeroed=*/true, ap.cols.empty() ? nullptr : &app,
+                             append_capacity(tb.n_rows), status, s, v, p + 1);
         if (st != PT_OK) return st;
         if (app.n_cols > 0) {
           pending = app;
@@ -900,7 +960,18 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
           app_idx.push_back(static_cast<uint32_t>(
               std::find(pending_cols.begin(), pending_cols.end(), c) - pending_cols.begin() + 1));
       }
-      if (!keys.empty()) {
+      if (!keys.empty() && pl.exact) {
+        const bool all = all_rows[v] != 0;
+        for (uint32_t e = 0; e < pl.n_e; e++) {
+          if (!pl.sends(p, e, v)) continue;
+          Timed tm("build", v, p + 1, tb.n_rows, tb.n_rows * key_bytes(tb.cols[col_at(graph, e, v)]), s);
+          st = check_hip(launch_set_build(set_at(pl, graph, tables, ws, p, e, v), tb.n_rows,
+                                          all ? nullptr : d_bitmaps[v], all ? nullptr : counts + cur[v] * pl.n_t + v,
+                                          s),
+                         "set build launch");
+          if (st != PT_OK) return st;
+        }
+      } else if (!keys.empty()) {
         const bool all = all_rows[v] != 0;
         st = build_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), tb.n_rows,
                            all ? nullptr : d_bitmaps[v], all ? nullptr : counts + cur[v] * pl.n_t + v,
@@ -1001,6 +1072,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
     const pt_problem &pr = probs[i];
     Plan &pl = bp.plans[i];
     pt_params params = pr.params;
+    if (params.flags & PT_FLAG_EXACT) return fail(PT_EUNSUPPORTED, "problem %u: a batch runs Bloom filters only", i);
     params.flags |= PT_FLAG_NO_APPEND;
     pt_status st = make_plan(pr.graph, pr.tables, &params, pl);
     if (st != PT_OK) return fail(st, "problem %u: %s", i, g_error.c_str());

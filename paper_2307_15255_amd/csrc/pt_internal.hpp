@@ -324,6 +324,31 @@ hipError_t prepare_batch_512();
 // Bytes of LDS a probe workgroup needs besides its staged filters.
 uint64_t probe_queue_bytes();
 
+// ---------------------------------------------------------- exact filters
+// (k_exact.hip) The precise filter of Sec. 3.2: the distinct keys of the
+// builder's selected rows in a device hash table.
+struct SetRef {
+  unsigned long long *keys;  // 2^lg_cap slots, then one word: INT64_MIN present
+  uint64_t *lg;              // device: log2 of the slots in use (set by the build)
+  const void *col;           // key column of the table the launch scans
+  uint32_t key64;
+  uint32_t lg_cap;
+};
+struct SetProbe {
+  uint32_t n;
+  uint32_t pad;
+  SetRef f[kMaxProbe];
+};
+// Sizes the set from *count (n_rows when NULL), clears it, and inserts the
+// keys of f.col's selected rows (bitmap NULL: every row).
+hipError_t launch_set_build(const SetRef &f, uint64_t n_rows, const uint64_t *bitmap, const uint64_t *count,
+                            hipStream_t s);
+// Clears the bitmap bit of every row whose key misses one of the sets
+// (input_all: the bitmap is not read, every row starts selected); adds the
+// rows left to *count (NULL: not counted).
+hipError_t launch_set_probe(const SetProbe &sp, uint64_t n_rows, uint64_t *bitmap, uint64_t *count, bool input_all,
+                            hipStream_t s);
+
 // ---------------------------------------------------------- join phase
 // (k_join.hip) Hash joins on the reduced tables: each table added to the
 // join gets a hash table over its selected rows; the tuples built so far

@@ -54,7 +54,7 @@ def test_capacity_and_workspace_sizes(ptlib):
 def test_parameter_validation(ptlib):
     bad = [ptlib.pt_params(48, 3, 10, 0), ptlib.pt_params(2048, 3, 10, 0), ptlib.pt_params(512, 0, 10, 0),
            ptlib.pt_params(512, 17, 10, 0), ptlib.pt_params(512, 3, 0, 0), ptlib.pt_params(512, 3, 65, 0),
-           ptlib.pt_params(512, 3, 10, 4), ptlib.pt_params(512, 3, 10, 0x80000001)]
+           ptlib.pt_params(512, 3, 10, 8), ptlib.pt_params(512, 3, 10, 0x80000001)]
     for p in bad:
         with pytest.raises(ptlib.PtError) as ei:
             ptlib.pt_bloom_capacity(10, p)
@@ -201,3 +201,18 @@ def test_join_rejects_bad_buffers(ptlib):
     assert lib.pt_join(C.byref(chain.graph), chain.tables, 2, None, outs, 16, C.byref(n_out), 4096, size,
                        None) == ptlib.PT_EINVAL
     assert "d_out[1]" in lib.pt_last_error().decode()
+
+
+def test_exact_flag_planning(ptlib):
+    """PT_FLAG_EXACT: the transfer plans key sets (at least 16 bytes per
+    builder row); a batch rejects it."""
+    chain = _HostProblem(ptlib, [10, 100, 1000], [(0, 0, 1, 0), (1, 1, 2, 0)])
+    st, size = chain.ws(ptlib, ptlib.params(flags=ptlib.PT_FLAG_EXACT))
+    assert st == ptlib.PT_OK
+    # forward builders R (10 rows) and S (100), backward S and T (1 000)
+    assert size >= 16 * (10 + 100 + 100 + 1000)
+    probs = (ptlib.pt_problem * 1)()
+    probs[0] = ptlib.pt_problem(C.pointer(chain.graph), chain.tables, None, 0, 0,
+                                ptlib.params(flags=ptlib.PT_FLAG_EXACT), None, None)
+    out = C.c_size_t()
+    assert ptlib.lib().pt_batch_workspace_size(1, probs, C.byref(out)) == ptlib.PT_EUNSUPPORTED
