@@ -43,7 +43,7 @@ def parse():
                     help="builds rescan the table instead of reading keys appended by its probe")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-join", action="store_true", help="star: skip the join-phase timing")
+    ap.add_argument("--no-join", action="store_true", help="star: skip the join-phase and exact-filter timings")
     ap.add_argument("--check", action="store_true", help="compare the result with the oracle")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without the per-kernel HIP events (no roofline figure)")
@@ -245,6 +245,7 @@ def main():
 
     if args.workload == "star" and not args.no_join:
         out["join"] = bench_join(args, torch, pt, prob, dp, tr)
+        out["exact_filters"] = bench_exact(args, torch, pt, prob, dp, tr, ms_per_step)
 
     if args.calibrate_copy:
         out["calibration_copy_bytes"] = 1 << 30
@@ -322,6 +323,32 @@ def bench_join(args, torch, pt, prob, dp, tr) -> dict:
         res[name] = {"ms": round(float(np.median(times)), 4), "tuples": int(j.n_out.item())}
     res["tuples_equal"] = res["after_transfer"]["tuples"] == res["after_local_filters_only"]["tuples"]
     res["root"] = "fact table; dimensions added in edge order as hash-table build sides"
+    return res
+
+
+def bench_exact(args, torch, pt, prob, dp, tr, bloom_ms: float) -> dict:
+    """The same transfer with exact filters (PT_FLAG_EXACT: key sets, every
+    transfer a semi-join, Sec. 3.2), timed apart from the Bloom steps: its
+    time per step against the Bloom step, and the rows each leaves."""
+    ex = pt.Transfer(dp, pt.params(512, 3, 10, pt.PT_FLAG_EXACT))
+    for _ in range(2):
+        ex.run()
+    ex.check_status()
+    times = []
+    for _ in range(max(3, min(args.steps, 20))):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        ex.run()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = float(np.median(times))
+    res = {"ms_per_step": round(ms, 4), "vs_bloom_step": round(ms / bloom_ms, 2),
+           "rows_left": [int(x) for x in ex.counts.cpu().tolist()],
+           "rows_left_bloom": [int(x) for x in tr.counts.cpu().tolist()],
+           "workspace_GB": round(ex.ws_bytes / 2**30, 2)}
+    del ex
+    torch.cuda.empty_cache()
     return res
 
 

@@ -71,6 +71,20 @@ class _Dump(C.Structure):
                 ("edge_src", C.POINTER(C.c_uint32))]
 
 
+_SAN_PATH = os.path.join(_HERE, "libpt_oracle_san.so")
+
+
+def build_sanitized() -> str:
+    """The oracle under AddressSanitizer and UBSan (any finding aborts), for
+    the CPU test that runs the pins against it under gcc's runtime."""
+    tmp = _SAN_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-fopenmp",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+                           "-o", tmp, _SRC])
+    os.replace(tmp, _SAN_PATH)
+    return _SAN_PATH
+
+
 def build(force: bool = True) -> str:
     """Compile pt_oracle.c with gcc into oracle/libpt_oracle.so (plain -O2,
     no SIMD intrinsics; OpenMP only for the optional row split of the

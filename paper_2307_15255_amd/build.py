@@ -28,6 +28,16 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpt_hip.so")
+# A build whose host code carries AddressSanitizer and UBSan (the device code
+# is built as usual); only the CPU tests load it, under the sanitizer runtime.
+SAN_OBJ = os.path.join(HERE, "_build_san")
+SAN_LIB = os.path.join(HERE, "libpt_hip_san.so")
+SAN_FLAGS = [
+    "-Xarch_host", "-fsanitize=address,undefined",
+    "-Xarch_host", "-fno-sanitize-recover=all",
+    "-Xarch_host", "-fno-omit-frame-pointer",
+    "-g",
+]
 HASH = LIB + ".srchash"
 HEADER = os.path.join(ROOT, "include", "pt.h")
 
@@ -64,9 +74,10 @@ def _jobs(jobs: int | None) -> int:
     return max(1, min(16, n))
 
 
-def _compile(src: str, verbose: bool) -> tuple[str, float]:
-    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+def _compile(src: str, verbose: bool, sanitize: bool = False) -> tuple[str, float]:
+    obj = os.path.join(SAN_OBJ if sanitize else OBJ, os.path.basename(src) + ".o")
+    flags = [f for f in FLAGS if not (sanitize and f == "-O3")] + (["-O1", *SAN_FLAGS] if sanitize else [])
+    cmd = [HIPCC, *flags, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     t = time.time()
@@ -79,21 +90,26 @@ def _compile(src: str, verbose: bool) -> tuple[str, float]:
     return obj, time.time() - t
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    """Compile every unit (in parallel) and link libpt_hip.so."""
-    os.makedirs(OBJ, exist_ok=True)
+def build(verbose: bool = False, jobs: int | None = None, sanitize: bool = False) -> str:
+    """Compile every unit (in parallel) and link libpt_hip.so (sanitize:
+    libpt_hip_san.so, host code under AddressSanitizer and UBSan)."""
+    os.makedirs(SAN_OBJ if sanitize else OBJ, exist_ok=True)
     digest = source_hash()
     srcs = sources()
     t0 = time.time()
     with cf.ThreadPoolExecutor(max_workers=_jobs(jobs)) as ex:
-        results = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        results = list(ex.map(lambda s: _compile(s, verbose, sanitize), srcs))
     objs = [o for o, _ in results]
-    tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    lib = SAN_LIB if sanitize else LIB
+    tmp = lib + f".tmp{os.getpid()}"
+    link_flags = ["-Xarch_host", "-fsanitize=address,undefined"] if sanitize else []
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, *link_flags, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+    if sanitize:
+        return lib
     with open(HASH + ".tmp", "w") as f:
         f.write(digest + "\n")
     os.replace(HASH + ".tmp", HASH)

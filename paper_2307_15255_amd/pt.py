@@ -81,8 +81,13 @@ class pt_kernel_time(C.Structure):
 
 
 def _load() -> C.CDLL:
-    from . import build
-    build.ensure_built()
+    global LIB_PATH
+    if os.environ.get("PT_LIB_PATH"):
+        # another build of the library (the sanitizer build the CPU tests use)
+        LIB_PATH = os.environ["PT_LIB_PATH"]
+    else:
+        from . import build
+        build.ensure_built()
     L = C.CDLL(LIB_PATH)
     vp, u32, u64, st = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
     sizep = C.POINTER(C.c_size_t)
