@@ -1479,10 +1479,32 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
   // The list in phase order (stable): items of a phase follow every item of
   // the phases before it.
   {
+    // Within a phase the longest items go first, so that the phase's last
+    // items are short and few workgroups wait at its end.
+    std::vector<double> cost(bp.tasks.size(), 0.0);
+    for (uint32_t t = 0; t < bp.tasks.size(); t++) {
+      const BTask &k = bp.tasks[t];
+      const double items = k.n_items;
+      switch (k.kind) {
+        case kBLocal: cost[t] = bp.locals[k.arg].n_rows * (1.0 + bp.locals[k.arg].ps.n) / items; break;
+        case kBProbe: cost[t] = bp.probes[k.arg].n_rows * (1.0 + bp.probes[k.arg].fs.n) / items; break;
+        case kBShared: cost[t] = bp.shared[k.arg].n_rows * (1.0 + bp.shared[k.arg].n_members) / items; break;
+        case kBBuild:
+        case kBCount:
+        case kBScatter:
+        case kBFill: cost[t] = bp.builds[k.arg].n_rows * (1.0 + bp.builds[k.arg].fs.n) / items; break;
+        case kBScan: cost[t] = 1.0 * bp.builds[k.arg].hist_cols * bp.builds[k.arg].hist_rows; break;
+        case kBReduce:
+        case kBZero: cost[t] = 4096.0; break;
+        default: cost[t] = 0.0;
+      }
+    }
     std::vector<uint32_t> order(bp.tasks.size());
     for (uint32_t t = 0; t < order.size(); t++) order[t] = t;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t x, uint32_t y) { return bp.tasks[x].phase < bp.tasks[y].phase; });
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+      if (bp.tasks[x].phase != bp.tasks[y].phase) return bp.tasks[x].phase < bp.tasks[y].phase;
+      return cost[x] > cost[y];
+    });
     std::vector<BTask> sorted;
     sorted.reserve(order.size());
     uint32_t n_phases = 0;
