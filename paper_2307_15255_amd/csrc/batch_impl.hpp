@@ -412,7 +412,7 @@ __device__ __forceinline__ void run_item(const BatchArgs &a, const BTask &task, 
       const AppendSet none{};
       part_scatter_body<false, K>(b.fs, none, b.k, block_log2<B>(b.lg), b.bits_per_key, b.count, b.n_rows, b.bitmap,
                                   b.seg_words, b.entries_cap, b.hist + static_cast<uint64_t>(vg.block) * b.hist_cols,
-                                  b.starts, b.entries, a.status, true, kBatchTargetBuckets, vg);
+                                  b.starts, b.entries, a.status, true, kBatchTargetBuckets, vg, a.lds_bytes);
       break;
     }
     case kBFill: {

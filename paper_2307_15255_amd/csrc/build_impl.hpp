@@ -95,14 +95,20 @@ __device__ __forceinline__ void hash_rows(const void *keys, uint32_t key64, cons
   }
 }
 
+struct NoHook {
+  __device__ void operator()() const {}
+};
+
 // Calls g(h1, h2) for the key of every selected row in the key column of
 // filter f. Without appended keys (APP false, or f.app == 0) the grid's
 // waves walk the bitmap; with them each wave takes whole regions, reading
 // their appended keys (contiguous) or, for a region that overflowed,
-// walking the bitmap words of the probe groups it covers.
-template <bool APP, typename G>
+// walking the bitmap words of the probe groups it covers. after() runs with
+// every lane of the wave after each key a lane may have passed to g.
+template <bool APP, typename G, typename H = NoHook>
 __device__ __forceinline__ void for_each_key(const FilterRef &f, const AppendSet &app, uint64_t n_rows,
-                                             const uint64_t *bitmap, uint32_t seg_words, const VGrid &vg, G &&g) {
+                                             const uint64_t *bitmap, uint32_t seg_words, const VGrid &vg, G &&g,
+                                             H &&after = H{}) {
   constexpr int U = kWalkBatch;
   const void *keys = f.keys;
   const uint32_t key64 = f.key64;
@@ -110,8 +116,10 @@ __device__ __forceinline__ void for_each_key(const FilterRef &f, const AppendSet
     uint32_t h1[U], h2[U];
     hash_rows<U>(keys, key64, row, ok, h1, h2);
 #pragma unroll
-    for (int u = 0; u < U; u++)
+    for (int u = 0; u < U; u++) {
       if ((ok >> u) & 1) g(h1[u], h2[u]);
+      after();
+    }
   };
   if (!APP || app.n_cols == 0 || f.app == 0) {
     walk_rows<U>(global_wave(vg), wave_count(vg), seg_words, n_rows, bitmap, from_rows);
@@ -140,8 +148,10 @@ __device__ __forceinline__ void for_each_key(const FilterRef &f, const AppendSet
       uint32_t h1[U], h2[U];
       hash_rows<U>(col, col64, idx, ok, h1, h2);
 #pragma unroll
-      for (int u = 0; u < U; u++)
+      for (int u = 0; u < U; u++) {
         if ((ok >> u) & 1) g(h1[u], h2[u]);
+        after();
+      }
     }
   }
 }
@@ -153,7 +163,7 @@ namespace pt {
 // ---------------------------------------------------- partitioned builds
 //
 // Filters too large for LDS are built tile by tile: each filter's blocks are
-// cut into tiles of tile_blocks blocks (at most 64 KB) and every (filter,
+// cut into tiles of tile_blocks blocks (at most 128 KB) and every (filter,
 // tile) pair is a bucket; filter i's buckets follow those of filters < i.
 // The plan fits when the buckets fit the bucket table and every key of
 // every filter fits the entry buffer (entries_cap entries).
@@ -183,7 +193,7 @@ __device__ __forceinline__ PartGeo part_geo(const FilterSet &fs, uint32_t lg, ui
   g.n_sel = count ? *count : n_rows;
   uint64_t all_blocks = 0;
   for (uint32_t i = 0; i < fs.n; i++) all_blocks += part_blocks(fs.f[i], lg, bits_per_key, g.n_sel, from_count);
-  // Tiles of at most 64 KB, small enough that the group has about
+  // Tiles of at most 128 KB, small enough that the group has about
   // target_buckets of them (the fill step runs one workgroup per tile).
   uint64_t tb = (all_blocks + target_buckets - 1) / target_buckets;
   const uint64_t max_tb = kTileWords >> (lg - 5);

@@ -62,10 +62,10 @@ __global__ void __launch_bounds__(kWideThreads)
     k_part_scatter(FilterSet fs, AppendSet app, uint32_t k, uint32_t lg_rt, uint32_t bits_per_key,
                    const uint64_t *count, uint64_t n_rows, const uint64_t *__restrict__ bitmap, uint32_t seg_words,
                    uint64_t entries_cap, const uint32_t *__restrict__ hist, const uint64_t *__restrict__ starts,
-                   uint32_t *__restrict__ entries, uint32_t *status) {
+                   uint32_t *__restrict__ entries, uint32_t *status, uint64_t lds_bytes) {
   part_scatter_body<true, K>(fs, app, k, block_log2<B>(lg_rt), bits_per_key, count, n_rows, bitmap, seg_words,
                              entries_cap, hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, starts, entries,
-                             status, false, kTargetBuckets, whole_grid());
+                             status, false, kTargetBuckets, whole_grid(), lds_bytes);
 }
 
 template <int B, int K>
@@ -95,7 +95,7 @@ hipError_t launch_part_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_
   const uint32_t n_groups = static_cast<uint32_t>(groups);
   const uint32_t W = block_bits / 32;
   // Upper bound of the device's bucket count: kTargetBuckets plus one
-  // partial tile per filter, or the 64 KB tiles of the largest filters.
+  // partial tile per filter, or the 128 KB tiles of the largest filters.
   uint64_t max_buckets = kTargetBuckets + fs.n;
   {
     uint64_t big = 0;
@@ -111,7 +111,10 @@ hipError_t launch_part_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_
   auto scatter_k = spec ? k_part_scatter<512, 3> : k_part_scatter<0, 0>;
   auto fill_k = spec ? k_part_fill<512, 3> : k_part_fill<0, 0>;
   const uint64_t hist_bytes = max_buckets * 4;
-  const uint64_t cursor_bytes = max_buckets * 8;
+  // the scatter stages entries per bucket in LDS when every bucket's stage fits
+  const uint64_t lds_avail = static_cast<uint64_t>(device_info().max_lds_block) - 2048;
+  const uint64_t staged_bytes = max_buckets * kStagedBucketBytes;
+  const uint64_t cursor_bytes = staged_bytes <= lds_avail ? staged_bytes : max_buckets * 8;
   const uint64_t tile_bytes = static_cast<uint64_t>(kTileWords) * 4;
   hipError_t e = allow_lds(reinterpret_cast<const void *>(count_k), hist_bytes);
   if (e == hipSuccess) e = allow_lds(reinterpret_cast<const void *>(scatter_k), cursor_bytes);
@@ -125,7 +128,7 @@ hipError_t launch_part_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_
                      entries_cap, scratch.totals, scratch.starts);
   hipLaunchKernelGGL(scatter_k, dim3(n_groups), dim3(kWideThreads), cursor_bytes, s, fs, a, k, lg, bits_per_key,
                      count, n_rows, bitmap, seg_words, entries_cap, scratch.hist, scratch.starts, scratch.entries,
-                     status);
+                     status, cursor_bytes);
   hipLaunchKernelGGL(fill_k, dim3(static_cast<uint32_t>(fill_grid ? fill_grid : 1)), dim3(kWideThreads), tile_bytes,
                      s, fs, k, lg, bits_per_key, count, n_rows, entries_cap, scratch.starts, scratch.entries);
   return hipGetLastError();

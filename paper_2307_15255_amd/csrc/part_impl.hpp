@@ -3,7 +3,7 @@
 // a table receive the keys of its selected rows), over a (virtual) grid:
 // shared by the partitioned-build kernels and the batch kernel.
 //
-// Each filter's blocks are cut into tiles of at most 64 KB, and every
+// Each filter's blocks are cut into tiles of at most 128 KB, and every
 // (filter, tile) pair is a bucket (buckets of filter i follow those of
 // filters < i).
 //   count    each workgroup walks its rows and histograms their bucket
@@ -26,7 +26,7 @@ namespace pt {
 
 // An entry is 32 bits: the block within its tile above the top 2 log2(B)
 // bits of H2, the only bits of H2 the bit positions use. Tiles hold at most
-// 64 KB, so the block index fits (14 bits for B = 32, 9 for B = 1024).
+// 128 KB, so the block index fits (15 bits for B = 32, 10 for B = 1024).
 __device__ __forceinline__ uint32_t pack_entry(uint32_t blk_in_tile, uint32_t h2, uint32_t lg) {
   return (blk_in_tile << (2 * lg)) | (h2 >> (32 - 2 * lg));
 }
@@ -82,17 +82,37 @@ __device__ __forceinline__ void part_count_body(const FilterSet &fs, const Appen
   for (uint32_t b = threadIdx.x; b < geo.buckets; b += blockDim.x) hist_row[b] = s_hist[b];
 }
 
+// Entries a bucket gathers in LDS before they are stored as one run.
+constexpr uint32_t kStageEntries = 32;
+// LDS bytes per bucket of a staged scatter: cursor, claim and write counts,
+// the staged entries.
+constexpr uint32_t kStagedBucketBytes = 8 + 4 + 4 + 4 * kStageEntries;
+// Fewer buckets than this are not staged: each wave's stores to one bucket
+// already form runs, and the workgroup's claims would crowd a few counters.
+constexpr uint32_t kStageMinBuckets = 64;
+
 // Writes this workgroup's entries at its ranges (hist_row: its exclusive
 // offsets within each bucket, starts: the buckets' first entries). When the
 // plan does not fit the entry buffer, inserts in place with global atomics
 // instead (the filters were zeroed in that case).
+//
+// With many buckets and room in lds_bytes for every bucket's stage, entries
+// are not stored one by one (thousands of buckets take one 4-byte store
+// each, and the partial cache lines cost several times the bytes in
+// write-backs): a lane claims a slot of its bucket's stage in LDS and
+// writes the entry there; the lane whose write fills the stage marks it,
+// and right after that key its wave stores the stage as one coalesced run
+// at the bucket's cursor and empties it. A claim beyond a full stage that
+// is not emptied yet stores its entry directly. What is left in the stages
+// is stored at the end. Every entry is stored exactly once, at the
+// workgroup's range of its bucket.
 template <bool APP, int K>
 __device__ __forceinline__ void part_scatter_body(const FilterSet &fs, const AppendSet &app, uint32_t k, uint32_t lg,
                                                   uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
                                                   const uint64_t *bitmap, uint32_t seg_words, uint64_t entries_cap,
                                                   const uint32_t *hist_row, const uint64_t *starts,
                                                   uint32_t *entries, uint32_t *status, bool from_count,
-                                                  uint32_t target, const VGrid &vg) {
+                                                  uint32_t target, const VGrid &vg, uint64_t lds_bytes = 0) {
   extern __shared__ __align__(16) uint64_t s_cur[];
   const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, from_count, target);
   if (!geo.ok) {
@@ -106,23 +126,82 @@ __device__ __forceinline__ void part_scatter_body(const FilterSet &fs, const App
     return;
   }
   // s_cur[b]: the next entry slot of this workgroup in bucket b
-  for (uint32_t b = threadIdx.x; b < geo.buckets; b += blockDim.x) s_cur[b] = starts[b] + hist_row[b];
+  const uint32_t nbk = geo.buckets;
+  const bool staged = nbk >= kStageMinBuckets && static_cast<uint64_t>(nbk) * kStagedBucketBytes <= lds_bytes;
+  uint32_t *s_claim = reinterpret_cast<uint32_t *>(s_cur + nbk);  // [nbk]: slots claimed
+  uint32_t *s_wrote = s_claim + nbk;                               // [nbk]: slots written
+  uint32_t *s_stage = s_wrote + nbk;                               // [nbk][kStageEntries]
+  for (uint32_t b = threadIdx.x; b < nbk; b += blockDim.x) {
+    s_cur[b] = starts[b] + hist_row[b];
+    if (staged) s_claim[b] = s_wrote[b] = 0;
+  }
   __syncthreads();
   const uint32_t tb = geo.tile_blocks;
+  const uint32_t lane = lane_id();
+  auto store = [&](uint64_t pos, uint32_t e) {
+    if (pos < entries_cap)  // always true while *count is the bitmap's popcount
+      entries[pos] = e;
+    else
+      raise_status(status, PT_STATUS_ENTRIES_OVERFLOW);
+  };
   uint32_t base = 0;
   for (uint32_t i = 0; i < fs.n; i++) {
     const FilterRef &f = fs.f[i];
     const uint32_t nb = part_blocks(f, lg, bits_per_key, geo.n_sel, from_count);
-    unsigned long long *cur = reinterpret_cast<unsigned long long *>(s_cur) + base;
-    for_each_key<APP>(f, app, n_rows, bitmap, seg_words, vg, [&](uint32_t h1, uint32_t h2) {
-      const uint32_t blk = block_of(h1, nb);
-      const uint64_t pos = wave_counter_add(cur, blk / tb);
-      if (pos < entries_cap)  // always true while *count is the bitmap's popcount
-        entries[pos] = pack_entry(blk % tb, h2, lg);
-      else
-        raise_status(status, PT_STATUS_ENTRIES_OVERFLOW);
-    });
+    unsigned long long *cur = reinterpret_cast<unsigned long long *>(s_cur);
+    if (!staged) {
+      for_each_key<APP>(f, app, n_rows, bitmap, seg_words, vg, [&](uint32_t h1, uint32_t h2) {
+        const uint32_t blk = block_of(h1, nb);
+        store(wave_counter_add(cur + base, blk / tb), pack_entry(blk % tb, h2, lg));
+      });
+    } else {
+      constexpr uint32_t kNone = 0xFFFFFFFFu;
+      uint32_t full = kNone;  // this lane filled the stage of bucket `full`
+      auto put = [&](uint32_t h1, uint32_t h2) {
+        const uint32_t blk = block_of(h1, nb);
+        const uint32_t b = base + blk / tb;
+        const uint32_t e = pack_entry(blk % tb, h2, lg);
+        const uint32_t slot = atomicAdd(&s_claim[b], 1u);
+        if (slot >= kStageEntries) {  // the stage is full and not emptied yet
+          store(atomicAdd(&cur[b], 1ull), e);
+          return;
+        }
+        s_stage[b * kStageEntries + slot] = e;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (atomicAdd(&s_wrote[b], 1u) == kStageEntries - 1) full = b;
+      };
+      auto flush = [&]() {
+        // every lane takes part: kStageEntries lanes store one full stage at a time
+        for (uint64_t m = __ballot(full != kNone); m; m &= m - 1) {
+          const uint32_t src = __builtin_amdgcn_readlane(full, __builtin_ctzll(m));
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          uint64_t at = 0;
+          if (lane == 0) at = atomicAdd(&cur[src], static_cast<unsigned long long>(kStageEntries));
+          at = (static_cast<uint64_t>(__builtin_amdgcn_readlane(static_cast<uint32_t>(at >> 32), 0)) << 32) |
+               static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<uint32_t>(at), 0));
+          if (lane < kStageEntries) store(at + lane, s_stage[src * kStageEntries + lane]);
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the stage's reads come first
+          // the stage is read: reopen it (the write count first, so that new
+          // claims start from a zero count)
+          if (lane == 0) {
+            atomicExch(&s_wrote[src], 0u);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            atomicExch(&s_claim[src], 0u);
+          }
+        }
+        full = kNone;
+      };
+      for_each_key<APP>(f, app, n_rows, bitmap, seg_words, vg, put, flush);
+    }
     base += (nb + tb - 1) / tb;
+  }
+  if (!staged) return;
+  // what is left in the stages (fewer than 16 entries each)
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < nbk; b += blockDim.x) {
+    const uint32_t n = min(s_wrote[b], kStageEntries);
+    for (uint32_t j = 0; j < n; j++) store(s_cur[b] + j, s_stage[b * kStageEntries + j]);
   }
 }
 

@@ -1648,6 +1648,7 @@ pt_status pt_batch_prepare_async(uint32_t n_problems, const pt_problem *problems
   a.n_phases = static_cast<uint32_t>(bp.phase_items.size());
   const uint64_t lds_bytes = static_cast<uint64_t>(device_info().max_lds_block) - 2048;
   a.lds_filter_words = static_cast<uint32_t>((lds_bytes - probe_queue_bytes()) / 4) & ~1u;
+  a.lds_bytes = static_cast<uint32_t>(lds_bytes);
   int rate_khz = 0;
   if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device_info().device) != hipSuccess ||
       rate_khz <= 0)

@@ -88,7 +88,7 @@ struct ProbeOpts {
   bool keep_order = false;  // test the filters in the given order (no selectivity ordering)
 };
 
-constexpr uint32_t kTileWords = 16384;   // 64 KB of filter per partitioned-build tile
+constexpr uint32_t kTileWords = 32768;   // 128 KB of filter per partitioned-build tile (fits LDS)
 constexpr uint32_t kMaxBuckets = 16384;  // (filter, tile) buckets of one partitioned build
 
 // Device buffers a build may use. copies: private per-workgroup LDS copies
@@ -304,7 +304,7 @@ struct BatchArgs {
   uint32_t n_items;
   uint32_t n_phases;
   uint32_t lds_filter_words;  // probe: LDS words for staged filters
-  uint32_t pad;
+  uint32_t lds_bytes;         // dynamic LDS of a workgroup
   uint64_t spin_limit;        // longest wait for a phase, in wall-clock ticks
   uint64_t *timeline;         // NULL, or the start and end (wall clock) of every item
 };
