@@ -273,16 +273,31 @@ __device__ __forceinline__ void shared_probe_body(const BatchArgs &a, const BSha
   const uint32_t n_cols = sh.n_cols;
   for (uint64_t w0 = global_wave(vg) * U; in && w0 < n_words; w0 += wave_count(vg) * U) {
     // every column's keys of the group, loaded and hashed once
+    // (a column's U loads are issued before any is used: a use inside the
+    // width branch would wait for each load in turn)
     uint32_t h1[kMaxSharedCols][U], h2[kMaxSharedCols][U];
 #pragma unroll
     for (int c = 0; c < kMaxSharedCols; c++) {
+      uint64_t x[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) h1[c][u] = h2[c][u] = 0;
+      if (c >= static_cast<int>(n_cols)) continue;
+      const bool key64 = sh.key64[c];
+      if (key64) {
+#pragma unroll
+        for (int u = 0; u < U; u++)
+          x[u] = static_cast<const uint64_t *>(sh.cols[c])[min(w0 * 64 + u * 64 + lane, n_rows - 1)];
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; u++)
+          x[u] = static_cast<const uint32_t *>(sh.cols[c])[min(w0 * 64 + u * 64 + lane, n_rows - 1)];
+      }
 #pragma unroll
       for (int u = 0; u < U; u++) {
-        h1[c][u] = h2[c][u] = 0;
-        if (c < static_cast<int>(n_cols)) {
-          const uint64_t row = min(w0 * 64 + u * 64 + lane, n_rows - 1);
-          hash_key(load_key(sh.cols[c], sh.key64[c], row), h1[c][u], h2[c][u]);
-        }
+        if (key64)
+          hash_key(x[u], h1[c][u], h2[c][u]);
+        else
+          hash_key32(static_cast<uint32_t>(x[u]), h1[c][u], h2[c][u]);
       }
     }
     // every member's bitmap words of the group in one load: lane 4 m + u

@@ -11,8 +11,9 @@ namespace pt {
 //
 // Each wave takes seg_words (1..64) consecutive words, builds word j with the
 // ballot of step j, keeps it in lane j, and stores the segment with one
-// coalesced store. Eight words are evaluated per step so their loads
-// overlap.
+// coalesced store. T words are evaluated per step, their loads in flight
+// together (8 keep 32 KB in flight per CU with one 1024-thread workgroup
+// there, as in the batch kernel, whose registers do not allow 16).
 
 __device__ __forceinline__ bool pred_holds(uint32_t op, int64_t v, int64_t lo, int64_t hi) {
   switch (op) {
@@ -26,9 +27,10 @@ __device__ __forceinline__ bool pred_holds(uint32_t op, int64_t v, int64_t lo, i
   }
 }
 
+template <int T = 8>
 __device__ __forceinline__ void local_body(const PredSet &ps, uint64_t n_rows, uint64_t *__restrict__ bitmap,
                                            unsigned long long *count, uint32_t seg_words, const VGrid &vg) {
-  constexpr int T = 8;
+  static_assert(T >= 1 && T <= 32, "the keep mask is one 32-bit word");
   __shared__ unsigned long long s_cnt;
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
@@ -40,26 +42,44 @@ __device__ __forceinline__ void local_body(const PredSet &ps, uint64_t n_rows, u
     const uint32_t n_j = static_cast<uint32_t>(n_words - w_base < seg_words ? n_words - w_base : seg_words);
     uint64_t mine = 0;
     for (uint32_t j0 = 0; j0 < n_j; j0 += T) {
-      bool keep[T];
-      uint64_t r[T];
+      // bit t of keep: row (w_base + j0 + t) * 64 + lane is still selected
+      uint32_t keep = 0;
 #pragma unroll
       for (int t = 0; t < T; t++) {
         const uint64_t row = (w_base + j0 + t) * 64 + lane;
-        keep[t] = j0 + t < n_j && row < n_rows;
-        r[t] = row < n_rows ? row : n_rows - 1;
-        if (ps.and_into && j0 + t < n_j) keep[t] = keep[t] && ((uniform64(bitmap[w_base + j0 + t]) >> lane) & 1);
+        keep |= static_cast<uint32_t>(j0 + t < n_j && row < n_rows) << t;
+      }
+      if (ps.and_into) {
+        uint64_t old[T];
+#pragma unroll
+        for (int t = 0; t < T; t++) old[t] = bitmap[w_base + min(j0 + t, n_j - 1)];
+#pragma unroll
+        for (int t = 0; t < T; t++) keep &= ~(static_cast<uint32_t>(((old[t] >> lane) & 1) == 0) << t);
       }
       for (uint32_t i = 0; i < ps.n; i++) {
         const PredRef &p = ps.p[i];
+        // the width test stays outside the unrolled loads: inside, each
+        // 4-byte load would be waited for before the next one is issued
+        int64_t v[T];
+        if (p.col64) {
 #pragma unroll
-        for (int t = 0; t < T; t++) {
-          const int64_t v = static_cast<int64_t>(load_key(p.col, p.col64, r[t]));
-          keep[t] = keep[t] && pred_holds(p.op, v, p.lo, p.hi);
+          for (int t = 0; t < T; t++) {
+            const uint64_t row = (w_base + j0 + t) * 64 + lane;
+            v[t] = static_cast<const int64_t *>(p.col)[row < n_rows ? row : n_rows - 1];
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < T; t++) {
+            const uint64_t row = (w_base + j0 + t) * 64 + lane;
+            v[t] = static_cast<const int32_t *>(p.col)[row < n_rows ? row : n_rows - 1];
+          }
         }
+#pragma unroll
+        for (int t = 0; t < T; t++) keep &= ~(static_cast<uint32_t>(!pred_holds(p.op, v[t], p.lo, p.hi)) << t);
       }
 #pragma unroll
       for (int t = 0; t < T; t++) {
-        const uint64_t m = __ballot(keep[t]);
+        const uint64_t m = __ballot((keep >> t) & 1);
         if (lane == j0 + t) mine = m;
       }
     }

@@ -59,17 +59,18 @@ __device__ __forceinline__ bool slot_has_any(const Slot &s, const uint32_t *lds_
 // 64-bit failure mask per word of the group.
 constexpr int probe_slice_words() { return kWave * 3 + 2 * kGroupWords; }
 
-// Key of row `row` of a column as low and high halves of its int64 value.
+// Key of row `row` of a column: the low and high halves of an int64 key, or
+// an int32 key in lo (hi is then left as it is: every use of an int32 key
+// reads lo alone). Nothing here uses the loaded value, so several gathers
+// are in flight together even though the width is only known at run time.
 __device__ __forceinline__ void gather_key(const void *col, uint32_t key64, uint64_t row, uint32_t &lo,
                                            uint32_t &hi) {
   if (key64) {
-    const uint64_t x = static_cast<const uint64_t *>(col)[row];
-    lo = static_cast<uint32_t>(x);
-    hi = static_cast<uint32_t>(x >> 32);
+    const uint2 x = static_cast<const uint2 *>(col)[row];
+    lo = x.x;
+    hi = x.y;
   } else {
-    const int32_t x = static_cast<const int32_t *>(col)[row];
-    lo = static_cast<uint32_t>(x);
-    hi = static_cast<uint32_t>(x >> 31);
+    lo = static_cast<const uint32_t *>(col)[row];
   }
 }
 

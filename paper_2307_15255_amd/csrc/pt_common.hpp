@@ -65,23 +65,6 @@ __device__ __forceinline__ uint64_t wave_count(const VGrid &g) {
   return static_cast<uint64_t>(g.blocks) * blockDim.x / kWave;
 }
 
-// The task of this workgroup. `first` holds the n + 1 first workgroups of
-// the tasks (first[t] <= blockIdx.x < first[t + 1]) followed by the task of
-// every workgroup of the grid, so the lookup is one load and one pair.
-__device__ __forceinline__ uint32_t task_of(const uint32_t *first, uint32_t n, VGrid &g) {
-  const uint32_t t = __builtin_amdgcn_readfirstlane(first[n + 1 + blockIdx.x]);
-  const uint32_t a = __builtin_amdgcn_readfirstlane(first[t]);
-  const uint32_t b = __builtin_amdgcn_readfirstlane(first[t + 1]);
-  g = VGrid{blockIdx.x - a, b - a};
-  return t;
-}
-
-__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
-  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
-  return (static_cast<uint64_t>(hi) << 32) | lo;
-}
-
 __device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
