@@ -59,7 +59,7 @@ class _Problem(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("block_bits", C.c_uint32), ("k", C.c_uint32), ("bits_per_key", C.c_uint32),
                 ("kind", C.c_uint32), ("n_passes", C.c_uint32), ("variant", C.c_uint32),
-                ("threads", C.c_uint32), ("pad", C.c_uint32)]
+                ("threads", C.c_uint32), ("prune", C.c_uint32)]
 
 
 class _Dump(C.Structure):
@@ -292,14 +292,16 @@ def _problem(problem, keep: list) -> _Problem:
 
 def transfer(problem, block_bits: int = 512, k: int = 3, bits_per_key: int = 10,
              kind: int = BLOOM, n_passes: int = 2, variant: int = 0,
-             dump_filters: bool = False, threads: int = 1) -> TransferResult:
+             dump_filters: bool = False, threads: int = 1, prune: bool = False) -> TransferResult:
     """Run the transfer phase on a `workloads.Problem` (threads > 1: the row
-    scans split over that many threads, with the same results)."""
+    scans split over that many threads, with the same results; prune: a
+    table that still holds every row sends no filter, Sec. 3.2 "Transfer
+    Path Pruning")."""
     L = lib()
     n_t, n_e = problem.n_tables, len(problem.edges)
     keep: list = []
     prob = _problem(problem, keep)
-    par = _Params(block_bits, k, bits_per_key, kind, n_passes, variant, threads, 0)
+    par = _Params(block_bits, k, bits_per_key, kind, n_passes, variant, threads, int(prune))
 
     res = TransferResult()
     res.bitmaps = [np.zeros(max(1, bitmap_words(problem.n_rows(t))), np.uint64) for t in range(n_t)]

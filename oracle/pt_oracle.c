@@ -191,9 +191,11 @@ int ptor_compact(const uint64_t *bitmap, uint64_t n_rows, uint32_t *idx, uint64_
 /* ------------------------------------------------------------------ */
 
 /* A transferred filter: a Bloom filter, or (precise filter, Sec. 3.2
- * "Filter Type") the sorted set of distinct keys. */
+ * "Filter Type") the sorted set of distinct keys; `absent` when pruning
+ * left it unbuilt (it then lets every key through). */
 typedef struct {
   uint32_t kind;
+  uint32_t absent;
   uint64_t nb;
   uint32_t *words;
   int64_t *keys;
@@ -262,6 +264,7 @@ static int filter_build(filter_t *f, const ptor_params *pa, const ptor_column *c
 }
 
 static int filter_contains(const filter_t *f, const ptor_params *pa, int64_t key) {
+  if (f->absent) return 1;
   if (f->kind == PTOR_BLOOM) return ptor_bloom_contains(f->words, f->nb, pa->block_bits, pa->k, key);
   return bsearch(&key, f->keys, f->n_keys, sizeof(int64_t), cmp_i64) != NULL;
 }
@@ -335,8 +338,8 @@ static void dump_filter(const ptor_dump *d, const ptor_problem *p, uint32_t pass
   if (!d) return;
   uint64_t slot = (uint64_t)pass * p->n_edges + e;
   if (d->edge_src) d->edge_src[slot] = builder;
-  if (d->filter_nb) d->filter_nb[slot] = (f->kind == PTOR_BLOOM) ? f->nb : 0;
-  if (d->filter_words && d->filter_words[slot] && f->kind == PTOR_BLOOM) {
+  if (d->filter_nb) d->filter_nb[slot] = (f->kind == PTOR_BLOOM && !f->absent) ? f->nb : 0;
+  if (d->filter_words && d->filter_words[slot] && f->kind == PTOR_BLOOM && !f->absent) {
     uint64_t n = f->nb * (pa->block_bits / 32);
     uint64_t cap = d->filter_cap ? d->filter_cap[slot] : n;
     memcpy(d->filter_words[slot], f->words, (n < cap ? n : cap) * sizeof(uint32_t));
@@ -382,8 +385,19 @@ static int run_pass(const ptor_problem *p, const ptor_params *pa, uint32_t pass,
         }
       }
     }
+    /* Transfer path pruning: a table that has lost no row yet would send
+     * filters holding every key of its columns; they are not built, and
+     * the probes above let every key through them. */
+    const int unreduced = pa->prune && bitmap_popcount(bitmaps[v], t->n_rows) == t->n_rows;
     for (uint32_t e = 0; e < m; e++) {
       if (src[e] != v || !edge_carries(&p->edges[e], src[e], dst[e])) continue;
+      if (unreduced) {
+        filter_free(&filters[e]);
+        filters[e].kind = pa->kind;
+        filters[e].absent = 1;
+        dump_filter(dump, p, pass, e, &filters[e], pa, v);
+        continue;
+      }
       int rc = filter_build(&filters[e], pa, edge_column(p, e, v), t->n_rows, bitmaps[v]);
       if (rc != PTOR_OK) return rc;
       dump_filter(dump, p, pass, e, &filters[e], pa, v);
@@ -413,7 +427,7 @@ int ptor_transfer(const ptor_problem *p, const ptor_params *pa, uint64_t *const 
   if (!problem_valid(p)) return PTOR_EINVAL;
   if (pa->kind == PTOR_BLOOM && !params_valid(pa->block_bits, pa->k, pa->bits_per_key))
     return PTOR_EINVAL;
-  if (pa->kind > PTOR_EXACT || pa->n_passes < 1 || pa->n_passes > 2) return PTOR_EINVAL;
+  if (pa->kind > PTOR_EXACT || pa->n_passes < 1 || pa->n_passes > 2 || pa->prune > 1) return PTOR_EINVAL;
 
   uint32_t n = p->n_tables, m = p->n_edges;
   uint32_t *src = (uint32_t *)malloc((m ? m : 1) * sizeof(uint32_t));

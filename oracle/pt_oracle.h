@@ -116,13 +116,18 @@ typedef struct {
                             each takes whole 64-row bitmap words, Bloom builds
                             fill private copies that are OR-ed together, so
                             the result does not depend on the count */
-  uint32_t pad;
+  uint32_t prune;        /* 1: transfer path pruning (Sec. 3.2 leaves the
+                            rule open; this is the reading used here): a
+                            table whose selection still holds every one of
+                            its rows builds no filter, and the tables it
+                            would have sent one to are not probed with it */
 } ptor_params;
 
 /* Optional outputs for inspection. Any pointer may be NULL.
  * filter_words[p * n_edges + e] receives the words of the filter carried by
  * edge e in pass p (p = 0 forward, 1 backward), at most filter_cap[...]
- * words; filter_nb[...] receives its block count (0 in exact mode).
+ * words; filter_nb[...] receives its block count (0 in exact mode, and 0
+ * for a filter that pruning left unbuilt).
  * fwd_bitmaps[t] receives table t's bitmap after the forward pass and
  * fwd_counts[t] its popcount. edge_src[p * n_edges + e] receives the table
  * that built the filter of edge e in pass p. */

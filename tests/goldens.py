@@ -17,5 +17,8 @@ def load(name: str) -> tuple[Problem, dict]:
     names = list(spec["tables"].keys())
     columns = [{c: np.array(v, np.int32) for c, v in spec["tables"][t].items()} for t in names]
     edges = [(names.index(u), uc, names.index(v), vc) for u, uc, v, vc in spec["edges"]]
-    prob = Problem(names, columns, edges, [], orient=spec.get("orient"), label=name)
+    preds = []
+    for t, c, op, lo, hi in spec.get("preds", []):
+        preds.append((names.index(t), c, op, lo, hi))
+    prob = Problem(names, columns, edges, preds, orient=spec.get("orient"), label=name)
     return prob, spec

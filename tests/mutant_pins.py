@@ -13,6 +13,7 @@ import oracle  # noqa: E402
 import test_oracle_filter as F  # noqa: E402
 import test_oracle_join as J  # noqa: E402
 import test_oracle_outer as OU  # noqa: E402
+import test_oracle_prune as PR  # noqa: E402
 import test_oracle_threads as TH  # noqa: E402
 import test_oracle_transfer as T  # noqa: E402
 
@@ -38,6 +39,7 @@ def checks():
     yield lambda: J.test_join_edge_cases(None)
     yield lambda: TH.test_threads_tiny(None, "tree")
     yield lambda: OU.test_outer_tree_query_unchanged(None, "tree")
+    yield lambda: PR.test_prune_worked_example(None, oracle.EXACT, 3, 10)
     yield lambda: OU.test_full_outer_blocks_every_transfer(None)
     yield lambda: OU.test_preserved_side_keeps_its_rows(None, 1, 0)
 
