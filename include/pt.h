@@ -218,6 +218,21 @@ typedef struct pt_params {
  * this flag with PT_EUNSUPPORTED. */
 #define PT_FLAG_EXACT 4u
 
+/* Transfer path pruning (Sec. 3.2, "Transfer Path Pruning": the paper asks
+ * for skipping transfers that cannot make a filter more selective and leaves
+ * the rule open). The rule implemented: a non-empty table whose selection
+ * still holds every one of its rows sends no filter (such a filter can only
+ * remove rows whose key appears nowhere in the whole table), and the tables
+ * it would have sent one to are not probed with it. The decision is taken from the
+ * exact counts: on the host when the table has no predicate and has not
+ * been probed yet (nothing is launched for its filters), otherwise on the
+ * device by the build's size step. Every row that joins is still kept, so
+ * the join result is the same; with exact filters the reduced tables hold a
+ * superset of the rows the full schedule keeps. A pruned filter is left
+ * with a block count of zero. Works with PT_FLAG_EXACT and in batches (a
+ * problem with this flag takes no part in shared scans). */
+#define PT_FLAG_PRUNE 8u
+
 /* A Bloom filter in device memory. `words` holds cap_words uint32 words; the
  * filter in use is its first nb * B/32 words, where nb is the uint64 at
  * device address `d_nb` (written by pt_bloom_build). `d_status` is NULL or
@@ -376,7 +391,8 @@ pt_status pt_join(const pt_graph *graph, const pt_table *tables, uint32_t root,
 
 /* Where pt_transfer left the filter that `edge` carried in `pass` (1 forward,
  * 2 backward) inside d_ws, and which table built it (*builder); PT_EINVAL
- * when an outer join kept the edge from carrying one in that pass. */
+ * when an outer join kept the edge from carrying one in that pass. With
+ * PT_FLAG_PRUNE, a filter that pruning left unbuilt has *d_nb == 0. */
 pt_status pt_transfer_filter(const pt_graph *graph, const pt_table *tables,
                              const pt_params *params, void *d_ws, uint32_t pass, uint32_t edge,
                              pt_bloom *out, uint32_t *builder);
@@ -384,12 +400,13 @@ pt_status pt_transfer_filter(const pt_graph *graph, const pt_table *tables,
 /* ---------------------------------------------------------------- batches
  *
  * Many independent transfer problems run together (the paper evaluates one
- * query at a time; batching is an addition). Every step of every problem
- * is grouped with the same step of the others: one launch per step and
- * schedule level covers all problems (tables of a level depend only on
- * lower levels, so the bits equal those of pt_transfer on each problem), and
- * the whole sequence is captured once into a HIP graph that each run
- * launches with a single call. */
+ * query at a time and names parallel execution as future work, Sec. 5).
+ * Every step of every problem becomes a task of work items, ordered by its
+ * depth in the problems' dependency graphs; one persistent kernel launch
+ * takes the items from a device queue and synchronises phase by phase, so
+ * the bits equal those of pt_transfer on each problem. A run (a zeroing
+ * kernel and the batch kernel) is captured once into a HIP graph that each
+ * later run launches with a single call. */
 
 /* One problem of a batch: the arguments of pt_transfer. */
 typedef struct pt_problem {

@@ -385,10 +385,13 @@ static int run_pass(const ptor_problem *p, const ptor_params *pa, uint32_t pass,
         }
       }
     }
-    /* Transfer path pruning: a table that has lost no row yet would send
-     * filters holding every key of its columns; they are not built, and
-     * the probes above let every key through them. */
-    const int unreduced = pa->prune && bitmap_popcount(bitmaps[v], t->n_rows) == t->n_rows;
+    /* Transfer path pruning: a non-empty table that has lost no row yet
+     * would send filters holding every key of its columns; they are not
+     * built, and the probes above let every key through them. (An empty
+     * table's filter holds no key and removes every row it reaches, so it
+     * is always sent.) */
+    const int unreduced =
+        pa->prune && t->n_rows > 0 && bitmap_popcount(bitmaps[v], t->n_rows) == t->n_rows;
     for (uint32_t e = 0; e < m; e++) {
       if (src[e] != v || !edge_carries(&p->edges[e], src[e], dst[e])) continue;
       if (unreduced) {

@@ -118,9 +118,10 @@ typedef struct {
                             the result does not depend on the count */
   uint32_t prune;        /* 1: transfer path pruning (Sec. 3.2 leaves the
                             rule open; this is the reading used here): a
-                            table whose selection still holds every one of
-                            its rows builds no filter, and the tables it
-                            would have sent one to are not probed with it */
+                            non-empty table whose selection still holds
+                            every one of its rows builds no filter, and the
+                            tables it would have sent one to are not probed
+                            with it */
 } ptor_params;
 
 /* Optional outputs for inspection. Any pointer may be NULL.

@@ -374,9 +374,32 @@ __device__ __forceinline__ void shared_probe_body(const BatchArgs &a, const BSha
   }
 }
 
+// Transfer path pruning: the (non-empty) builder of b still holds every row, so none
+// of its filters is built; the step that records the block counts (the
+// reduction, or the fill of a partitioned build) records zero, which the
+// probes of the receivers read as "no filter".
+__device__ __forceinline__ bool build_item_pruned(const BBuild &b, uint32_t kind, const VGrid &vg) {
+  if (!b.fs.prune || b.n_rows == 0 || load_shared_u64(b.count) != b.n_rows) return false;
+  if ((kind == kBReduce || kind == kBFill) && vg.block == 0 && threadIdx.x < b.fs.n) *b.fs.f[threadIdx.x].nb = 0;
+  return true;
+}
+
 template <int B, int K>
 __device__ __forceinline__ void run_item(const BatchArgs &a, const BTask &task, const VGrid &vg, uint32_t *lds) {
   __shared__ uint32_t s_off[kMaxFilters + 1];
+  switch (task.kind) {
+    case kBBuild:
+    case kBReduce:
+    case kBZero:
+    case kBCount:
+    case kBScan:
+    case kBScatter:
+    case kBFill:
+      if (build_item_pruned(a.builds[task.arg], task.kind, vg)) return;
+      break;
+    default:
+      break;
+  }
   switch (task.kind) {
     case kBLocal: {
       const BLocal &l = a.locals[task.arg];

@@ -27,6 +27,7 @@ template <int B, int K>
 __global__ void __launch_bounds__(kThreads)
     k_build(FilterSet fs, AppendSet app, uint32_t k, uint32_t lg_rt, uint64_t n_rows,
             const uint64_t *__restrict__ bitmap, uint32_t seg_words, uint32_t *status) {
+  if (build_pruned(fs)) return;
   const uint32_t lg = block_log2<B>(lg_rt);
   for (uint32_t i = 0; i < fs.n; i++) {
     const FilterRef &f = fs.f[i];
@@ -51,6 +52,7 @@ __global__ void __launch_bounds__(kWideThreads)
                 const uint64_t *__restrict__ bitmap, uint32_t seg_words, uint32_t *__restrict__ partials,
                 uint32_t lds_words, uint32_t *status) {
   extern __shared__ __align__(16) uint32_t lds[];
+  if (build_pruned(fs)) return;
   const uint32_t lg = block_log2<B>(lg_rt);
   const uint32_t total = lds_total(fs, lg, lds_words);
   if (total == 0) {
@@ -89,7 +91,7 @@ __global__ void __launch_bounds__(kWideThreads)
                    uint32_t lds_words) {
   constexpr int kGroups = kWideThreads / kWave;
   __shared__ uint32_t s_or[kGroups][kWave];
-  if (lds_total(fs, lg, lds_words) == 0) return;
+  if (build_pruned(fs) || lds_total(fs, lg, lds_words) == 0) return;
   const uint32_t i = blockIdx.y;
   uint32_t off = 0;
   for (uint32_t j = 0; j < i; j++) off += filter_blocks(fs.f[j], lg, nullptr) << (lg - 5);

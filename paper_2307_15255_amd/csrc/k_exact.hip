@@ -33,9 +33,16 @@ __device__ __forceinline__ bool set_has(const SetRef &f, uint32_t lg, unsigned l
 }
 
 // Sizes the set from the builder's selected rows (twice that many slots,
-// rounded up to a power of two, within [64, 2^lg_cap]) and clears it.
-__global__ void __launch_bounds__(kThreads) k_set_clear(SetRef f, const uint64_t *count, uint64_t n_rows) {
+// rounded up to a power of two, within [64, 2^lg_cap]) and clears it. With
+// prune, a non-empty builder that still holds every row leaves lg = 0: no
+// set.
+__global__ void __launch_bounds__(kThreads)
+    k_set_clear(SetRef f, const uint64_t *count, uint64_t n_rows, uint32_t prune) {
   uint64_t n = count ? *count : n_rows;
+  if (prune && count && n_rows > 0 && n == n_rows) {
+    if (thread_index() == 0) *f.lg = 0;
+    return;
+  }
   if (n > n_rows) n = n_rows;
   uint32_t lg = 6;
   while (lg < f.lg_cap && (1ull << lg) < 2 * n) lg++;
@@ -51,6 +58,7 @@ __global__ void __launch_bounds__(kThreads) k_set_clear(SetRef f, const uint64_t
 // in use are at least twice the selected rows, so a free slot is reached.
 __global__ void __launch_bounds__(kThreads) k_set_build(SetRef f, uint64_t n_rows, const uint64_t *bitmap) {
   const uint32_t lg = static_cast<uint32_t>(*f.lg);
+  if (lg == 0) return;  // pruned
   const uint64_t mask = (1ull << lg) - 1;
   const uint64_t n_words = (n_rows + 63) / 64;
   const uint32_t lane = lane_id();
@@ -91,7 +99,8 @@ __global__ void __launch_bounds__(kThreads)
     bool keep = (word >> lane) & 1;
 #pragma unroll
     for (int j = 0; j < kMaxProbe; j++) {
-      if (j < static_cast<int>(sp.n) && keep) keep = set_has(sp.f[j], lg[j], load_key(sp.f[j].col, sp.f[j].key64, r));
+      if (j < static_cast<int>(sp.n) && keep && lg[j] != 0)  // lg 0: a pruned set
+        keep = set_has(sp.f[j], lg[j], load_key(sp.f[j].col, sp.f[j].key64, r));
     }
     const uint64_t m = __ballot(keep);
     if (lane == 0) {
@@ -107,9 +116,9 @@ __global__ void __launch_bounds__(kThreads)
 }  // namespace
 
 hipError_t launch_set_build(const SetRef &f, uint64_t n_rows, const uint64_t *bitmap, const uint64_t *count,
-                            hipStream_t s) {
+                            bool prune, hipStream_t s) {
   hipLaunchKernelGGL(k_set_clear, dim3(grid_for((1ull << f.lg_cap) / 64, kThreads, 8)), dim3(kThreads), 0, s, f,
-                     count, n_rows);
+                     count, n_rows, prune ? 1u : 0u);
   if (n_rows)
     hipLaunchKernelGGL(k_set_build, dim3(grid_for((n_rows + 63) / 64, kThreads, 8)), dim3(kThreads), 0, s, f,
                        n_rows, bitmap);

@@ -40,13 +40,17 @@ __global__ void __launch_bounds__(kWideThreads)
 // Filter i (blockIdx.y) gets nb = max(1, ceil(count * bits_per_key / B))
 // blocks, read from the device counter so the launch sequence never waits
 // for the host. Its first nb blocks are zeroed unless the partitioned build
-// (which writes every block) will run.
+// (which writes every block) will run. A pruned build set gets nb = 0.
 
 __global__ void __launch_bounds__(kThreads)
     k_size_zero(FilterSet fs, uint32_t lg, uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
                 uint64_t entries_cap, uint32_t *status) {
   const FilterRef &f = fs.f[blockIdx.y];
   const uint64_t W = 1u << (lg - 5);
+  if (fs.prune && count && n_rows > 0 && *count == n_rows) {  // pruned: no filter
+    if (blockIdx.x == 0 && threadIdx.x == 0) *f.nb = 0;
+    return;
+  }
   const uint64_t nb = blocks_needed(count ? *count : n_rows, 1u << lg, bits_per_key, f.cap_words / W,
                                     blockIdx.x == 0 && threadIdx.x == 0 ? status : nullptr);
   if (blockIdx.x == 0 && threadIdx.x == 0) *f.nb = nb;

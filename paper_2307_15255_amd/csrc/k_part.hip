@@ -14,6 +14,7 @@ __global__ void __launch_bounds__(kWideThreads)
     k_part_count(FilterSet fs, AppendSet app, uint32_t lg_rt, uint32_t bits_per_key, const uint64_t *count,
                  uint64_t n_rows, const uint64_t *__restrict__ bitmap, uint32_t seg_words, uint64_t entries_cap,
                  uint32_t *__restrict__ hist) {
+  if (build_pruned(fs)) return;
   part_count_body<true>(fs, app, block_log2<B>(lg_rt), bits_per_key, count, n_rows, bitmap, seg_words, entries_cap,
                         hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, false, kTargetBuckets,
                         whole_grid());
@@ -26,6 +27,7 @@ __global__ void __launch_bounds__(kWideThreads)
                        uint64_t entries_cap, uint32_t *__restrict__ hist, uint32_t n_groups,
                        uint64_t *__restrict__ totals) {
   __shared__ uint64_t s[kWideThreads];
+  if (build_pruned(fs)) return;
   const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false);
   if (!geo.ok) return;
   for (uint32_t b = blockIdx.x; b < geo.buckets; b += gridDim.x) {
@@ -43,6 +45,7 @@ __global__ void __launch_bounds__(kWideThreads)
     k_part_scan_buckets(FilterSet fs, uint32_t lg, uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
                         uint64_t entries_cap, const uint64_t *__restrict__ totals, uint64_t *__restrict__ starts) {
   __shared__ uint64_t s[kWideThreads];
+  if (build_pruned(fs)) return;
   const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false);
   if (!geo.ok) return;
   uint64_t carry = 0;
@@ -63,6 +66,7 @@ __global__ void __launch_bounds__(kWideThreads)
                    const uint64_t *count, uint64_t n_rows, const uint64_t *__restrict__ bitmap, uint32_t seg_words,
                    uint64_t entries_cap, const uint32_t *__restrict__ hist, const uint64_t *__restrict__ starts,
                    uint32_t *__restrict__ entries, uint32_t *status, uint64_t lds_bytes) {
+  if (build_pruned(fs)) return;
   part_scatter_body<true, K>(fs, app, k, block_log2<B>(lg_rt), bits_per_key, count, n_rows, bitmap, seg_words,
                              entries_cap, hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, starts, entries,
                              status, false, kTargetBuckets, whole_grid(), lds_bytes);
@@ -73,6 +77,7 @@ __global__ void __launch_bounds__(kWideThreads)
     k_part_fill(FilterSet fs, uint32_t k, uint32_t lg_rt, uint32_t bits_per_key, const uint64_t *count,
                 uint64_t n_rows, uint64_t entries_cap, const uint64_t *__restrict__ starts,
                 const uint32_t *__restrict__ entries) {
+  if (build_pruned(fs)) return;
   part_fill_body<K>(fs, k, block_log2<B>(lg_rt), bits_per_key, count, n_rows, entries_cap, starts, entries,
                     blockIdx.x, gridDim.x, false, kTargetBuckets);
 }

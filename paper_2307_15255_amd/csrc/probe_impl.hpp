@@ -342,9 +342,10 @@ __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint
 
   __shared__ uint64_t s_sel[kMaxProbe];
   __shared__ uint64_t s_nb_raw[kMaxProbe];
-  const uint32_t n_f = fs.n;
+  __shared__ uint32_t s_nf;
+  const uint32_t n_in = fs.n;
   // Thread i reads filter i's builder count and block count (in parallel).
-  if (threadIdx.x < n_f) {
+  if (threadIdx.x < n_in) {
     const FilterRef &f = fs.f[threadIdx.x];
     s_sel[threadIdx.x] = (f.sel && f.rows) ? *f.sel : 1;
     s_nb_raw[threadIdx.x] = *f.nb;
@@ -353,16 +354,21 @@ __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint
   if (threadIdx.x == 0) {
     uint32_t ord[kMaxProbe];
     uint64_t sel[kMaxProbe], rows[kMaxProbe];
+    uint32_t n_f = 0;
 #pragma unroll
     for (int i = 0; i < kMaxProbe; i++) {
-      ord[i] = i;
+      ord[i] = 0;
       sel[i] = 1;
       rows[i] = 1;
-      if (i < static_cast<int>(n_f) && fs.f[i].sel && fs.f[i].rows) {
+      if (i < static_cast<int>(n_in) && fs.f[i].sel && fs.f[i].rows) {
         sel[i] = s_sel[i];
         rows[i] = fs.f[i].rows;
       }
     }
+    // A pruned filter (its builder kept every row, so its size step left a
+    // block count of zero) lets every key through: it is not tested.
+    for (uint32_t i = 0; i < n_in; i++)
+      if (!(fs.prune && s_nb_raw[i] == 0)) ord[n_f++] = i;
     // stable insertion sort by sel / rows (the given order with keep_order)
     for (uint32_t a = 1; a < n_f && !keep_order; a++) {
       for (uint32_t b = a; b > 0; b--) {
@@ -391,9 +397,33 @@ __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint
         s_off[j] = kNotStaged;
       }
     }
+    s_nf = n_f;
     s_cnt = 0;
   }
   __syncthreads();
+  const uint32_t n_f = __builtin_amdgcn_readfirstlane(s_nf);
+  if (n_f == 0) {
+    // Every filter was pruned: the rows stay as they are.
+    const uint64_t n_words = (n_rows + 63) / 64;
+    const uint32_t lane = lane_id();
+    int64_t cnt = 0;
+    for (uint64_t w0 = global_wave(vg) * kWave; w0 < n_words; w0 += wave_count(vg) * kWave) {
+      const uint64_t w = w0 + lane;
+      uint64_t m = 0;
+      if (w < n_words) {
+        m = tail_mask(w, n_words, n_rows);
+        if (input_all)
+          bitmap[w] = m;
+        else
+          m &= bitmap[w];
+      }
+      cnt += static_cast<int64_t>(wave_sum(static_cast<uint64_t>(__popcll(m))));
+    }
+    // builds that would read appended keys walk the bitmap instead
+    if (APPEND && lane_id() == 0) app.counts[global_wave(vg)] = app.region_cap + 1;
+    block_count_add(cnt, &s_cnt, count);
+    return;
+  }
   for (uint32_t j = 0; j < n_f; j++) {
     if (s_off[j] == kNotStaged) continue;
     const uint32_t n = s_nb[j] * W;

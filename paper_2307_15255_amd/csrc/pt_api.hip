@@ -127,7 +127,7 @@ pt_status check_params(const pt_params *p) {
   if (p->k < 1 || p->k > 16) return fail(PT_EINVAL, "k %u outside [1, 16]", p->k);
   if (p->bits_per_key < 1 || p->bits_per_key > 64)
     return fail(PT_EINVAL, "bits_per_key %u outside [1, 64]", p->bits_per_key);
-  if ((p->flags & ~(PT_FLAG_NO_APPEND | PT_FLAG_SHARED_SCAN | PT_FLAG_EXACT)) != 0)
+  if ((p->flags & ~(PT_FLAG_NO_APPEND | PT_FLAG_SHARED_SCAN | PT_FLAG_EXACT | PT_FLAG_PRUNE)) != 0)
     return fail(PT_EINVAL, "params.flags: unknown bits 0x%x", p->flags);
   if (p->hash_version > 1)
     return fail(PT_EUNSUPPORTED, "hash_version %u (this library implements version 1)", p->hash_version);
@@ -578,10 +578,11 @@ static pt_status build_filters(uint32_t n_filters, const pt_column *keys, const 
                                uint64_t n_rows, const uint64_t *d_bitmap, const uint64_t *d_count,
                                const BuildScratch *scratch, const AppendSet *app,
                                const uint32_t *app_idx, uint32_t *status, hipStream_t s, uint32_t table,
-                               uint32_t pass) {
+                               uint32_t pass, bool prune = false) {
   const pt_params &p = filters[0].params;
   for (uint32_t done = 0; done < n_filters;) {
     FilterSet fs{};
+    fs.prune = prune ? 1u : 0u;
     uint64_t bytes = (n_rows + 63) / 64 * 8;
     for (; done < n_filters && fs.n < kMaxFilters; done++, fs.n++) {
       fs.f[fs.n] = make_ref(keys[done], filters[done]);
@@ -607,7 +608,7 @@ static pt_status probe_filters(uint32_t n_filters, const pt_column *keys, const 
                                const uint64_t *const *sel, const uint64_t *rows, uint64_t n_rows,
                                uint64_t *d_bitmap, uint64_t *d_count, bool input_all,
                                bool count_zeroed, AppendSet *app, uint64_t capacity, uint32_t *status,
-                               hipStream_t s, uint32_t table, uint32_t pass) {
+                               hipStream_t s, uint32_t table, uint32_t pass, bool prune = false) {
   const pt_params &p = filters[0].params;
   if (d_count && !count_zeroed) {
     pt_status st = check_hip(launch_zero_u64(d_count, 1, s), "zero count");
@@ -615,6 +616,7 @@ static pt_status probe_filters(uint32_t n_filters, const pt_column *keys, const 
   }
   for (uint32_t done = 0; done < n_filters;) {
     FilterSet fs{};
+    fs.prune = prune ? 1u : 0u;
     const bool first = done == 0;
     uint64_t bytes = ((input_all && first) ? 1 : 2) * ((n_rows + 63) / 64 * 8);
     for (; done < n_filters && fs.n < kMaxProbe; done++, fs.n++) {
@@ -654,10 +656,11 @@ static SetRef set_at(const Plan &pl, const pt_graph *g, const pt_table *tables, 
 // Probes every set table v receives in pass p, kMaxProbe per scan; the last
 // scan counts the rows left into *d_count (which holds zero).
 static pt_status probe_sets(const Plan &pl, const pt_graph *g, const pt_table *tables, char *ws, uint32_t p,
-                            uint32_t v, uint64_t *d_bitmap, uint64_t *d_count, bool input_all, hipStream_t s) {
+                            uint32_t v, uint64_t *d_bitmap, uint64_t *d_count, bool input_all,
+                            const std::vector<char> &skipped, hipStream_t s) {
   std::vector<uint32_t> in;
   for (uint32_t e = 0; e < pl.n_e; e++)
-    if (pl.receives(p, e, v)) in.push_back(e);
+    if (pl.receives(p, e, v) && !skipped[p * pl.n_e + e]) in.push_back(e);
   for (size_t c0 = 0; c0 < in.size(); c0 += kMaxProbe) {
     SetProbe sp{};
     uint64_t bytes = (c0 == 0 && input_all ? 1 : 2) * ((tables[v].n_rows + 63) / 64 * 8);
@@ -828,9 +831,10 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
   };
 
   {
-    // the status word and the counters (everything before off_counts is
-    // the workspace header)
-    const uint64_t words = (pl.off_counts + 3ull * pl.n_t * 8) / 8;
+    // the status word, the counters and the filters' block counts
+    // (everything before off_counts is the workspace header); a filter that
+    // pruning leaves unbuilt keeps a block count of zero
+    const uint64_t words = (pl.off_nb + 2ull * pl.n_e * 8) / 8;
     Timed tm("zero", 0, 0, 0, words * 8, s);
     st = check_hip(launch_zero_u64(reinterpret_cast<uint64_t *>(ws), words, s), "zero counters");
     if (st != PT_OK) return st;
@@ -890,13 +894,19 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
   std::vector<const uint64_t *> sel;
   std::vector<uint64_t> rows;
   std::vector<const uint64_t *> built_sel(2ull * pl.n_e, nullptr);  // builder count per filter
+  // Transfer path pruning (Sec. 3.2): a non-empty table that still holds
+  // every row sends no filter. When the host knows it (no predicate, no probe yet)
+  // nothing is launched for the filter and its receivers leave it out
+  // (skipped); otherwise the builds' size step decides on the device from
+  // the builder's count and the probes skip the filters it pruned.
+  const bool prune = (params->flags & PT_FLAG_PRUNE) != 0;
+  std::vector<char> skipped(2ull * pl.n_e, 0);
   // The appended keys waiting for their builds: table, pass, columns.
   AppendSet pending{};
   uint32_t pending_table = pl.n_t, pending_pass = 2;
   std::vector<uint32_t> pending_cols, app_idx;
   for (uint32_t p = 0; p < 2; p++) {
     const std::vector<uint32_t> &from = p == 0 ? pl.src : pl.dst;
-    const std::vector<uint32_t> &to = p == 0 ? pl.dst : pl.src;
     const std::vector<uint32_t> &seq = p == 0 ? pl.order : rev;
     for (uint32_t v : seq) {
       const pt_table &tb = tables[v];
@@ -906,7 +916,7 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
       sel.clear();
       rows.clear();
       for (uint32_t e = 0; e < pl.n_e; e++) {
-        if (!pl.receives(p, e, v)) continue;
+        if (!pl.receives(p, e, v) || skipped[p * pl.n_e + e]) continue;
         keys.push_back(tb.cols[col_at(graph, e, v)]);
         blooms.push_back(bloom_at(p * pl.n_e + e));
         sel.push_back(built_sel[p * pl.n_e + e]);
@@ -929,12 +939,12 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
           }
         }
         if (pl.exact)
-          st = probe_sets(pl, graph, tables, ws, p, v, d_bitmaps[v], cnt, all_rows[v] != 0, s);
+          st = probe_sets(pl, graph, tables, ws, p, v, d_bitmaps[v], cnt, all_rows[v] != 0, skipped, s);
         else
           st = probe_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), sel.data(),
                              rows.data(), tb.n_rows, d_bitmaps[v], cnt, all_rows[v] != 0,
                              /*count_zeroed=*/true, ap.cols.empty() ? nullptr : &app,
-                             append_capacity(tb.n_rows), status, s, v, p + 1);
+                             append_capacity(tb.n_rows), status, s, v, p + 1, prune);
         if (st != PT_OK) return st;
         if (app.n_cols > 0) {
           pending = app;
@@ -952,6 +962,10 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
       app_idx.clear();
       for (uint32_t e = 0; e < pl.n_e; e++) {
         if (!pl.sends(p, e, v)) continue;
+        if (prune && all_rows[v] && tb.n_rows > 0) {
+          skipped[p * pl.n_e + e] = 1;
+          continue;
+        }
         const uint32_t c = col_at(graph, e, v);
         keys.push_back(tb.cols[c]);
         blooms.push_back(bloom_at(p * pl.n_e + e));
@@ -963,11 +977,11 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
       if (!keys.empty() && pl.exact) {
         const bool all = all_rows[v] != 0;
         for (uint32_t e = 0; e < pl.n_e; e++) {
-          if (!pl.sends(p, e, v)) continue;
+          if (!pl.sends(p, e, v) || skipped[p * pl.n_e + e]) continue;
           Timed tm("build", v, p + 1, tb.n_rows, tb.n_rows * key_bytes(tb.cols[col_at(graph, e, v)]), s);
           st = check_hip(launch_set_build(set_at(pl, graph, tables, ws, p, e, v), tb.n_rows,
                                           all ? nullptr : d_bitmaps[v], all ? nullptr : counts + cur[v] * pl.n_t + v,
-                                          s),
+                                          prune, s),
                          "set build launch");
           if (st != PT_OK) return st;
         }
@@ -975,7 +989,7 @@ pt_status pt_transfer(const pt_graph *graph, const pt_table *tables, const pt_pr
         const bool all = all_rows[v] != 0;
         st = build_filters(static_cast<uint32_t>(keys.size()), keys.data(), blooms.data(), tb.n_rows,
                            all ? nullptr : d_bitmaps[v], all ? nullptr : counts + cur[v] * pl.n_t + v,
-                           &scratch, use_app ? &pending : nullptr, app_idx.data(), status, s, v, p + 1);
+                           &scratch, use_app ? &pending : nullptr, app_idx.data(), status, s, v, p + 1, prune);
         if (st != PT_OK) return st;
       }
       if (pending_table == v && pending_pass == p) pending_table = pl.n_t;
@@ -1359,6 +1373,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
           for (uint32_t c0 = 0; c0 < in.size(); c0 += kMaxProbe) {
             ProbeCand c{i, v, BProbe{}, {writer[i][v]}, n_words, 2 * n_words * 8};
             BProbe &pt = c.pt;
+            pt.fs.prune = (pr.params.flags & PT_FLAG_PRUNE) ? 1u : 0u;
             c.deps.insert(c.deps.end(), readers[i][v].begin(), readers[i][v].end());
             for (uint32_t j = c0; j < in.size() && pt.fs.n < static_cast<uint32_t>(kMaxProbe); j++) {
               const uint32_t e = in[j];
@@ -1381,7 +1396,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
             pt.lg = lg;
             // The only probe of a large table may join a shared scan.
             if (in.size() <= static_cast<size_t>(kMaxProbe) && n_rows >= kSharedMinRows &&
-                (pr.params.flags & PT_FLAG_SHARED_SCAN))
+                (pr.params.flags & PT_FLAG_SHARED_SCAN) && !(pr.params.flags & PT_FLAG_PRUNE))
               cands.push_back(std::move(c));
             else
               emit_probe(c);
@@ -1402,6 +1417,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
           const uint64_t n_rows = pr.tables[v].n_rows, n_words = (n_rows + 63) / 64;
           for (uint32_t c0 = 0; c0 < out.size(); c0 += kMaxFilters) {
             BBuild b{};
+            b.fs.prune = (pr.params.flags & PT_FLAG_PRUNE) ? 1u : 0u;
             for (uint32_t j = c0; j < out.size() && b.fs.n < static_cast<uint32_t>(kMaxFilters); j++)
               b.fs.f[b.fs.n++] = filter_ref(i, p, out[j], v);
             b.n_rows = n_rows;

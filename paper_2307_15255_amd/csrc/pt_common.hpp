@@ -91,6 +91,13 @@ __device__ __forceinline__ void raise_status(uint32_t *status, uint32_t bit) {
   if (status) atomicOr(status, bit);
 }
 
+// Whether a build set was pruned: its size step found the builder holding
+// every row and recorded a block count of zero (the set's filters share
+// their builder, so the first one tells).
+__device__ __forceinline__ bool build_pruned(const FilterSet &fs) {
+  return fs.prune && fs.n > 0 && *fs.f[0].nb == 0;
+}
+
 // A filter's block count as read from device memory, kept inside [1, cap]
 // so that no address computed from it leaves the filter's buffer. A count
 // above the capacity is reported as an overflow.

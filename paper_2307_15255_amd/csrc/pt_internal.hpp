@@ -35,7 +35,12 @@ struct FilterRef {
 
 struct FilterSet {
   uint32_t n;
-  uint32_t pad;
+  // Transfer path pruning: a build whose non-empty builder still holds
+  // every row (*count == n_rows) builds nothing and records a block count
+  // of zero;
+  // a probe skips every filter whose block count is zero. The filters of
+  // one build set share their builder.
+  uint32_t prune;
   FilterRef f[kMaxFilters];
 };
 
@@ -340,12 +345,15 @@ struct SetProbe {
   SetRef f[kMaxProbe];
 };
 // Sizes the set from *count (n_rows when NULL), clears it, and inserts the
-// keys of f.col's selected rows (bitmap NULL: every row).
+// keys of f.col's selected rows (bitmap NULL: every row). With prune, a
+// non-empty builder that still holds every row (*count == n_rows) builds
+// nothing and the set's *lg is 0 (a pruned set).
 hipError_t launch_set_build(const SetRef &f, uint64_t n_rows, const uint64_t *bitmap, const uint64_t *count,
-                            hipStream_t s);
+                            bool prune, hipStream_t s);
 // Clears the bitmap bit of every row whose key misses one of the sets
 // (input_all: the bitmap is not read, every row starts selected); adds the
-// rows left to *count (NULL: not counted).
+// rows left to *count (NULL: not counted). A pruned set (*lg == 0) lets
+// every key through.
 hipError_t launch_set_probe(const SetProbe &sp, uint64_t n_rows, uint64_t *bitmap, uint64_t *count, bool input_all,
                             hipStream_t s);
 

@@ -168,6 +168,7 @@ PT_FLAG_NO_APPEND = 1
 PT_EDGE_INNER, PT_EDGE_LEFT_OUTER, PT_EDGE_RIGHT_OUTER, PT_EDGE_FULL_OUTER = 0, 1, 2, 3
 PT_FLAG_SHARED_SCAN = 2
 PT_FLAG_EXACT = 4
+PT_FLAG_PRUNE = 8
 
 
 def params(block_bits: int = 512, k: int = 3, bits_per_key: int = 10, flags: int = 0, *, hash_version: int = 1,

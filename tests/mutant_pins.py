@@ -40,6 +40,7 @@ def checks():
     yield lambda: TH.test_threads_tiny(None, "tree")
     yield lambda: OU.test_outer_tree_query_unchanged(None, "tree")
     yield lambda: PR.test_prune_worked_example(None, oracle.EXACT, 3, 10)
+    yield lambda: PR.test_prune_keeps_an_empty_tables_filter(None)
     yield lambda: OU.test_full_outer_blocks_every_transfer(None)
     yield lambda: OU.test_preserved_side_keeps_its_rows(None, 1, 0)
 

@@ -54,7 +54,7 @@ def test_capacity_and_workspace_sizes(ptlib):
 def test_parameter_validation(ptlib):
     bad = [ptlib.pt_params(48, 3, 10, 0), ptlib.pt_params(2048, 3, 10, 0), ptlib.pt_params(512, 0, 10, 0),
            ptlib.pt_params(512, 17, 10, 0), ptlib.pt_params(512, 3, 0, 0), ptlib.pt_params(512, 3, 65, 0),
-           ptlib.pt_params(512, 3, 10, 8), ptlib.pt_params(512, 3, 10, 0x80000001)]
+           ptlib.pt_params(512, 3, 10, 16), ptlib.pt_params(512, 3, 10, 0x80000001)]
     for p in bad:
         with pytest.raises(ptlib.PtError) as ei:
             ptlib.pt_bloom_capacity(10, p)

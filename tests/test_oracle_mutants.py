@@ -45,8 +45,9 @@ MUTANTS = {
                                 "if ((uint32_t)slot[b_t] >= i || b_t != u) continue;"),
     "join_upper_bound": ("if (index[mid].key < key) lo = mid + 1;", "if (index[mid].key <= key) lo = mid + 1;"),
     "join_ignores_bitmap": ("if (!row_selected(bitmaps, v, r)) continue;", "(void)0;"),
-    "prune_ignores_reduction": ("pa->prune && bitmap_popcount(bitmaps[v], t->n_rows) == t->n_rows",
+    "prune_ignores_reduction": ("pa->prune && t->n_rows > 0 && bitmap_popcount(bitmaps[v], t->n_rows) == t->n_rows",
                                 "pa->prune"),
+    "prune_empty_tables": ("pa->prune && t->n_rows > 0 && bitmap_popcount", "pa->prune && bitmap_popcount"),
     "prune_absent_blocks_keys": ("if (f->absent) return 1;", "if (f->absent) return 0;"),
     "join_columns_in_bfs_order": ("sorted[j * w + q] = cur[j * w + slot[comp[q]]];",
                                   "sorted[j * w + q] = cur[j * w + q];"),

@@ -1,8 +1,8 @@
 """Pins of the oracle's transfer path pruning (Sec. 3.2, "Transfer Path
 Pruning": the paper asks for skipping transfers that cannot make a filter
-more selective and leaves the rule open). The rule read here: a table whose
-selection still holds every one of its rows sends no filter, and the tables
-it would have sent one to are not probed with it.
+more selective and leaves the rule open). The rule read here: a non-empty
+table whose selection still holds every one of its rows sends no filter,
+and the tables it would have sent one to are not probed with it.
 
 * an authored chain worked by hand, where pruning keeps a row that the full
   transfer removes, and the join result is the same;
@@ -13,6 +13,7 @@ it would have sent one to are not probed with it.
   filters remove nothing, so the result is bit for bit the full one;
 * an unreduced table passes its state on: a table that receives only
   pruned filters is unreduced in turn and sends none either;
+* an empty table's filter (it holds no key) is never pruned;
 * on the paper's own Fig. 3 instance (no table has a predicate) nothing is
   transferred at all.
 """
@@ -136,6 +137,19 @@ def test_prune_propagates_along_a_path(oracle_lib):
     assert all(full.filter_nb[(0, e)] > 0 for e in range(3))
     assert res.fwd_counts[prob.table("A")] == 8 and res.fwd_counts[prob.table("B")] == 20
     assert rc.join_multiset(prob, masks_from(res, prob)) == rc.join_multiset(prob)
+
+
+def test_prune_keeps_an_empty_tables_filter(oracle_lib):
+    """An empty table holds all of its (zero) rows, but its filter holds no
+    key: it still goes out and empties every table it reaches, as without
+    pruning (the join result is empty either way)."""
+    prob = Problem(["E", "S", "T"],
+                   [{"a": np.zeros(0, np.int32)}, {"a": np.arange(6, dtype=np.int32), "b": np.arange(6, dtype=np.int32)},
+                    {"b": np.arange(9, dtype=np.int32)}],
+                   [(0, "a", 1, "a"), (1, "b", 2, "b")], [])
+    for kind in (oracle.BLOOM, oracle.EXACT):
+        res = oracle.transfer(prob, 512, 3, 10, kind=kind, prune=True)
+        assert res.counts == [0, 0, 0]
 
 
 def test_prune_on_fig3_transfers_nothing(oracle_lib):
