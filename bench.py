@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-join", action="store_true", help="star: skip the join-phase and exact-filter timings")
+    ap.add_argument("--no-prune", action="store_true", help="star, snowflake: skip the transfer-path-pruning timing")
     ap.add_argument("--check", action="store_true", help="compare the result with the oracle")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without the per-kernel HIP events (no roofline figure)")
@@ -246,6 +247,8 @@ def main():
     if args.workload == "star" and not args.no_join:
         out["join"] = bench_join(args, torch, pt, prob, dp, tr)
         out["exact_filters"] = bench_exact(args, torch, pt, prob, dp, tr, ms_per_step)
+    if args.workload in ("star", "snowflake") and not args.no_prune:
+        out["pruned"] = bench_prune(args, torch, pt, prob, dp, tr, bpk, ms_per_step)
 
     if args.calibrate_copy:
         out["calibration_copy_bytes"] = 1 << 30
@@ -348,6 +351,33 @@ def bench_exact(args, torch, pt, prob, dp, tr, bloom_ms: float) -> dict:
            "rows_left_bloom": [int(x) for x in tr.counts.cpu().tolist()],
            "workspace_GB": round(ex.ws_bytes / 2**30, 2)}
     del ex
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_prune(args, torch, pt, prob, dp, tr, bpk: int, full_ms: float) -> dict:
+    """The same transfer with transfer path pruning (PT_FLAG_PRUNE, Sec. 3.2:
+    a table that still holds every row sends no filter), timed apart from
+    the full steps: its time per step against the full step, and whether it
+    left the same rows (it does when every foreign key references an
+    existing key, as in these workloads)."""
+    pr = pt.Transfer(dp, pt.params(512, 3, bpk, pt.PT_FLAG_PRUNE))
+    for _ in range(2):
+        pr.run()
+    pr.check_status()
+    times = []
+    for _ in range(max(3, min(args.steps, 20))):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        pr.run()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = float(np.median(times))
+    same = all(torch.equal(x, y) for x, y in zip(pr.bitmaps, tr.bitmaps))
+    res = {"ms_per_step": round(ms, 4), "vs_full_step": round(ms / full_ms, 3),
+           "rows_left": [int(x) for x in pr.counts.cpu().tolist()], "bits_equal_full": bool(same)}
+    del pr
     torch.cuda.empty_cache()
     return res
 
