@@ -260,13 +260,14 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const
         klo[0] = q_lo[idx];
         khi[0] = KEY64 ? q_hi[idx] : static_cast<uint32_t>(static_cast<int32_t>(klo[0]) >> 31);
       }
-#pragma unroll
-      for (int s = 1; s < kMaxProbe; s++)
-        if (s < static_cast<int>(n_f)) gather_key(sl[s].keys, sl[s].key64, row, klo[s], khi[s]);
+      // Filter by filter, the next column's key is read only for the rows
+      // still alive: the later filters' columns are read in fewer cache
+      // lines (the filters are ordered most selective first).
       bool ok = act;
 #pragma unroll
       for (int s = 1; s < kMaxProbe; s++) {
         if (s < static_cast<int>(n_f)) {
+          if (ok) gather_key(sl[s].keys, sl[s].key64, row, klo[s], khi[s]);
           uint32_t h1, h2;
           hash_parts(klo[s], khi[s], sl[s].key64, h1, h2);
           ok = ok && slot_has_any<K>(sl[s], lds_filters, lds_off[s], h1, h2, k, lg);
