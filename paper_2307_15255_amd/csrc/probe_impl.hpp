@@ -260,14 +260,24 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const
         klo[0] = q_lo[idx];
         khi[0] = KEY64 ? q_hi[idx] : static_cast<uint32_t>(static_cast<int32_t>(klo[0]) >> 31);
       }
-      // Filter by filter, the next column's key is read only for the rows
-      // still alive: the later filters' columns are read in fewer cache
-      // lines (the filters are ordered most selective first).
+      // The second filter's key is read for the survivors of the first,
+      // the remaining filters' keys only for the rows that pass the second
+      // too (the filters are ordered most selective first, so later
+      // columns are read in fewer cache lines; the remaining ones are read
+      // together, in one round trip).
       bool ok = act;
+      if (n_f > 1) {
+        gather_key(sl[1].keys, sl[1].key64, row, klo[1], khi[1]);
+        uint32_t h1, h2;
+        hash_parts(klo[1], khi[1], sl[1].key64, h1, h2);
+        ok = ok && slot_has_any<K>(sl[1], lds_filters, lds_off[1], h1, h2, k, lg);
+      }
 #pragma unroll
-      for (int s = 1; s < kMaxProbe; s++) {
+      for (int s = 2; s < kMaxProbe; s++)
+        if (s < static_cast<int>(n_f) && ok) gather_key(sl[s].keys, sl[s].key64, row, klo[s], khi[s]);
+#pragma unroll
+      for (int s = 2; s < kMaxProbe; s++) {
         if (s < static_cast<int>(n_f)) {
-          if (ok) gather_key(sl[s].keys, sl[s].key64, row, klo[s], khi[s]);
           uint32_t h1, h2;
           hash_parts(klo[s], khi[s], sl[s].key64, h1, h2);
           ok = ok && slot_has_any<K>(sl[s], lds_filters, lds_off[s], h1, h2, k, lg);
