@@ -1262,6 +1262,12 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
       for (uint32_t v : lvl[p][i]) max_lvl = std::max(max_lvl, v);
     }
   }
+  // Probes whose smallest filter is too large for LDS (per bp.probes
+  // entry): their items are cut kCacheProbeSplit times smaller and counted
+  // kCacheProbeCost times dearer per row when the items are ordered.
+  constexpr uint64_t kCacheProbeSplit = 4;
+  constexpr double kCacheProbeCost = 3.0;
+  std::vector<char> probe_from_cache;
   // A probe a shared scan may take: the only probe of a large table in its
   // pass (tasks are created once the level's candidates are grouped).
   struct ProbeCand {
@@ -1272,11 +1278,20 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
   };
   auto emit_probe = [&](const ProbeCand &c) {
     // Every item first copies the filters into its LDS when they fit
-    // there: give it at least eight times their size in keys.
-    uint64_t filter_words = 0;
-    for (uint32_t j = 0; j < c.pt.fs.n; j++) filter_words += c.pt.fs.f[j].cap_words;
+    // there: give it at least eight times their size in keys. When even
+    // the smallest filter is too large for LDS, every row's test reads
+    // the filter from the caches at random, several times slower per row:
+    // smaller items keep the phase's last items short.
+    uint64_t filter_words = 0, min_words = ~0ull;
+    for (uint32_t j = 0; j < c.pt.fs.n; j++) {
+      filter_words += c.pt.fs.f[j].cap_words;
+      min_words = std::min<uint64_t>(min_words, c.pt.fs.f[j].cap_words);
+    }
     const uint64_t staged = filter_words <= lds_filter_words ? filter_words : 0;
-    const uint64_t probe_words = std::max<uint64_t>(words_per_item, staged * 4 * 8 / (64 * 4));
+    const bool from_cache = min_words > lds_filter_words;
+    const uint64_t probe_words = from_cache ? std::max<uint64_t>(64, words_per_item / kCacheProbeSplit)
+                                            : std::max<uint64_t>(words_per_item, staged * 4 * 8 / (64 * 4));
+    probe_from_cache.push_back(from_cache);
     bp.bytes_moved += c.bytes;
     writer[c.i][c.v] = add_task(kBProbe, div_up32(c.n_words, probe_words), c.deps,
                                 static_cast<uint32_t>(bp.probes.size()));
@@ -1343,6 +1358,7 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
         }
         deps.insert(deps.end(), c.deps.begin(), c.deps.end());
         bp.probes.push_back(c.pt);
+        probe_from_cache.push_back(0);
         bp.bytes_moved += 2 * c.n_words * 8;
       }
       const uint32_t id = add_task(kBShared, div_up32(c0.n_words, words_per_item), deps,
@@ -1503,7 +1519,10 @@ pt_status plan_batch(uint32_t n_problems, const pt_problem *probs, char *ws, Bat
       const double items = k.n_items;
       switch (k.kind) {
         case kBLocal: cost[t] = bp.locals[k.arg].n_rows * (1.0 + bp.locals[k.arg].ps.n) / items; break;
-        case kBProbe: cost[t] = bp.probes[k.arg].n_rows * (1.0 + bp.probes[k.arg].fs.n) / items; break;
+        case kBProbe:
+          cost[t] = bp.probes[k.arg].n_rows * (1.0 + bp.probes[k.arg].fs.n) / items *
+                    (probe_from_cache[k.arg] ? kCacheProbeCost : 1.0);
+          break;
         case kBShared: cost[t] = bp.shared[k.arg].n_rows * (1.0 + bp.shared[k.arg].n_members) / items; break;
         case kBBuild:
         case kBCount:
