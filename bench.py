@@ -543,6 +543,7 @@ def bench_served(args, torch, pt, W):
                        "G_rows_probed_per_s": round(rows / srv.wall / 1e9, 3), "batches": len(srv.batches),
                        "mean_batch": round(len(qs) / len(srv.batches), 2),
                        "rejected": len(srv.rejected), "timed_out": len(srv.timed_out),
+                       "host_launch_ms_per_batch": round(srv.launch_host_s * 1e3 / max(1, len(srv.batches)), 3),
                        "peak_admitted_GB": round(srv.peak_bytes / 2**30, 2)},
             "one_at_a_time": {"p50_ms": round(fifo.percentile(50) * 1e3, 3),
                               "p99_ms": round(fifo.percentile(99) * 1e3, 3),

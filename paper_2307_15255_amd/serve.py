@@ -115,6 +115,7 @@ class Report:
     timed_out: dict = field(default_factory=dict)  # qid -> seconds waited when it was dropped
     peak_bytes: int = 0
     wall: float = 0.0
+    launch_host_s: float = 0.0  # host time spent in executor.launch (planning and enqueueing batches)
 
     def percentile(self, p: float) -> float:
         """Latency percentile over the queries that completed."""
@@ -177,7 +178,9 @@ def serve(queries: list[Query], executor, budget_bytes: int, slots: int = 2, max
                 used += nbytes
                 rep.peak_bytes = max(rep.peak_bytes, used)
                 rep.batches.append((clock() - t0, [q.qid for q in take], nbytes))
+                t_launch = clock()
                 inflight.append((executor.launch(take, slot), take, nbytes, slot))
+                rep.launch_host_s += clock() - t_launch
                 progressed = True
         if not progressed:
             idle()
