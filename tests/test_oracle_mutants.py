@@ -57,7 +57,7 @@ MUTANTS = {
 def _mutate(text: str, name: str) -> str:
     if name == "build_before_probe":
         a = text.index("    for (uint32_t j = 0; j < m; j++) {\n      uint32_t e = reverse_probe")
-        b = text.index("    for (uint32_t e = 0; e < m; e++) {\n      if (src[e] != v || !edge_carries")
+        b = text.index("    /* Transfer path pruning: a non-empty table")
         c = text.index("  return PTOR_OK;\n}\n\nstatic int problem_valid")
         probe, build = text[a:b], text[b:c - len("  }\n")]
         return text[:a] + build + probe + text[c - len("  }\n"):]
