@@ -384,19 +384,22 @@ def bench_prune(args, torch, pt, prob, dp, tr, bpk: int, full_ms: float) -> dict
 
 def bench_batch(args, torch, pt, W):
     """256 independent chain and star problems (tables log-uniform on
-    [10 k, 5 M] rows) run as one batch: one graph launch per step. Beside it,
-    the same problems one at a time with plain pt_transfer launches."""
+    [10 k, 5 M] rows) run as one batch: one persistent launch per step (a
+    captured graph). Beside it, the same problems one at a time with plain
+    pt_transfer launches."""
     from paper_2307_15255_amd import autotune
     t0 = time.time()
     probs = W.batch(seed=args.seed, n_problems=args.problems)
     dps = [pt.DeviceProblem(p) for p in probs]
     torch.cuda.synchronize()
     print(f"# batch inputs ready in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    tiles = None
     if args.no_tune:
         ps, tune_s = [pt.params(512, 3, 10) for _ in probs], 0.0
     else:
         t1 = time.time()
         ps, _ = autotune.tune(probs)
+        ps, tiles = autotune.tune_tiles(dps, ps)
         tune_s = time.time() - t1
     chosen: dict[str, int] = {}
     for p in ps:
@@ -450,6 +453,8 @@ def bench_batch(args, torch, pt, W):
         "data": "synthetic",
         "config": {"workload": "batch", "problems": len(probs), "rows": sum(sum(d.n_rows) for d in dps),
                    "table_rows": "log-uniform [10k, 5M]", "params": chosen, "autotune_s": round(tune_s, 2),
+                   "tile_rows": ps[0].tile_rows,
+                   "tile_search_ms": tiles["measured_ms"] if tiles else None,
                    "launches_per_run": n_launch},
         "rows_probed_per_step": n_probed,
         "one_at_a_time": {"ms_per_step": round(single_ms, 4),

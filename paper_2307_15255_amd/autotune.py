@@ -13,11 +13,16 @@ given cost table the choice is a function of the problem alone. The
 candidates are the settings the batch kernel is specialised for (512-bit
 blocks, k = 2 or 3), so a tuned batch never runs the generic kernel.
 
-The rows per work item (`tile_rows`) follow from the batch's shape: enough
-items that every CU gets several, but none smaller than 32 768 rows.
+The rows per work item (`tile_rows`) are picked by `tune_tiles`: the batch
+itself is timed with every candidate and the fastest is kept in a second
+table keyed by the device and a digest of the batch (its tables, edges,
+predicates and filter settings), so a batch seen before gets the same
+choice without a measurement. Without a GPU measurement `tile_rows_for`
+gives a rule of thumb from the batch's shape.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import math
 import os
@@ -29,7 +34,7 @@ BLOCK_BITS = (512,)
 HASHES = (2, 3)
 BITS_PER_KEY = tuple(range(6, 25))
 SIZE_CLASSES = (20_000, 400_000, 4_000_000)  # filter keys the costs are measured at
-TILE_ROWS = (32_768, 65_536, 131_072)
+TILE_ROWS = (32_768, 65_536, 131_072, 262_144)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # Saved cost tables, one per device (PT_TUNING_DIR overrides the folder).
@@ -210,3 +215,65 @@ def tune(problems, costs: CostTable | None = None, fpr_cap: float = 0.02, n_cu: 
                  for p, c in zip(problems, picks)]
     tile = tile_rows_for(problems, n_cu)
     return [pt.params(*c, tile_rows=tile) for c in picks], costs
+
+
+def batch_digest(problems, params) -> str:
+    """A digest of a batch: every problem's table sizes, edges, edge kinds,
+    predicates and filter settings."""
+    h = hashlib.sha256()
+    for prob, p in zip(problems, params):
+        rows = [prob.n_rows(t) for t in range(prob.n_tables)]
+        h.update(repr((rows, prob.edges, prob.edge_flags, prob.orient, prob.preds,
+                       (p.block_bits, p.k, p.bits_per_key, p.flags))).encode())
+    return h.hexdigest()[:32]
+
+
+def _tiles_path(name: str) -> str:
+    safe = "".join(c if c.isalnum() else "_" for c in name)
+    return os.path.join(COST_DIR, f"tiles_{safe}.json")
+
+
+def tune_tiles(dps, params, reps: int = 5) -> tuple[list, dict]:
+    """The batch's parameters with the fastest rows per work item. A choice
+    saved for this device and batch digest is reused; otherwise the batch
+    runs with every candidate in TILE_ROWS (two warm-up runs, then the
+    median of `reps`) and the fastest is saved. The bits do not depend on
+    this choice. Returns the parameters and a record of the choice."""
+    from . import pt
+    digest = batch_digest([dp.problem for dp in dps], params)
+    path = _tiles_path(device_name())
+    table = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+    times = None
+    if digest in table:
+        best = int(table[digest]["tile_rows"])
+    else:
+        times = {}
+        for tr in TILE_ROWS:
+            ps = [pt.params(p.block_bits, p.k, p.bits_per_key, p.flags, hash_version=p.hash_version,
+                            lds_budget=p.lds_budget, tile_rows=tr, probe_order=p.probe_order) for p in params]
+            bt = pt.Batch(dps, ps)
+            for _ in range(2):
+                bt.run()
+            runs = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                bt.run()
+                b.record()
+                b.synchronize()
+                runs.append(a.elapsed_time(b))
+            bt.close()
+            del bt
+            times[tr] = sorted(runs)[len(runs) // 2]
+        best = min(TILE_ROWS, key=lambda tr: (times[tr], tr))
+        table[digest] = {"tile_rows": best, "ms": {str(k): round(v, 4) for k, v in times.items()}}
+        os.makedirs(COST_DIR, exist_ok=True)
+        with open(path + ".tmp", "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(path + ".tmp", path)
+    out = [pt.params(p.block_bits, p.k, p.bits_per_key, p.flags, hash_version=p.hash_version,
+                     lds_budget=p.lds_budget, tile_rows=best, probe_order=p.probe_order) for p in params]
+    return out, {"tile_rows": best, "digest": digest, "measured_ms": times}

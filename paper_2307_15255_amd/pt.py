@@ -449,9 +449,9 @@ def pt_batch_workspace_size(dps: list[DeviceProblem], ps: list[pt_params]) -> in
 
 
 class Batch:
-    """Many problems run together (pt_batch_*): one launch per step and
-    schedule level for all of them, captured once into a HIP graph. Holds
-    the workspace, every problem's bitmaps and counts."""
+    """Many problems run together (pt_batch_*): one persistent kernel launch
+    for all of them, captured once into a HIP graph. Holds the workspace,
+    every problem's bitmaps and counts."""
 
     def __init__(self, dps: list[DeviceProblem], ps: list[pt_params] | None = None, device="cuda",
                  stream=None, ws: torch.Tensor | None = None):

@@ -71,3 +71,33 @@ def test_tile_rows_follow_the_batch_size():
     assert A.tile_rows_for(small, 256) == min(A.TILE_ROWS)
     big = W.batch(seed=1, n_problems=8, lo=4_000_000, hi=5_000_000)
     assert A.tile_rows_for(big, 8) == max(A.TILE_ROWS)
+
+
+def test_tile_choice_saved_for_a_batch_is_reused(tmp_path, monkeypatch):
+    """tune_tiles reads its choice from the device's table when the batch's
+    digest is there (no measurement), and the digest follows what the batch
+    is made of."""
+    from paper_2307_15255_amd import pt
+    monkeypatch.setattr(A, "COST_DIR", str(tmp_path))
+    monkeypatch.setattr(A, "device_name", lambda: "test device 8cu")
+    probs = [W.tiny_random(np.random.default_rng(s), "tree") for s in range(6)]
+    params = [pt.params(512, 3, 10)] * len(probs)
+    digest = A.batch_digest(probs, params)
+    with open(A._tiles_path("test device 8cu"), "w") as f:
+        f.write('{"%s": {"tile_rows": 65536, "ms": {}}}' % digest)
+
+    class DP:
+        def __init__(self, p):
+            self.problem = p
+
+    out, rec = A.tune_tiles([DP(p) for p in probs], params)
+    assert [p.tile_rows for p in out] == [65536] * len(probs)
+    assert rec["measured_ms"] is None and rec["digest"] == digest
+    assert [(p.block_bits, p.k, p.bits_per_key) for p in out] == [(512, 3, 10)] * len(probs)
+    # another predicate constant or other filter settings: another batch
+    changed = [W.Problem(p.names, p.columns, p.edges, [(t, c, op, lo + 1, hi) for t, c, op, lo, hi in p.preds],
+                         p.orient, p.label, p.edge_flags) for p in probs]
+    if any(p.preds for p in probs):
+        assert A.batch_digest(changed, params) != digest
+    assert A.batch_digest(probs, [pt.params(512, 2, 14)] * len(probs)) != digest
+    assert A.batch_digest(probs[::-1], params) != digest

@@ -173,3 +173,31 @@ def test_shared_scans(pt, sel_hi):
         for t in range(dps[i].n_tables):
             assert torch.equal(bt.bitmaps[i][t], solo.bitmaps[i][t]), (i, t)
         assert torch.equal(bt.counts[i], solo.counts[i]), i
+
+
+def test_tile_search_keeps_bits(pt, tmp_path, monkeypatch):
+    """The rows-per-item search times the batch with every candidate and
+    keeps the fastest (a second call reuses the saved choice); every
+    candidate gives the same bits, the oracle's."""
+    from paper_2307_15255_amd import autotune as A
+    monkeypatch.setattr(A, "COST_DIR", str(tmp_path))
+    probs = W.batch(seed=12, n_problems=24, lo=10_000, hi=400_000)
+    dps = [pt.DeviceProblem(p) for p in probs]
+    ps = [pt.params(512, 3, 10)] * len(probs)
+    say("tile search")
+    out, rec = A.tune_tiles(dps, ps, reps=3)
+    assert set(rec["measured_ms"]) == set(A.TILE_ROWS)
+    assert rec["tile_rows"] == min(A.TILE_ROWS, key=lambda t: (rec["measured_ms"][t], t))
+    again, rec2 = A.tune_tiles(dps, ps)
+    assert rec2["measured_ms"] is None and rec2["tile_rows"] == rec["tile_rows"]
+    results = []
+    for tr in (min(A.TILE_ROWS), max(A.TILE_ROWS)):
+        bt = pt.Batch(dps, [pt.params(512, 3, 10, tile_rows=tr)] * len(dps))
+        bt.run()
+        torch.cuda.synchronize()
+        bt.check_status()
+        results.append(bt)
+    for i in range(len(dps)):
+        for t in range(dps[i].n_tables):
+            assert torch.equal(results[0].bitmaps[i][t], results[1].bitmaps[i][t]), (i, t)
+    check_against_oracle(pt, results[1], probs, [pt.params(512, 3, 10)] * len(probs), which=[0, 7, 23])
