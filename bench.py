@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-join", action="store_true", help="star: skip the join-phase and exact-filter timings")
     ap.add_argument("--no-prune", action="store_true", help="star, snowflake: skip the transfer-path-pruning timing")
+    ap.add_argument("--hold", type=float, default=0.0,
+                    help="served: hold a lone query beside a running batch for up to this many mean solo "
+                         "service times, for another query to batch with")
     ap.add_argument("--check", action="store_true", help="compare the result with the oracle")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without the per-kernel HIP events (no roofline figure)")
@@ -533,7 +536,8 @@ def bench_served(args, torch, pt, W):
     for rho, qs in zip(loads, streams):
         for q, t in zip(qs, S.poisson_arrivals(rng, len(qs), rho / s1)):
             q.arrival = float(t)
-        srv = S.serve(qs, ex, budget_bytes=2 * arena, slots=2, max_batch=64, batch_bytes=arena)
+        srv = S.serve(qs, ex, budget_bytes=2 * arena, slots=2, max_batch=64, batch_bytes=arena,
+                      hold=args.hold * s1)
         torch.cuda.synchronize()
         print(f"# load {rho}: served in {srv.wall:.2f} s", file=sys.stderr, flush=True)
         fifo = S.one_at_a_time(qs, ex)
@@ -574,7 +578,8 @@ def bench_served(args, torch, pt, W):
         "config": {"workload": "served", "resident": "star 100M fact + dims (2M, 200k, 10k, 25), int64 twins "
                    "of (k0, D0.pk) and (k1, D1.pk)", "query": "fact + 1-4 dims, 1-2 predicates with selectivity "
                    "log-uniform [0.1%, 50%]", "arrivals": "Poisson", "solo_latency_ms": round(s1 * 1e3, 3),
-                   "slots": 2, "max_batch": 64, "arena_GB_per_slot": arena / 2**30},
+                   "slots": 2, "max_batch": 64, "arena_GB_per_slot": arena / 2**30,
+                   "hold_ms": round(args.hold * s1 * 1e3, 3)},
         "loads": levels,
     }
     print(json.dumps(out), flush=True)

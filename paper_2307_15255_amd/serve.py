@@ -123,15 +123,17 @@ class Report:
 
 
 def serve(queries: list[Query], executor, budget_bytes: int, slots: int = 2, max_batch: int = 64,
-          batch_bytes: int | None = None, timeout: float | None = None, clock=time.perf_counter,
-          idle=lambda: time.sleep(50e-6)) -> Report:
+          batch_bytes: int | None = None, timeout: float | None = None, hold: float = 0.0,
+          clock=time.perf_counter, idle=lambda: time.sleep(50e-6)) -> Report:
     """Runs the request loop over `queries` (sorted by arrival) on
     `executor` and reports every query's latency. budget_bytes bounds the
     memory of all batches in flight, batch_bytes (default: the budget) that
     of one batch. A query needing more than either is rejected when it
     arrives (Report.rejected, the library's out-of-memory case); a query
     still waiting `timeout` seconds after its arrival is dropped
-    (Report.timed_out). Neither stops the others."""
+    (Report.timed_out). Neither stops the others. hold > 0: while another
+    batch is running, a query waiting alone is held up to `hold` seconds
+    after its arrival for another one to batch with."""
     rep = Report()
     cap = budget_bytes if batch_bytes is None else min(batch_bytes, budget_bytes)
     need = {q.qid: executor.mem_need(q) for q in queries}
@@ -166,7 +168,9 @@ def serve(queries: list[Query], executor, budget_bytes: int, slots: int = 2, max
                 free_slots.append(slot)
                 inflight.remove(item)
                 progressed = True
-        if waiting and free_slots:
+        held = (hold > 0 and inflight and len(waiting) == 1 and pending
+                and now - waiting[0].arrival < hold)
+        if waiting and free_slots and not held:
             take, nbytes = [], 0
             while (waiting and len(take) < max_batch and used + nbytes + need[waiting[0].qid] <= budget_bytes
                    and nbytes + need[waiting[0].qid] <= cap):

@@ -89,6 +89,27 @@ def test_batches_overlap_and_beat_one_at_a_time():
     assert alone.percentile(50) >= 3e-3 - 1e-9  # every lone query takes fixed + per-query time
 
 
+def test_hold_batches_lone_queries_while_busy():
+    """With hold, a query that would launch alone beside a running batch
+    waits (at most `hold` after its arrival) for company: batches grow, no
+    launch of a lone query beside a running batch happens before its hold
+    ran out unless another query came, and every query completes."""
+    qs = make_queries(300, qps=600)
+    hold = 1.5e-3
+    c1 = Clock()
+    plain = S.serve(qs, HostExecutor(c1), 10_000, slots=2, clock=c1, idle=c1.idle)
+    c2 = Clock()
+    held = S.serve(qs, HostExecutor(c2), 10_000, slots=2, hold=hold, clock=c2, idle=c2.idle)
+    assert set(held.latency) == {q.qid for q in qs}
+    assert len(held.batches) < len(plain.batches)
+    arrival = {q.qid: q.arrival for q in qs}
+    finish = [(t, held.finish[ids[0]]) for t, ids, _ in held.batches]
+    for t, ids, _ in held.batches:
+        busy = any(s < t < f for s, f in finish if s != t)
+        if busy and len(ids) == 1:
+            assert t - arrival[ids[0]] >= hold - 2e-4
+
+
 def test_oversized_query_is_rejected_alone():
     """A query that can never fit the memory limit is rejected by itself;
     the others are served."""
