@@ -337,7 +337,13 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const
   return cnt;
 }
 
-template <int B, int K, bool APPEND, int G = kGroupWords>
+// Key widths a probe kernel is built for: the first filter's key column
+// decides on the device which loop runs, and a kernel that only ever meets
+// one width (every key column of its filters int32, or every one int64)
+// leaves the other loop out, which frees registers.
+constexpr int kKeysMixed = 0, kKeys32 = 1, kKeys64 = 2;
+
+template <int B, int K, bool APPEND, int G = kGroupWords, int KW = kKeysMixed>
 __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint32_t lg_rt, uint64_t n_rows,
                                            uint64_t *__restrict__ bitmap, unsigned long long *count,
                                            uint32_t lds_filter_words, uint32_t input_all, uint32_t keep_order,
@@ -472,36 +478,44 @@ __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint
   // The per-wave slices follow the filters; lds_filter_words is even, so
   // each slice's 64-bit failure masks stay 8-byte aligned.
   uint32_t *slice = lds + lds_filter_words + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave) * kSliceWords;
-  int64_t cnt;
+  int64_t cnt = 0;
   if (!staged) off[0] = 0;  // slot 0 takes the global path by template
-  if (sl[0].key64) {
-    if (staged)
-      cnt = probe_loop<K, true, true, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
-                                              app_slot, vg);
-    else
-      cnt = probe_loop<K, true, false, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
-                                               app_slot, vg);
-  } else {
-    if (staged)
-      cnt = probe_loop<K, false, true, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
-                                               app_slot, vg);
-    else
-      cnt = probe_loop<K, false, false, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
+  // (with KW fixed, the host guarantees that every filter's key column has
+  // that width, so sl[0].key64 agrees with it)
+  const bool key64 = KW == kKeys64 || (KW == kKeysMixed && sl[0].key64);
+  if (key64) {
+    if constexpr (KW != kKeys32) {
+      if (staged)
+        cnt = probe_loop<K, true, true, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice, app,
                                                 app_slot, vg);
+      else
+        cnt = probe_loop<K, true, false, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice,
+                                                 app, app_slot, vg);
+    }
+  } else {
+    if constexpr (KW != kKeys64) {
+      if (staged)
+        cnt = probe_loop<K, false, true, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice,
+                                                 app, app_slot, vg);
+      else
+        cnt = probe_loop<K, false, false, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice,
+                                                  app, app_slot, vg);
+    }
   }
   block_count_add(cnt, &s_cnt, count);
 }
 
-template <int B, int K, bool APPEND>
+template <int B, int K, bool APPEND, int KW>
 __global__ void __launch_bounds__(kProbeThreads)
     k_probe(FilterSet fs, uint32_t k, uint32_t lg, uint64_t n_rows, uint64_t *__restrict__ bitmap,
             unsigned long long *count, uint32_t lds_filter_words, uint32_t input_all, uint32_t keep_order,
             uint32_t *status, AppendSet app) {
-  probe_body<B, K, APPEND>(fs, k, lg, n_rows, bitmap, count, lds_filter_words, input_all, keep_order, status, app,
-                           whole_grid());
+  probe_body<B, K, APPEND, kGroupWords, KW>(fs, k, lg, n_rows, bitmap, count, lds_filter_words, input_all,
+                                            keep_order, status, app, whole_grid());
 }
 
-// Launches k_probe<B, K, *> for one ProbeLaunch.
+// Launches k_probe<B, K, *, *> for one ProbeLaunch: the appending variant
+// when it appends, and the one built for its filters' key widths.
 template <int B, int K>
 hipError_t launch_probe_kernel(const ProbeLaunch &pl, hipStream_t s) {
   auto launch = [&](auto kern) -> hipError_t {
@@ -511,8 +525,17 @@ hipError_t launch_probe_kernel(const ProbeLaunch &pl, hipStream_t s) {
                        pl.bitmap, pl.count, pl.lds_filter_words, pl.input_all, pl.keep_order, pl.status, pl.app);
     return hipGetLastError();
   };
-  if (pl.app.n_cols) return launch(k_probe<B, K, true>);
-  return launch(k_probe<B, K, false>);
+  uint32_t n64 = 0;
+  for (uint32_t i = 0; i < pl.fs.n; i++) n64 += pl.fs.f[i].key64 ? 1u : 0u;
+  const int kw = n64 == 0 ? kKeys32 : n64 == pl.fs.n ? kKeys64 : kKeysMixed;
+  if (pl.app.n_cols) {
+    if (kw == kKeys32) return launch(k_probe<B, K, true, kKeys32>);
+    if (kw == kKeys64) return launch(k_probe<B, K, true, kKeys64>);
+    return launch(k_probe<B, K, true, kKeysMixed>);
+  }
+  if (kw == kKeys32) return launch(k_probe<B, K, false, kKeys32>);
+  if (kw == kKeys64) return launch(k_probe<B, K, false, kKeys64>);
+  return launch(k_probe<B, K, false, kKeysMixed>);
 }
 
 }  // namespace pt
