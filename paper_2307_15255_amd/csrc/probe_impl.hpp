@@ -116,30 +116,22 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const
   const void *col0 = sl[0].keys;
 
   // Software pipeline: the keys (and bitmap words) of the group after the
-  // current one are requested before the current one is tested.
+  // current one are requested before the current one's other filters are
+  // tested.
   uint64_t w0 = global_wave(vg) * U;
-  uint32_t nlo[U], nhi[KEY64 ? U : 1];
+  // One set of key registers: the next group's keys are requested as soon
+  // as the first filter has consumed the current group's, so the load is in
+  // flight while the current group's other filters are tested.
+  uint32_t lo[U], hi[KEY64 ? U : 1];
   uint64_t nbits = 0;
   if (w0 < n_words) {
     const uint64_t left = n_rows - 1 - w0 * 64;
-    load_group<KEY64, U>(col0, w0 * 64, left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu, nlo, nhi);
+    load_group<KEY64, U>(col0, w0 * 64, left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu, lo, hi);
     if (!input_all) nbits = bitmap[min(w0 + (lane < U ? lane : 0), n_words - 1)];
   }
   for (; w0 < n_words; w0 += stride) {
-    uint32_t lo[U], hi[KEY64 ? U : 1];
-#pragma unroll
-    for (int u = 0; u < U; u++) {
-      lo[u] = nlo[u];
-      if constexpr (KEY64) hi[u] = nhi[u];
-    }
     const uint64_t bits = nbits;  // lane u < U: bitmap word w0 + u (unless input_all)
     const uint64_t w_next = w0 + stride;
-    if (w_next < n_words) {
-      const uint64_t left = n_rows - 1 - w_next * 64;
-      load_group<KEY64, U>(col0, w_next * 64, left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu, nlo,
-                        nhi);
-      if (!input_all) nbits = bitmap[min(w_next + (lane < U ? lane : 0), n_words - 1)];
-    }
     const uint64_t base_row = w0 * 64;
 
     // The first (most selective) filter on every row of the group. The
@@ -196,6 +188,14 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const
           total0 += static_cast<uint32_t>(__popcll(m));
         }
       }
+    }
+    // The current group's first-column keys are consumed (the survivors'
+    // ones are in the slice): request the next group's.
+    if (w_next < n_words) {
+      const uint64_t left = n_rows - 1 - w_next * 64;
+      load_group<KEY64, U>(col0, w_next * 64, left < 0xFFFFFFFFull ? static_cast<uint32_t>(left) : 0xFFFFFFFFu, lo,
+                        hi);
+      if (!input_all) nbits = bitmap[min(w_next + (lane < U ? lane : 0), n_words - 1)];
     }
 
     uint32_t total = total0;  // rows left in the group
