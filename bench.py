@@ -138,7 +138,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the transfer path is built and timed on a single MI355X; "
-              "runs on more than one GPU are not part of this build.", file=sys.stderr)
+              "the library has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -24,8 +24,9 @@
  *           (HIP device memory on the current device). Everything else is
  *           host memory, read during the call only. The caller allocates and
  *           owns every buffer and keeps device buffers alive until the work
- *           queued on `stream` has finished. The library allocates no device
- *           memory; scratch space is the caller's workspace argument.
+ *           queued on `stream` has finished. No call allocates device
+ *           memory: scratch space is the caller's workspace argument (and
+ *           for pt_compact_noalloc, an array the library holds per GPU).
  * Streams.  Work is queued on `stream` (a hipStream_t; NULL is the null
  *           stream) and the call returns without waiting for it.
  * Errors.   Arguments are checked on the host first. A rejected call returns
@@ -71,7 +72,7 @@ typedef enum pt_status {
   PT_EINVAL = 1,       /* an argument was rejected; nothing was queued */
   PT_ENOMEM = 2,       /* a caller-provided workspace is too small */
   PT_EDEVICE = 3,      /* a HIP call or kernel launch failed */
-  PT_EUNSUPPORTED = 4, /* a valid request this build does not implement */
+  PT_EUNSUPPORTED = 4, /* a valid request this library does not implement */
   PT_EOVERFLOW = 5     /* pt_check_status: a kernel found a size above a capacity */
 } pt_status;
 
@@ -165,7 +166,7 @@ typedef struct pt_pred {
 /* Filter parameters, one set for every filter of a call. The first three
  * fix the filter bits (with the hash version); the rest only change how the
  * work is laid out on the device, never a bit of any result.
- *   hash_version  0 or 1: the filter specification above (PTSPEC-1); other
+ *   hash_version  0 or 1: the filter specification above; other
  *                 values are rejected with PT_EUNSUPPORTED
  *   lds_budget    bytes of LDS a probe workgroup may stage filters in
  *                 (0: as much as the device allows); filters that do not
@@ -338,10 +339,10 @@ pt_status pt_transfer_workspace_size(const pt_graph *graph, const pt_table *tabl
 
 /* The transfer phase (Sec. 3.2): local predicates, orientation, the forward
  * pass in topological order, then the backward pass on the reversed edges
- * starting from the forward survivors, with no pruning (every edge carries
- * one filter in each pass). Every source of a pass builds filters whether or
- * not it has a predicate. A filter is sized from the builder's row count
- * after that pass's probes at the builder.
+ * starting from the forward survivors. Without PT_FLAG_PRUNE every edge
+ * carries one filter in each pass, and every source of a pass builds its
+ * filters whether or not it has a predicate. A filter is sized from the
+ * builder's row count after that pass's probes at the builder.
  *   tables     graph->n_tables tables (at most 64)
  *   preds      n_preds predicates, each naming its table
  *   d_ws       workspace of at least pt_transfer_workspace_size bytes,
