@@ -20,23 +20,44 @@ __global__ void __launch_bounds__(kWideThreads)
                         whole_grid());
 }
 
-// Bucket b (blockIdx.x): exclusive scan of hist[g][b] over the n_groups
-// workgroups, in place; the bucket's total goes to totals[b].
+// Exclusive scan of hist[g][b] over the n_groups workgroups for every
+// bucket b, in place; bucket b's total goes to totals[b]. A workgroup takes
+// 64 buckets at a time (lane = bucket, so every read covers 64 consecutive
+// counters); wave w sums its share of the groups, the waves' sums are
+// combined in LDS, and each wave rewrites its share as running offsets.
 __global__ void __launch_bounds__(kWideThreads)
     k_part_scan_groups(FilterSet fs, uint32_t lg, uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
                        uint64_t entries_cap, uint32_t *__restrict__ hist, uint32_t n_groups,
                        uint64_t *__restrict__ totals) {
-  __shared__ uint64_t s[kWideThreads];
+  constexpr uint32_t kWaves = kWideThreads / kWave;
+  __shared__ uint64_t s_part[kWaves][kWave];
   if (build_pruned(fs)) return;
   const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false);
   if (!geo.ok) return;
-  for (uint32_t b = blockIdx.x; b < geo.buckets; b += gridDim.x) {
-    const uint32_t g = threadIdx.x;
-    const uint64_t v = g < n_groups ? hist[static_cast<uint64_t>(g) * kMaxBuckets + b] : 0;
-    uint64_t total;
-    const uint64_t ex = block_exclusive_scan(v, s, total);
-    if (g < n_groups) hist[static_cast<uint64_t>(g) * kMaxBuckets + b] = static_cast<uint32_t>(ex);
-    if (g == 0) totals[b] = total;
+  const uint32_t lane = lane_id();
+  const uint32_t wv = threadIdx.x / kWave;
+  const uint32_t per = (n_groups + kWaves - 1) / kWaves;
+  const uint32_t g0 = min(wv * per, n_groups), g1 = min(g0 + per, n_groups);
+  for (uint32_t b0 = blockIdx.x * kWave; b0 < geo.buckets; b0 += gridDim.x * kWave) {
+    const uint32_t b = b0 + lane;
+    const bool in = b < geo.buckets;
+    uint64_t sum = 0;
+#pragma unroll 8
+    for (uint32_t g = g0; g < g1; g++) sum += in ? hist[static_cast<uint64_t>(g) * kMaxBuckets + b] : 0;
+    s_part[wv][lane] = sum;
+    __syncthreads();
+    uint64_t run = 0;
+    for (uint32_t w = 0; w < wv; w++) run += s_part[w][lane];
+    if (wv == kWaves - 1 && in) totals[b] = run + sum;
+    for (uint32_t g = g0; g < g1; g++) {
+      if (in) {
+        uint32_t *h = hist + static_cast<uint64_t>(g) * kMaxBuckets + b;
+        const uint32_t v = *h;
+        *h = static_cast<uint32_t>(run);
+        run += v;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -108,7 +129,7 @@ hipError_t launch_part_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_
     if (big > max_buckets) max_buckets = big;
   }
   if (max_buckets > kMaxBuckets) max_buckets = kMaxBuckets;
-  const uint32_t scan_grid = static_cast<uint32_t>(max_buckets < 2048 ? max_buckets : 2048);
+  const uint32_t scan_grid = static_cast<uint32_t>((max_buckets + kWave - 1) / kWave);
   uint64_t fill_grid = static_cast<uint64_t>(device_info().n_cu) * 2;
   if (fill_grid > max_buckets) fill_grid = max_buckets;
   const bool spec = block_bits == 512 && k == 3;
