@@ -476,8 +476,14 @@ pt_status pt_transfer_batch(uint32_t n_problems, const pt_problem *problems, voi
  * of the calls above; on = 2: probe launches only; 0: off), each launch is
  * bracketed by HIP events recorded on the launch's own stream.
  * pt_profile_read waits for those events, copies up to `max` records into
- * `out`, sets *n to the number copied and clears the list. */
+ * `out`, sets *n to the number copied and clears the list.
+ * pt_profile_only narrows recording on the calling thread to the launches
+ * whose record would carry this name (compared as stored, at most 23
+ * characters), table and pass, so that a timed loop brackets one kernel
+ * and leaves the others' launches back to back; NULL or "" records every
+ * launch the mode selects again. */
 pt_status pt_profile_enable(int on);
+pt_status pt_profile_only(const char *name, uint32_t table, uint32_t pass);
 pt_status pt_profile_read(pt_kernel_time *out, uint32_t max, uint32_t *n);
 
 #ifdef __cplusplus

@@ -68,6 +68,9 @@ struct ProfRecord {
 };
 
 thread_local int g_prof_mode = 0;  // 0 off, 1 every launch, 2 probe launches only
+// when g_prof_only[0] != 0, only launches of that (name, table, pass) record
+thread_local char g_prof_only[sizeof(pt_kernel_time{}.name)] = {};
+thread_local uint32_t g_prof_only_table = 0, g_prof_only_pass = 0;
 thread_local std::vector<ProfRecord> g_prof;
 thread_local std::vector<hipEvent_t> g_event_pool;
 
@@ -91,6 +94,9 @@ class Timed {
         hipStream_t s)
       : s_(s) {
     if (!name || g_prof_mode == 0 || (g_prof_mode == 2 && std::strstr(name, "probe") == nullptr)) return;
+    if (g_prof_only[0] && (table != g_prof_only_table || pass != g_prof_only_pass ||
+                           std::strncmp(name, g_prof_only, sizeof g_prof_only - 1) != 0))
+      return;
     rec_.t = pt_kernel_time{};
     std::snprintf(rec_.t.name, sizeof rec_.t.name, "%s", name);
     rec_.t.table = table;
@@ -506,6 +512,17 @@ pt_status pt_check_status(const void *d_status, pt_stream stream) {
 pt_status pt_profile_enable(int on) {
   if (on < 0 || on > 2) return fail(PT_EINVAL, "pt_profile_enable: mode %d", on);
   g_prof_mode = on;
+  return PT_OK;
+}
+
+pt_status pt_profile_only(const char *name, uint32_t table, uint32_t pass) {
+  if (!name || !name[0]) {
+    g_prof_only[0] = 0;
+    return PT_OK;
+  }
+  std::snprintf(g_prof_only, sizeof g_prof_only, "%s", name);
+  g_prof_only_table = table;
+  g_prof_only_pass = pass;
   return PT_OK;
 }
 

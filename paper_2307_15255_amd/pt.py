@@ -120,6 +120,7 @@ def _load() -> C.CDLL:
         "pt_join": ([C.POINTER(pt_graph), C.POINTER(pt_table), u32, C.POINTER(vp), C.POINTER(vp), u64, vp, vp,
                      C.c_size_t, vp], st),
         "pt_profile_enable": ([C.c_int], st),
+        "pt_profile_only": ([C.c_char_p, u32, u32], st),
         "pt_profile_read": ([C.POINTER(pt_kernel_time), u32, C.POINTER(u32)], st),
     }
     for name, (args, res) in sigs.items():
@@ -135,7 +136,7 @@ EXPORTS = ("pt_version", "pt_last_error", "pt_check_status", "pt_local_filter", 
            "pt_transfer", "pt_transfer_filter", "pt_batch_workspace_size", "pt_batch_prepare",
            "pt_batch_prepare_async", "pt_batch_run",
            "pt_batch_info", "pt_batch_timeline", "pt_batch_free", "pt_transfer_batch", "pt_join_workspace_size",
-           "pt_join", "pt_profile_enable", "pt_profile_read")
+           "pt_join", "pt_profile_enable", "pt_profile_only", "pt_profile_read")
 PT_BATCH_EAGER = 1
 
 
@@ -268,6 +269,12 @@ def pt_compact_noalloc(bitmap: torch.Tensor, n_rows: int, idx: torch.Tensor, cou
 def pt_profile_enable(on: bool | int) -> None:
     """on: False/0 off, True/1 every launch, 2 probe launches only."""
     _check(_lib.pt_profile_enable(int(on)))
+
+
+def pt_profile_only(name: str | None, table: int = 0, pass_: int = 0) -> None:
+    """Record events only around launches of this (name, table, pass);
+    None records every launch the mode selects again."""
+    _check(_lib.pt_profile_only(name.encode() if name else None, table, pass_))
 
 
 def pt_profile_read(max_records: int = 4096) -> list[dict]:

@@ -216,3 +216,14 @@ def test_exact_flag_planning(ptlib):
                                 ptlib.params(flags=ptlib.PT_FLAG_EXACT), None, None)
     out = C.c_size_t()
     assert ptlib.lib().pt_batch_workspace_size(1, probs, C.byref(out)) == ptlib.PT_EUNSUPPORTED
+
+
+def test_profile_switches(ptlib):
+    """Profiling switches are host state: a mode outside 0..2 is rejected,
+    a selection set and cleared, and nothing is recorded without a launch."""
+    with pytest.raises(ptlib.PtError) as ei:
+        ptlib.pt_profile_enable(3)
+    assert ei.value.status == ptlib.PT_EINVAL
+    ptlib.pt_profile_only("probe", 2, 1)
+    ptlib.pt_profile_only(None)
+    assert ptlib.pt_profile_read(16) == []
