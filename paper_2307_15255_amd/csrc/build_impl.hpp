@@ -160,6 +160,30 @@ __device__ __forceinline__ void for_each_key(const FilterRef &f, const AppendSet
 
 namespace pt {
 
+// ------------------------------------------------------- the size step
+//
+// A build kernel sizes its filters itself from the builder's selected count
+// (n_rows when count is NULL): nb = max(1, ceil(n_sel * bpk / B)), at most
+// the capacity. Returns false when the set is pruned (a non-empty builder
+// that kept every row). `lead`, one thread of the grid, records each
+// filter's block count (0 for a pruned set) and raises an overflow.
+__device__ __forceinline__ bool size_step(const FilterSet &fs, uint32_t lg, uint32_t bits_per_key,
+                                          const uint64_t *count, uint64_t n_rows, bool lead, uint32_t *status,
+                                          uint64_t &n_sel) {
+  n_sel = count ? *count : n_rows;
+  const bool pruned = fs.prune && count && n_rows > 0 && n_sel == n_rows;
+  if (lead)
+    for (uint32_t i = 0; i < fs.n; i++)
+      *fs.f[i].nb = pruned ? 0 : blocks_needed(n_sel, 1u << lg, bits_per_key, fs.f[i].cap_words >> (lg - 5), status);
+  return !pruned;
+}
+
+// Filter f's block count for n_sel selected keys (as the size step records it).
+__device__ __forceinline__ uint32_t sized_blocks(const FilterRef &f, uint32_t lg, uint32_t bits_per_key,
+                                                 uint64_t n_sel) {
+  return static_cast<uint32_t>(blocks_needed(n_sel, 1u << lg, bits_per_key, f.cap_words >> (lg - 5), nullptr));
+}
+
 // ---------------------------------------------------- partitioned builds
 //
 // Filters too large for LDS are built tile by tile: each filter's blocks are

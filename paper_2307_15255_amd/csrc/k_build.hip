@@ -3,10 +3,13 @@
 // into each outgoing filter by OR, which is order-free, so the filter bits do
 // not depend on scheduling.
 //
-// Filters that fit in LDS together are built without global atomics: each
-// workgroup sets the bits of its rows in private LDS copies (LDS atomics),
-// writes the copies to scratch memory, and a second kernel ORs the copies
-// word by word into the filters. Larger filters go to the partitioned build
+// Filters that fit in LDS together are built without global atomics. A
+// small table's are built by one workgroup in one launch: it sizes them
+// from the selected count, sets the bits in LDS and stores every word.
+// Otherwise each workgroup sets the bits of its rows in private LDS copies
+// (LDS atomics), writes the copies to scratch memory, and a second kernel
+// ORs the copies word by word into the filters. Larger filters go to the
+// partitioned build
 // (k_part.hip) when the caller gave its scratch, else they are built in
 // place with global atomic OR, skipped when a read already shows the bit set.
 #include <cstdlib>
@@ -17,6 +20,12 @@
 namespace pt {
 
 namespace {
+
+// Tables of at most this many bitmap words (4096 rows) whose filters fit in
+// LDS are built by one workgroup: its 16 waves then walk a few words each
+// (10 k rows took one workgroup longer than the three launches of the
+// copies path).
+constexpr uint64_t kOneGroupWords = 64;
 
 // Block count of filter f as recorded by its size step, in [1, capacity].
 __device__ __forceinline__ uint32_t filter_blocks(const FilterRef &f, uint32_t lg, uint32_t *status) {
@@ -46,39 +55,34 @@ __device__ __forceinline__ uint32_t lds_total(const FilterSet &fs, uint32_t lg, 
   return total <= lds_words ? static_cast<uint32_t>(total) : 0;
 }
 
+// Private LDS copies: each workgroup sizes the filters (the size step;
+// workgroup 0 records the counts), sets the bits of its rows in its copies
+// and stores them at partials + blockIdx.x * copy_words. The launch makes
+// sure every filter's capacity fits in copy_words together.
 template <int B, int K>
 __global__ void __launch_bounds__(kWideThreads)
-    k_build_lds(FilterSet fs, AppendSet app, uint32_t k, uint32_t lg_rt, uint64_t n_rows,
-                const uint64_t *__restrict__ bitmap, uint32_t seg_words, uint32_t *__restrict__ partials,
-                uint32_t lds_words, uint32_t *status) {
+    k_build_lds(FilterSet fs, AppendSet app, uint32_t k, uint32_t lg_rt, uint32_t bits_per_key,
+                const uint64_t *count, uint64_t n_rows, const uint64_t *__restrict__ bitmap, uint32_t seg_words,
+                uint32_t *__restrict__ partials, uint32_t copy_words, uint32_t *status) {
   extern __shared__ __align__(16) uint32_t lds[];
-  if (build_pruned(fs)) return;
   const uint32_t lg = block_log2<B>(lg_rt);
-  const uint32_t total = lds_total(fs, lg, lds_words);
-  if (total == 0) {
-    // Too large for LDS: insert in place with global atomics.
-    for (uint32_t i = 0; i < fs.n; i++) {
-      const FilterRef &f = fs.f[i];
-      const uint32_t nb = filter_blocks(f, lg, status);
-      uint32_t *words = f.words;
-      for_each_key<true>(f, app, n_rows, bitmap, seg_words, whole_grid(),
-                         [&](uint32_t h1, uint32_t h2) { insert_bits<K>(words, nb, k, h1, h2, lg); });
-    }
-    return;
-  }
+  uint64_t n_sel;
+  if (!size_step(fs, lg, bits_per_key, count, n_rows, blockIdx.x == 0 && threadIdx.x == 0, status, n_sel)) return;
+  uint32_t total = 0;
+  for (uint32_t i = 0; i < fs.n; i++) total += sized_blocks(fs.f[i], lg, bits_per_key, n_sel) << (lg - 5);
   for (uint32_t j = threadIdx.x; j < total; j += blockDim.x) lds[j] = 0;
   __syncthreads();
   uint32_t off = 0;
   for (uint32_t i = 0; i < fs.n; i++) {
     const FilterRef &f = fs.f[i];
-    const uint32_t nb = filter_blocks(f, lg, status);
+    const uint32_t nb = sized_blocks(f, lg, bits_per_key, n_sel);
     uint32_t *mine = lds + off;
     for_each_key<true>(f, app, n_rows, bitmap, seg_words, whole_grid(),
                        [&](uint32_t h1, uint32_t h2) { insert_lds<K>(mine, nb, k, h1, h2, lg); });
     off += nb << (lg - 5);
   }
   __syncthreads();
-  uint32_t *out = partials + static_cast<uint64_t>(blockIdx.x) * lds_words;
+  uint32_t *out = partials + static_cast<uint64_t>(blockIdx.x) * copy_words;
   for (uint32_t j = threadIdx.x; j < total; j += blockDim.x) out[j] = lds[j];
 }
 
@@ -126,6 +130,43 @@ uint64_t build_lds_words() {
   return (static_cast<uint64_t>(device_info().max_lds_block) - 1024) / 4;
 }
 
+// The one-launch build of a small table: the size step's work (the pruned
+// marker, each filter's block count from the selected count, the overflow
+// status), then every filter built in LDS (their capacities fit) and stored
+// whole, so nothing has to be cleared first.
+template <int B, int K>
+__global__ void __launch_bounds__(kWideThreads)
+    k_build_one(FilterSet fs, AppendSet app, uint32_t k, uint32_t lg_rt, uint32_t bits_per_key,
+                const uint64_t *count, uint64_t n_rows, const uint64_t *__restrict__ bitmap, uint32_t seg_words,
+                uint32_t *status) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const uint32_t lg = block_log2<B>(lg_rt);
+  uint64_t n_sel;
+  if (!size_step(fs, lg, bits_per_key, count, n_rows, threadIdx.x == 0, status, n_sel)) return;
+  uint32_t total = 0;
+  for (uint32_t i = 0; i < fs.n; i++) total += sized_blocks(fs.f[i], lg, bits_per_key, n_sel) << (lg - 5);
+  for (uint32_t j = threadIdx.x; j < total; j += blockDim.x) lds[j] = 0;
+  __syncthreads();
+  uint32_t off = 0;
+  for (uint32_t i = 0; i < fs.n; i++) {
+    const FilterRef &f = fs.f[i];
+    const uint32_t nb = sized_blocks(f, lg, bits_per_key, n_sel);
+    uint32_t *mine = lds + off;
+    for_each_key<true>(f, app, n_rows, bitmap, seg_words, whole_grid(),
+                       [&](uint32_t h1, uint32_t h2) { insert_lds<K>(mine, nb, k, h1, h2, lg); });
+    off += nb << (lg - 5);
+  }
+  __syncthreads();
+  off = 0;
+  for (uint32_t i = 0; i < fs.n; i++) {
+    const FilterRef &f = fs.f[i];
+    const uint32_t n = sized_blocks(f, lg, bits_per_key, n_sel) << (lg - 5);
+    uint32_t *words = f.words;
+    for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) words[j] = lds[off + j];
+    off += n;
+  }
+}
+
 hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, const FilterSet &fs,
                         uint64_t n_rows, const uint64_t *bitmap, const uint64_t *count, const BuildScratch *scratch,
                         const AppendSet *app, uint32_t *status, hipStream_t s) {
@@ -144,20 +185,36 @@ hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, 
   const uint64_t lds_words = build_lds_words();
   uint64_t cap_words = 0;
   for (uint32_t i = 0; i < fs.n; i++) cap_words += fs.f[i].cap_words;
-  // Which path: private LDS copies when all filters surely fit in LDS, the
-  // partitioned build when the caller gave its buffers, else atomics.
-  enum { kLds, kPart, kAtomic } path = kAtomic;
-  if (scratch && scratch->copies && cap_words <= lds_words) path = kLds;
+  // Which path: when all filters surely fit in LDS, one workgroup for a
+  // small table, else private LDS copies; the partitioned build when the
+  // caller gave its buffers; else atomics.
+  enum { kOne, kLds, kPart, kAtomic } path = kAtomic;
+  if (cap_words <= lds_words && n_words <= kOneGroupWords) path = kOne;
+  else if (scratch && scratch->copies && cap_words <= lds_words) path = kLds;
   else if (scratch && scratch->entries && scratch->entries_cap) path = kPart;
-  // PT_BUILD_PATH=atomic|part (testing): take that path where it is allowed.
+  // PT_BUILD_PATH=atomic|lds|part (testing): take that path where it is allowed.
   if (const char *force = std::getenv("PT_BUILD_PATH")) {
     if (std::strcmp(force, "atomic") == 0) path = kAtomic;
+    else if (std::strcmp(force, "lds") == 0 && scratch && scratch->copies && cap_words <= lds_words) path = kLds;
     else if (std::strcmp(force, "part") == 0 && scratch && scratch->entries && scratch->entries_cap) path = kPart;
   }
 
-  hipError_t e = launch_size(block_bits, bits_per_key, fs, count, n_rows, path == kPart ? scratch->entries_cap : 0,
-                             status, s);
-  if (e != hipSuccess || n_words == 0) return e;
+  hipError_t e = hipSuccess;
+  if (path == kOne) {
+    auto kern = (block_bits == 512 && k == 3) ? k_build_one<512, 3> : k_build_one<0, 0>;
+    e = allow_lds(reinterpret_cast<const void *>(kern), cap_words * 4);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(kWideThreads), cap_words * 4, s, fs, a, k, lg, bits_per_key, count,
+                       n_rows, bitmap, seg_words, status);
+    return hipGetLastError();
+  }
+  // The partitioned and LDS-copy builds do the size step in their first
+  // kernel.
+  if (path == kAtomic || n_words == 0) {
+    e = launch_size(block_bits, bits_per_key, fs, count, n_rows, path == kPart ? scratch->entries_cap : 0, status,
+                    s);
+    if (e != hipSuccess || n_words == 0) return e;
+  }
 
   if (path == kPart)
     return launch_part_build(block_bits, k, bits_per_key, fs, n_rows, bitmap, count, *scratch, a, seg_words, status,
@@ -185,8 +242,8 @@ hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, 
   auto kern = (block_bits == 512 && k == 3) ? k_build_lds<512, 3> : k_build_lds<0, 0>;
   e = allow_lds(reinterpret_cast<const void *>(kern), copy_words * 4);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(n_parts), dim3(kWideThreads), copy_words * 4, s, fs, a, k, lg, n_rows, bitmap,
-                     seg_words, scratch->copies, cw, status);
+  hipLaunchKernelGGL(kern, dim3(n_parts), dim3(kWideThreads), copy_words * 4, s, fs, a, k, lg, bits_per_key, count,
+                     n_rows, bitmap, seg_words, scratch->copies, cw, status);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   uint64_t gx = (copy_words + kWave - 1) / kWave;

@@ -1,23 +1,40 @@
 // k_part.hip - partitioned build of Bloom filters too large for LDS: the
-// count, scan, scatter and fill kernels of one table's build (their bodies
-// and the scheme are in part_impl.hpp). No step needs a global atomic:
-// device-scope atomics bypass the per-XCD L2 on this chip, while every tile
-// here is written by one workgroup.
+// count (with the size step), scan, scatter and fill kernels of one table's
+// build (their bodies and the scheme are in part_impl.hpp). No step needs a
+// global atomic: device-scope atomics bypass the per-XCD L2 on this chip,
+// while every tile here is written by one workgroup.
 #include "part_impl.hpp"
 
 namespace pt {
 
 namespace {
 
+// The count kernel also does the size step: workgroup 0 records the
+// pruned marker or each filter's block count (from the selected count) and
+// the overflow status. When the plan does not fit, the filters are cleared
+// here instead of counted: the scatter then inserts in place with global
+// atomics.
 template <int B>
 __global__ void __launch_bounds__(kWideThreads)
     k_part_count(FilterSet fs, AppendSet app, uint32_t lg_rt, uint32_t bits_per_key, const uint64_t *count,
                  uint64_t n_rows, const uint64_t *__restrict__ bitmap, uint32_t seg_words, uint64_t entries_cap,
-                 uint32_t *__restrict__ hist) {
-  if (build_pruned(fs)) return;
-  part_count_body<true>(fs, app, block_log2<B>(lg_rt), bits_per_key, count, n_rows, bitmap, seg_words, entries_cap,
-                        hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, false, kTargetBuckets,
-                        whole_grid());
+                 uint32_t *__restrict__ hist, uint32_t *status) {
+  const uint32_t lg = block_log2<B>(lg_rt);
+  uint64_t n_sel;
+  if (!size_step(fs, lg, bits_per_key, count, n_rows, blockIdx.x == 0 && threadIdx.x == 0, status, n_sel)) return;
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, true);
+  if (!geo.ok) {
+    for (uint32_t i = 0; i < fs.n; i++) {
+      const FilterRef &f = fs.f[i];
+      const uint64_t n = static_cast<uint64_t>(sized_blocks(f, lg, bits_per_key, n_sel)) << (lg - 5);
+      for (uint64_t j = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; j < n;
+           j += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        f.words[j] = 0;
+    }
+    return;
+  }
+  part_count_body<true>(fs, app, lg, bits_per_key, count, n_rows, bitmap, seg_words, entries_cap,
+                        hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, true, kTargetBuckets, whole_grid());
 }
 
 // Exclusive scan of hist[g][b] over the n_groups workgroups for every
@@ -147,7 +164,7 @@ hipError_t launch_part_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_
   if (e == hipSuccess) e = allow_lds(reinterpret_cast<const void *>(fill_k), tile_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(count_k, dim3(n_groups), dim3(kWideThreads), hist_bytes, s, fs, a, lg, bits_per_key, count,
-                     n_rows, bitmap, seg_words, entries_cap, scratch.hist);
+                     n_rows, bitmap, seg_words, entries_cap, scratch.hist, status);
   hipLaunchKernelGGL(k_part_scan_groups, dim3(scan_grid ? scan_grid : 1), dim3(kWideThreads), 0, s, fs, lg,
                      bits_per_key, count, n_rows, entries_cap, scratch.hist, n_groups, scratch.totals);
   hipLaunchKernelGGL(k_part_scan_buckets, dim3(1), dim3(kWideThreads), 0, s, fs, lg, bits_per_key, count, n_rows,

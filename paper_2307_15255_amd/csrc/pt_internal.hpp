@@ -184,9 +184,10 @@ hipError_t launch_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, 
                         const BuildScratch *scratch, const AppendSet *app, uint32_t *status, hipStream_t s);
 // Words of LDS one build workgroup uses for its private filter copies.
 uint64_t build_lds_words();
-// Partitioned build of filters too large for LDS (sized and not zeroed
-// beforehand by launch_size); falls back to global atomics in place when
-// the plan does not fit the scratch (then the filters must be zeroed).
+// Partitioned build of filters too large for LDS. Its count kernel sizes
+// the filters from *count (the size step); when the plan does not fit the
+// scratch it clears them instead, and the scatter inserts in place with
+// global atomics.
 hipError_t launch_part_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_key, const FilterSet &fs,
                              uint64_t n_rows, const uint64_t *bitmap, const uint64_t *count,
                              const BuildScratch &scratch, const AppendSet &app, uint32_t seg_words,

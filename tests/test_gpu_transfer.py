@@ -171,12 +171,13 @@ def test_append_and_rescan_agree(pt, flags, n_fact):
         check_transfer(pt, W.tiny_random(np.random.default_rng(9100 + s), SHAPES[s]), flags=flags)
 
 
-@pytest.mark.parametrize("path,max_entries", [("atomic", None), ("part", None), ("part", "1000")])
+@pytest.mark.parametrize("path,max_entries", [("atomic", None), ("lds", None), ("part", None), ("part", "1000")])
 def test_build_paths(pt, monkeypatch, path, max_entries):
-    """Every build path - per-workgroup LDS copies (the default for small
-    filters), the partitioned tile build, and in-place atomic OR (forced, or
-    the partitioned build's fallback when its entry buffer is too small) -
-    writes the same filter words."""
+    """Every build path - one workgroup for a small table (the default when
+    its filters fit in LDS), per-workgroup LDS copies (the default for larger
+    tables whose filters fit), the partitioned tile build, and in-place
+    atomic OR (forced, or the partitioned build's fallback when its entry
+    buffer is too small) - writes the same filter words."""
     monkeypatch.setenv("PT_BUILD_PATH", path)
     if max_entries:
         monkeypatch.setenv("PT_MAX_ENTRIES", max_entries)
