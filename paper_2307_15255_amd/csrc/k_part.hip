@@ -78,36 +78,57 @@ __global__ void __launch_bounds__(kWideThreads)
   }
 }
 
-// starts[b] = sum of totals[0..b) for every bucket, starts[buckets] = all.
-__global__ void __launch_bounds__(kWideThreads)
-    k_part_scan_buckets(FilterSet fs, uint32_t lg, uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
-                        uint64_t entries_cap, const uint64_t *__restrict__ totals, uint64_t *__restrict__ starts) {
-  __shared__ uint64_t s[kWideThreads];
-  if (build_pruned(fs)) return;
-  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false);
-  if (!geo.ok) return;
-  uint64_t carry = 0;
-  for (uint32_t base = 0; base < geo.buckets; base += blockDim.x) {
-    const uint32_t b = base + threadIdx.x;
-    const uint64_t v = b < geo.buckets ? totals[b] : 0;
-    uint64_t total;
-    const uint64_t ex = block_exclusive_scan(v, s, total);
-    if (b < geo.buckets) starts[b] = carry + ex;
-    carry += total;
-  }
-  if (threadIdx.x == 0) starts[geo.buckets] = carry;
-}
-
+// Every workgroup first turns the bucket totals into the buckets' first
+// entries itself (an exclusive scan, 1024 buckets per round: lane shuffles
+// within a wave, the wave sums through LDS) and keeps them as its cursors;
+// workgroup 0 also stores them, with starts[buckets] = all, for the fill.
+// Redoing the scan in each workgroup costs less than a launch of its own.
 template <int B, int K>
 __global__ void __launch_bounds__(kWideThreads)
     k_part_scatter(FilterSet fs, AppendSet app, uint32_t k, uint32_t lg_rt, uint32_t bits_per_key,
                    const uint64_t *count, uint64_t n_rows, const uint64_t *__restrict__ bitmap, uint32_t seg_words,
-                   uint64_t entries_cap, const uint32_t *__restrict__ hist, const uint64_t *__restrict__ starts,
-                   uint32_t *__restrict__ entries, uint32_t *status, uint64_t lds_bytes) {
+                   uint64_t entries_cap, const uint32_t *__restrict__ hist, const uint64_t *__restrict__ totals,
+                   uint64_t *__restrict__ starts, uint32_t *__restrict__ entries, uint32_t *status,
+                   uint64_t lds_bytes) {
+  constexpr uint32_t kWaves = kWideThreads / kWave;
+  extern __shared__ __align__(16) uint64_t s_cur[];
+  __shared__ uint64_t s_wsum[kWaves];
   if (build_pruned(fs)) return;
-  part_scatter_body<true, K>(fs, app, k, block_log2<B>(lg_rt), bits_per_key, count, n_rows, bitmap, seg_words,
-                             entries_cap, hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, starts, entries,
-                             status, false, kTargetBuckets, whole_grid(), lds_bytes);
+  const uint32_t lg = block_log2<B>(lg_rt);
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false);
+  if (geo.ok) {
+    const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < geo.buckets; base += blockDim.x) {
+      const uint32_t b = base + threadIdx.x;
+      const uint64_t v = b < geo.buckets ? totals[b] : 0;
+      uint64_t incl = v;
+#pragma unroll
+      for (uint32_t d = 1; d < kWave; d <<= 1) {
+        const uint64_t t = __shfl_up(static_cast<unsigned long long>(incl), d, kWave);
+        if (lane >= d) incl += t;
+      }
+      if (lane == kWave - 1) s_wsum[wv] = incl;
+      __syncthreads();
+      uint64_t before = 0, all = 0;
+      for (uint32_t w = 0; w < kWaves; w++) {
+        const uint64_t ws = s_wsum[w];
+        before += w < wv ? ws : 0;
+        all += ws;
+      }
+      if (b < geo.buckets) {
+        const uint64_t ex = carry + before + incl - v;
+        s_cur[b] = ex;
+        if (blockIdx.x == 0) starts[b] = ex;
+      }
+      carry += all;
+      __syncthreads();
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) starts[geo.buckets] = carry;
+  }
+  part_scatter_body<true, K>(fs, app, k, lg, bits_per_key, count, n_rows, bitmap, seg_words, entries_cap,
+                             hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, nullptr, entries, status, false,
+                             kTargetBuckets, whole_grid(), lds_bytes);
 }
 
 template <int B, int K>
@@ -167,11 +188,9 @@ hipError_t launch_part_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_
                      n_rows, bitmap, seg_words, entries_cap, scratch.hist, status);
   hipLaunchKernelGGL(k_part_scan_groups, dim3(scan_grid ? scan_grid : 1), dim3(kWideThreads), 0, s, fs, lg,
                      bits_per_key, count, n_rows, entries_cap, scratch.hist, n_groups, scratch.totals);
-  hipLaunchKernelGGL(k_part_scan_buckets, dim3(1), dim3(kWideThreads), 0, s, fs, lg, bits_per_key, count, n_rows,
-                     entries_cap, scratch.totals, scratch.starts);
   hipLaunchKernelGGL(scatter_k, dim3(n_groups), dim3(kWideThreads), cursor_bytes, s, fs, a, k, lg, bits_per_key,
-                     count, n_rows, bitmap, seg_words, entries_cap, scratch.hist, scratch.starts, scratch.entries,
-                     status, cursor_bytes);
+                     count, n_rows, bitmap, seg_words, entries_cap, scratch.hist, scratch.totals, scratch.starts,
+                     scratch.entries, status, cursor_bytes);
   hipLaunchKernelGGL(fill_k, dim3(static_cast<uint32_t>(fill_grid ? fill_grid : 1)), dim3(kWideThreads), tile_bytes,
                      s, fs, k, lg, bits_per_key, count, n_rows, entries_cap, scratch.starts, scratch.entries);
   return hipGetLastError();

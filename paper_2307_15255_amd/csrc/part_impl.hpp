@@ -92,7 +92,8 @@ constexpr uint32_t kStagedBucketBytes = 8 + 4 + 4 + 4 * kStageEntries;
 constexpr uint32_t kStageMinBuckets = 64;
 
 // Writes this workgroup's entries at its ranges (hist_row: its exclusive
-// offsets within each bucket, starts: the buckets' first entries). When the
+// offsets within each bucket, starts: the buckets' first entries, or NULL
+// when the caller left them in the cursor array s_cur). When the
 // plan does not fit the entry buffer, inserts in place with global atomics
 // instead (the filters were zeroed in that case).
 //
@@ -132,7 +133,7 @@ __device__ __forceinline__ void part_scatter_body(const FilterSet &fs, const App
   uint32_t *s_wrote = s_claim + nbk;                               // [nbk]: slots written
   uint32_t *s_stage = s_wrote + nbk;                               // [nbk][kStageEntries]
   for (uint32_t b = threadIdx.x; b < nbk; b += blockDim.x) {
-    s_cur[b] = starts[b] + hist_row[b];
+    s_cur[b] = (starts ? starts[b] : s_cur[b]) + hist_row[b];
     if (staged) s_claim[b] = s_wrote[b] = 0;
   }
   __syncthreads();
