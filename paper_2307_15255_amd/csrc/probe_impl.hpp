@@ -95,7 +95,13 @@ __device__ __forceinline__ void load_group(const void *col, uint64_t base, uint3
   }
 }
 
-template <int K, bool KEY64, bool STAGED, bool APPEND, int G>
+// SPARSE (int32 keys, a bitmap that may hold few rows and a first filter in
+// global memory): a row that is not selected reads the same filter words as
+// every other such row, so the wave's reads for them fall on one line
+// instead of one line each. (The int64 kernels are left without this loop:
+// their register allocation, already at the limit, made their other loops
+// slower with it.)
+template <int K, bool KEY64, bool STAGED, bool APPEND, int G, bool SPARSE = false>
 __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const uint32_t (&lds_off)[kMaxProbe],
                                               uint32_t n_f, uint32_t k, uint32_t lg, uint64_t n_rows,
                                               uint64_t *bitmap, uint32_t input_all, const uint32_t *lds_filters,
@@ -164,6 +170,9 @@ __device__ __forceinline__ int64_t probe_loop(const Slot (&sl)[kMaxProbe], const
             hash_key((static_cast<uint64_t>(hi[u]) << 32) | lo[u], h1, h2);
           else
             hash_key32(lo[u], h1, h2);
+          if constexpr (SPARSE) {
+            if (!((word[j] >> lane) & 1)) h1 = h2 = 0;
+          }
           ok[j] = slot_has<K, STAGED>(sl[0], lds_filters + lds_off[0], h1, h2, k, lg);
         }
       }
@@ -497,9 +506,12 @@ __device__ __forceinline__ void probe_body(const FilterSet &fs, uint32_t k, uint
       if (staged)
         cnt = probe_loop<K, false, true, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice,
                                                  app, app_slot, vg);
-      else
+      else if (input_all)
         cnt = probe_loop<K, false, false, APPEND, G>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds, slice,
                                                   app, app_slot, vg);
+      else
+        cnt = probe_loop<K, false, false, APPEND, G, true>(sl, off, n_f, k, lg, n_rows, bitmap, input_all, lds,
+                                                        slice, app, app_slot, vg);
     }
   }
   block_count_add(cnt, &s_cnt, count);
