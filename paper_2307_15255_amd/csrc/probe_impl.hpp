@@ -533,7 +533,7 @@ hipError_t launch_probe_kernel(const ProbeLaunch &pl, hipStream_t s) {
   auto launch = [&](auto kern) -> hipError_t {
     hipError_t e = allow_lds(reinterpret_cast<const void *>(kern), pl.lds_bytes);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(pl.grid), dim3(kProbeThreads), pl.lds_bytes, s, pl.fs, pl.k, pl.lg, pl.n_rows,
+    hipLaunchKernelGGL(kern, dim3(pl.grid), dim3(pl.threads), pl.lds_bytes, s, pl.fs, pl.k, pl.lg, pl.n_rows,
                        pl.bitmap, pl.count, pl.lds_filter_words, pl.input_all, pl.keep_order, pl.status, pl.app);
     return hipGetLastError();
   };

@@ -167,6 +167,7 @@ struct ProbeLaunch {
   uint32_t *status;
   AppendSet app;
   uint32_t grid;
+  uint32_t threads;  // per workgroup: kProbeThreads, or fewer for a small table
   uint64_t lds_bytes;
 };
 // One probe kernel, specialised for B = 512 and k = 3 (k_probe_512.hip) or
