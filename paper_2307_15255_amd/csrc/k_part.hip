@@ -3,25 +3,75 @@
 // build (their bodies and the scheme are in part_impl.hpp). No step needs a
 // global atomic: device-scope atomics bypass the per-XCD L2 on this chip,
 // while every tile here is written by one workgroup.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
 #include "part_impl.hpp"
 
 namespace pt {
 
 namespace {
 
+// LDS words of the private copies a partitioned build falls back to when
+// its filters turn out small: 64 KB, so that two count workgroups still fit
+// on a CU.
+constexpr uint32_t kCopyWords = 16384;
+
+// Filters sized for a partitioned build (the capacity of a large table)
+// may turn out small once the selected count is known. When the recorded
+// sizes fit in copy_words together (0: no room for copies), the build runs
+// as private LDS copies instead: the count kernel sets each workgroup's
+// rows' bits in its copy, the scan kernel ORs the copies into the filters,
+// and the scatter and fill kernels have nothing to do. Returns the words
+// of the filters in that case, else 0.
+__device__ __forceinline__ uint32_t copies_total(const FilterSet &fs, uint32_t lg, uint32_t copy_words) {
+  if (copy_words == 0) return 0;
+  uint64_t t = 0;
+  for (uint32_t i = 0; i < fs.n; i++)
+    t += static_cast<uint64_t>(clamp_blocks(*fs.f[i].nb, fs.f[i].cap_words >> (lg - 5), nullptr)) << (lg - 5);
+  return t <= copy_words ? static_cast<uint32_t>(t) : 0;
+}
+
 // The count kernel also does the size step: workgroup 0 records the
 // pruned marker or each filter's block count (from the selected count) and
-// the overflow status. When the plan does not fit, the filters are cleared
-// here instead of counted: the scatter then inserts in place with global
+// the overflow status. Small filters are built as LDS copies (see
+// copies_total). When the plan does not fit, the filters are cleared here
+// instead of counted: the scatter then inserts in place with global
 // atomics.
-template <int B>
+template <int B, int K>
 __global__ void __launch_bounds__(kWideThreads)
-    k_part_count(FilterSet fs, AppendSet app, uint32_t lg_rt, uint32_t bits_per_key, const uint64_t *count,
-                 uint64_t n_rows, const uint64_t *__restrict__ bitmap, uint32_t seg_words, uint64_t entries_cap,
-                 uint32_t *__restrict__ hist, uint32_t *status) {
+    k_part_count(FilterSet fs, AppendSet app, uint32_t k, uint32_t lg_rt, uint32_t bits_per_key,
+                 const uint64_t *count, uint64_t n_rows, const uint64_t *__restrict__ bitmap, uint32_t seg_words,
+                 uint64_t entries_cap, uint32_t *__restrict__ hist, uint32_t *__restrict__ copies,
+                 uint32_t copy_words, uint32_t *status) {
+  extern __shared__ __align__(16) uint32_t s_copy[];
   const uint32_t lg = block_log2<B>(lg_rt);
   uint64_t n_sel;
   if (!size_step(fs, lg, bits_per_key, count, n_rows, blockIdx.x == 0 && threadIdx.x == 0, status, n_sel)) return;
+  if (copy_words) {
+    // the sizes workgroup 0 records, computed here (they are not stored yet)
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < fs.n; i++) total += static_cast<uint64_t>(sized_blocks(fs.f[i], lg, bits_per_key, n_sel))
+                                                 << (lg - 5);
+    if (total <= copy_words) {
+      for (uint32_t j = threadIdx.x; j < total; j += blockDim.x) s_copy[j] = 0;
+      __syncthreads();
+      uint32_t off = 0;
+      for (uint32_t i = 0; i < fs.n; i++) {
+        const FilterRef &f = fs.f[i];
+        const uint32_t nb = sized_blocks(f, lg, bits_per_key, n_sel);
+        uint32_t *mine = s_copy + off;
+        for_each_key<true>(f, app, n_rows, bitmap, seg_words, whole_grid(),
+                           [&](uint32_t h1, uint32_t h2) { insert_lds<K>(mine, nb, k, h1, h2, lg); });
+        off += nb << (lg - 5);
+      }
+      __syncthreads();
+      uint32_t *out = copies + static_cast<uint64_t>(blockIdx.x) * copy_words;
+      for (uint32_t j = threadIdx.x; j < total; j += blockDim.x) out[j] = s_copy[j];
+      return;
+    }
+  }
   const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, true);
   if (!geo.ok) {
     for (uint32_t i = 0; i < fs.n; i++) {
@@ -42,17 +92,47 @@ __global__ void __launch_bounds__(kWideThreads)
 // 64 buckets at a time (lane = bucket, so every read covers 64 consecutive
 // counters); wave w sums its share of the groups, the waves' sums are
 // combined in LDS, and each wave rewrites its share as running offsets.
+// When the filters were built as copies, it ORs the n_groups copies into
+// them instead, 64 words per workgroup step (wave w ORs every 16th copy,
+// the waves' results are combined in LDS).
 __global__ void __launch_bounds__(kWideThreads)
     k_part_scan_groups(FilterSet fs, uint32_t lg, uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
                        uint64_t entries_cap, uint32_t *__restrict__ hist, uint32_t n_groups,
-                       uint64_t *__restrict__ totals) {
+                       uint64_t *__restrict__ totals, const uint32_t *__restrict__ copies, uint32_t copy_words) {
   constexpr uint32_t kWaves = kWideThreads / kWave;
   __shared__ uint64_t s_part[kWaves][kWave];
   if (build_pruned(fs)) return;
-  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false);
-  if (!geo.ok) return;
   const uint32_t lane = lane_id();
   const uint32_t wv = threadIdx.x / kWave;
+  const uint32_t total = copies_total(fs, lg, copy_words);
+  if (total) {
+    for (uint32_t base = blockIdx.x * kWave; base < total; base += gridDim.x * kWave) {
+      const uint32_t w = base + lane;
+      uint32_t v = 0;
+      if (w < total) {
+#pragma unroll 8
+        for (uint32_t g = wv; g < n_groups; g += kWaves) v |= copies[static_cast<uint64_t>(g) * copy_words + w];
+      }
+      s_part[wv][lane] = v;
+      __syncthreads();
+      if (wv == 0 && w < total) {
+        uint32_t r = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kWaves; q++) r |= static_cast<uint32_t>(s_part[q][lane]);
+        // word w of the concatenated filters
+        uint32_t off = 0;
+        for (uint32_t i = 0; i < fs.n; i++) {
+          const uint32_t n = clamp_blocks(*fs.f[i].nb, fs.f[i].cap_words >> (lg - 5), nullptr) << (lg - 5);
+          if (w >= off && w < off + n) fs.f[i].words[w - off] = r;
+          off += n;
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false);
+  if (!geo.ok) return;
   const uint32_t per = (n_groups + kWaves - 1) / kWaves;
   const uint32_t g0 = min(wv * per, n_groups), g1 = min(g0 + per, n_groups);
   for (uint32_t b0 = blockIdx.x * kWave; b0 < geo.buckets; b0 += gridDim.x * kWave) {
@@ -89,12 +169,12 @@ __global__ void __launch_bounds__(kWideThreads)
                    const uint64_t *count, uint64_t n_rows, const uint64_t *__restrict__ bitmap, uint32_t seg_words,
                    uint64_t entries_cap, const uint32_t *__restrict__ hist, const uint64_t *__restrict__ totals,
                    uint64_t *__restrict__ starts, uint32_t *__restrict__ entries, uint32_t *status,
-                   uint64_t lds_bytes) {
+                   uint64_t lds_bytes, uint32_t copy_words) {
   constexpr uint32_t kWaves = kWideThreads / kWave;
   extern __shared__ __align__(16) uint64_t s_cur[];
   __shared__ uint64_t s_wsum[kWaves];
-  if (build_pruned(fs)) return;
   const uint32_t lg = block_log2<B>(lg_rt);
+  if (build_pruned(fs) || copies_total(fs, lg, copy_words)) return;
   const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false);
   if (geo.ok) {
     const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
@@ -135,10 +215,11 @@ template <int B, int K>
 __global__ void __launch_bounds__(kWideThreads)
     k_part_fill(FilterSet fs, uint32_t k, uint32_t lg_rt, uint32_t bits_per_key, const uint64_t *count,
                 uint64_t n_rows, uint64_t entries_cap, const uint64_t *__restrict__ starts,
-                const uint32_t *__restrict__ entries) {
-  if (build_pruned(fs)) return;
-  part_fill_body<K>(fs, k, block_log2<B>(lg_rt), bits_per_key, count, n_rows, entries_cap, starts, entries,
-                    blockIdx.x, gridDim.x, false, kTargetBuckets);
+                const uint32_t *__restrict__ entries, uint32_t copy_words) {
+  const uint32_t lg = block_log2<B>(lg_rt);
+  if (build_pruned(fs) || copies_total(fs, lg, copy_words)) return;
+  part_fill_body<K>(fs, k, lg, bits_per_key, count, n_rows, entries_cap, starts, entries, blockIdx.x, gridDim.x,
+                    false, kTargetBuckets);
 }
 
 }  // namespace
@@ -171,7 +252,15 @@ hipError_t launch_part_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_
   uint64_t fill_grid = static_cast<uint64_t>(device_info().n_cu) * 2;
   if (fill_grid > max_buckets) fill_grid = max_buckets;
   const bool spec = block_bits == 512 && k == 3;
-  auto count_k = spec ? k_part_count<512> : k_part_count<0>;
+  auto count_k = spec ? k_part_count<512, 3> : k_part_count<0, 0>;
+  // Room for the small-filter copies: kCopyWords per count workgroup
+  // (PT_BUILD_PATH=part, for testing: always partition).
+  const char *force = std::getenv("PT_BUILD_PATH");
+  const bool force_part = force && std::strcmp(force, "part") == 0;
+  const uint32_t copy_words =
+      !force_part && scratch.copies && scratch.copies_words >= static_cast<uint64_t>(n_groups) * kCopyWords
+          ? kCopyWords
+          : 0;
   auto scatter_k = spec ? k_part_scatter<512, 3> : k_part_scatter<0, 0>;
   auto fill_k = spec ? k_part_fill<512, 3> : k_part_fill<0, 0>;
   const uint64_t hist_bytes = max_buckets * 4;
@@ -180,19 +269,24 @@ hipError_t launch_part_build(uint32_t block_bits, uint32_t k, uint32_t bits_per_
   const uint64_t staged_bytes = max_buckets * kStagedBucketBytes;
   const uint64_t cursor_bytes = staged_bytes <= lds_avail ? staged_bytes : max_buckets * 8;
   const uint64_t tile_bytes = static_cast<uint64_t>(kTileWords) * 4;
-  hipError_t e = allow_lds(reinterpret_cast<const void *>(count_k), hist_bytes);
+  const uint64_t count_bytes = std::max<uint64_t>(hist_bytes, static_cast<uint64_t>(copy_words) * 4);
+  // the scan kernel ORs up to copy_words words of copies, 64 per workgroup
+  const uint32_t scan_blocks = std::max<uint32_t>(scan_grid, copy_words / kWave);
+  hipError_t e = allow_lds(reinterpret_cast<const void *>(count_k), count_bytes);
   if (e == hipSuccess) e = allow_lds(reinterpret_cast<const void *>(scatter_k), cursor_bytes);
   if (e == hipSuccess) e = allow_lds(reinterpret_cast<const void *>(fill_k), tile_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(count_k, dim3(n_groups), dim3(kWideThreads), hist_bytes, s, fs, a, lg, bits_per_key, count,
-                     n_rows, bitmap, seg_words, entries_cap, scratch.hist, status);
-  hipLaunchKernelGGL(k_part_scan_groups, dim3(scan_grid ? scan_grid : 1), dim3(kWideThreads), 0, s, fs, lg,
-                     bits_per_key, count, n_rows, entries_cap, scratch.hist, n_groups, scratch.totals);
+  hipLaunchKernelGGL(count_k, dim3(n_groups), dim3(kWideThreads), count_bytes, s, fs, a, k, lg, bits_per_key, count,
+                     n_rows, bitmap, seg_words, entries_cap, scratch.hist, scratch.copies, copy_words, status);
+  hipLaunchKernelGGL(k_part_scan_groups, dim3(scan_blocks ? scan_blocks : 1), dim3(kWideThreads), 0, s, fs, lg,
+                     bits_per_key, count, n_rows, entries_cap, scratch.hist, n_groups, scratch.totals, scratch.copies,
+                     copy_words);
   hipLaunchKernelGGL(scatter_k, dim3(n_groups), dim3(kWideThreads), cursor_bytes, s, fs, a, k, lg, bits_per_key,
                      count, n_rows, bitmap, seg_words, entries_cap, scratch.hist, scratch.totals, scratch.starts,
-                     scratch.entries, status, cursor_bytes);
+                     scratch.entries, status, cursor_bytes, copy_words);
   hipLaunchKernelGGL(fill_k, dim3(static_cast<uint32_t>(fill_grid ? fill_grid : 1)), dim3(kWideThreads), tile_bytes,
-                     s, fs, k, lg, bits_per_key, count, n_rows, entries_cap, scratch.starts, scratch.entries);
+                     s, fs, k, lg, bits_per_key, count, n_rows, entries_cap, scratch.starts, scratch.entries,
+                     copy_words);
   return hipGetLastError();
 }
 

@@ -175,9 +175,10 @@ def test_append_and_rescan_agree(pt, flags, n_fact):
 def test_build_paths(pt, monkeypatch, path, max_entries):
     """Every build path - one workgroup for a small table (the default when
     its filters fit in LDS), per-workgroup LDS copies (the default for larger
-    tables whose filters fit), the partitioned tile build, and in-place
-    atomic OR (forced, or the partitioned build's fallback when its entry
-    buffer is too small) - writes the same filter words."""
+    tables whose filters fit, and for a large table whose selected rows make
+    small filters), the partitioned tile build (forced here for every size),
+    and in-place atomic OR (forced, or the partitioned build's fallback when
+    its entry buffer is too small) - writes the same filter words."""
     monkeypatch.setenv("PT_BUILD_PATH", path)
     if max_entries:
         monkeypatch.setenv("PT_MAX_ENTRIES", max_entries)
