@@ -210,9 +210,12 @@ __device__ __forceinline__ uint32_t part_blocks(const FilterRef &f, uint32_t lg,
 // target_buckets: how many (filter, tile) buckets the build aims for - many
 // for one large build that must fill the device by itself, few for the
 // builds of a batch, which fill it together (fewer, larger tiles).
+// min_tile_blocks: the smallest tile (fewer, larger buckets for a small
+// build: less to scan, more entries per fill workgroup).
 __device__ __forceinline__ PartGeo part_geo(const FilterSet &fs, uint32_t lg, uint32_t bits_per_key,
                                             const uint64_t *count, uint64_t n_rows, uint64_t entries_cap,
-                                            bool from_count, uint32_t target_buckets = kTargetBuckets) {
+                                            bool from_count, uint32_t target_buckets = kTargetBuckets,
+                                            uint32_t min_tile_blocks = 1) {
   PartGeo g{};
   g.n_sel = count ? *count : n_rows;
   uint64_t all_blocks = 0;
@@ -220,6 +223,7 @@ __device__ __forceinline__ PartGeo part_geo(const FilterSet &fs, uint32_t lg, ui
   // Tiles of at most 128 KB, small enough that the group has about
   // target_buckets of them (the fill step runs one workgroup per tile).
   uint64_t tb = (all_blocks + target_buckets - 1) / target_buckets;
+  if (tb < min_tile_blocks) tb = min_tile_blocks;
   const uint64_t max_tb = kTileWords >> (lg - 5);
   g.tile_blocks = static_cast<uint32_t>(tb < 1 ? 1 : (tb > max_tb ? max_tb : tb));
   uint64_t buckets = 0;

@@ -13,6 +13,10 @@ namespace pt {
 
 namespace {
 
+// Smallest tile of a single build: 8 KB (a 3 MB set of filters then has
+// about 370 buckets instead of 1024 tiles of 3 KB).
+constexpr uint32_t kMinTileWords = 2048;
+
 // LDS words of the private copies a partitioned build falls back to when
 // its filters turn out small: 64 KB, so that two count workgroups still fit
 // on a CU.
@@ -72,7 +76,8 @@ __global__ void __launch_bounds__(kWideThreads)
       return;
     }
   }
-  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, true);
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, true, kTargetBuckets,
+                                 kMinTileWords >> (lg - 5));
   if (!geo.ok) {
     for (uint32_t i = 0; i < fs.n; i++) {
       const FilterRef &f = fs.f[i];
@@ -84,7 +89,8 @@ __global__ void __launch_bounds__(kWideThreads)
     return;
   }
   part_count_body<true>(fs, app, lg, bits_per_key, count, n_rows, bitmap, seg_words, entries_cap,
-                        hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, true, kTargetBuckets, whole_grid());
+                        hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, true, kTargetBuckets, whole_grid(),
+                        kMinTileWords >> (lg - 5));
 }
 
 // Exclusive scan of hist[g][b] over the n_groups workgroups for every
@@ -131,7 +137,8 @@ __global__ void __launch_bounds__(kWideThreads)
     }
     return;
   }
-  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false);
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false, kTargetBuckets,
+                                 kMinTileWords >> (lg - 5));
   if (!geo.ok) return;
   const uint32_t per = (n_groups + kWaves - 1) / kWaves;
   const uint32_t g0 = min(wv * per, n_groups), g1 = min(g0 + per, n_groups);
@@ -175,7 +182,8 @@ __global__ void __launch_bounds__(kWideThreads)
   __shared__ uint64_t s_wsum[kWaves];
   const uint32_t lg = block_log2<B>(lg_rt);
   if (build_pruned(fs) || copies_total(fs, lg, copy_words)) return;
-  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false);
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false, kTargetBuckets,
+                                 kMinTileWords >> (lg - 5));
   if (geo.ok) {
     const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
     uint64_t carry = 0;
@@ -208,7 +216,7 @@ __global__ void __launch_bounds__(kWideThreads)
   }
   part_scatter_body<true, K>(fs, app, k, lg, bits_per_key, count, n_rows, bitmap, seg_words, entries_cap,
                              hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, nullptr, entries, status, false,
-                             kTargetBuckets, whole_grid(), lds_bytes);
+                             kTargetBuckets, whole_grid(), lds_bytes, kMinTileWords >> (lg - 5));
 }
 
 template <int B, int K>
@@ -219,7 +227,7 @@ __global__ void __launch_bounds__(kWideThreads)
   const uint32_t lg = block_log2<B>(lg_rt);
   if (build_pruned(fs) || copies_total(fs, lg, copy_words)) return;
   part_fill_body<K>(fs, k, lg, bits_per_key, count, n_rows, entries_cap, starts, entries, blockIdx.x, gridDim.x,
-                    false, kTargetBuckets);
+                    false, kTargetBuckets, kMinTileWords >> (lg - 5));
 }
 
 }  // namespace

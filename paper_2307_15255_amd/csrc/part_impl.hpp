@@ -62,9 +62,9 @@ __device__ __forceinline__ void part_count_body(const FilterSet &fs, const Appen
                                                 uint32_t bits_per_key, const uint64_t *count, uint64_t n_rows,
                                                 const uint64_t *bitmap, uint32_t seg_words, uint64_t entries_cap,
                                                 uint32_t *hist_row, bool from_count, uint32_t target,
-                                                const VGrid &vg) {
+                                                const VGrid &vg, uint32_t min_tile = 1) {
   extern __shared__ __align__(16) uint32_t s_hist[];
-  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, from_count, target);
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, from_count, target, min_tile);
   if (!geo.ok) return;
   for (uint32_t b = threadIdx.x; b < geo.buckets; b += blockDim.x) s_hist[b] = 0;
   __syncthreads();
@@ -113,9 +113,10 @@ __device__ __forceinline__ void part_scatter_body(const FilterSet &fs, const App
                                                   const uint64_t *bitmap, uint32_t seg_words, uint64_t entries_cap,
                                                   const uint32_t *hist_row, const uint64_t *starts,
                                                   uint32_t *entries, uint32_t *status, bool from_count,
-                                                  uint32_t target, const VGrid &vg, uint64_t lds_bytes = 0) {
+                                                  uint32_t target, const VGrid &vg, uint64_t lds_bytes = 0,
+                                                  uint32_t min_tile = 1) {
   extern __shared__ __align__(16) uint64_t s_cur[];
-  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, from_count, target);
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, from_count, target, min_tile);
   if (!geo.ok) {
     for (uint32_t i = 0; i < fs.n; i++) {
       const FilterRef &f = fs.f[i];
@@ -213,10 +214,11 @@ template <int K>
 __device__ __forceinline__ void part_fill_body(const FilterSet &fs, uint32_t k, uint32_t lg, uint32_t bits_per_key,
                                                const uint64_t *count, uint64_t n_rows, uint64_t entries_cap,
                                                const uint64_t *starts, const uint32_t *entries, uint32_t b_first,
-                                               uint32_t b_step, bool from_count, uint32_t target) {
+                                               uint32_t b_step, bool from_count, uint32_t target,
+                                               uint32_t min_tile = 1) {
   extern __shared__ __align__(16) uint32_t tile[];
   const uint32_t W = 1u << (lg - 5);
-  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, from_count, target);
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, from_count, target, min_tile);
   if (!geo.ok) return;
   const uint32_t tb = geo.tile_blocks;
   for (uint32_t b = b_first; b < geo.buckets; b += b_step) {
