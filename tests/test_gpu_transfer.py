@@ -190,6 +190,31 @@ def test_build_paths(pt, monkeypatch, path, max_entries):
     check_transfer(pt, W.star(seed=9, n_fact=300_000, dims=(60_000, 7_000, 500, 25), payload=0))
 
 
+@pytest.mark.parametrize("key64", [(), (True, True, False, False)])
+def test_small_filters_of_large_tables(pt, key64):
+    """Builds sized for the partitioned path by their table's rows: D0 keeps
+    2 % of 300 k rows (its filter fits the LDS copies the partitioned
+    kernels fall back to), D1 keeps 90 % of 250 k rows (partitioned), and
+    the fact table's backward filters are partitioned too; a 3 000-row
+    dimension takes the one-workgroup build. Every bitmap, count and filter
+    word equals the oracle's, with and without transfer path pruning (int32
+    keys, then int64 keys on the two large dimensions)."""
+    prob = W.star(seed=21, n_fact=400_000, dims=(300_000, 250_000, 3_000, 25), keeps=(0.02, 0.9, None, None),
+                  payload=0, key64=key64)
+    say("small filters of large tables", key64)
+    check_transfer(pt, prob)
+    say("small filters of large tables, pruned", key64)
+    dp = pt.DeviceProblem(prob)
+    tr = pt.Transfer(dp, pt.params(512, 3, 10, pt.PT_FLAG_PRUNE))
+    tr.run()
+    tr.check_status()
+    ref = oracle.transfer(prob, 512, 3, 10, prune=True)
+    counts = tr.counts.cpu().numpy()
+    for t in range(prob.n_tables):
+        assert_bitmaps_equal(tr.bitmap(t), ref.bitmaps[t], f"{prob.label} table {t}")
+        assert counts[t] == ref.counts[t], (prob.label, t)
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 def test_outer_join_edges(pt, shape):
     """Random graphs whose edges are inner, left, right or full outer joins
