@@ -9,8 +9,9 @@
 //   count    each workgroup walks its rows and histograms their bucket
 //            in LDS, then stores its histogram row;
 //   scan     per bucket, an exclusive scan over the workgroups' counts, then
-//            one scan over the bucket totals: every (workgroup, bucket) gets
-//            its own range of the entry buffer;
+//            one scan over the bucket totals (in the single-build kernels
+//            every scatter workgroup does this one itself): every
+//            (workgroup, bucket) gets its own range of the entry buffer;
 //   scatter  the same walk again (same grid, so the same rows per
 //            workgroup) writes each entry - block within the tile and H2 -
 //            at its range's next slot (LDS cursors); when the plan does not
