@@ -13,9 +13,27 @@ namespace pt {
 
 namespace {
 
-// Smallest tile of a single build: 8 KB (a 3 MB set of filters then has
-// about 370 buckets instead of 1024 tiles of 3 KB).
+// Smallest tile of a single build: 8 KB.
 constexpr uint32_t kMinTileWords = 2048;
+// A single build whose filters would take tiles of at most 32 KB at
+// kTargetBuckets aims for 256 buckets instead, one fill workgroup per CU
+// (the star's 3 MB of backward filters: 256 tiles of 12 KB rather than 372
+// of 8 KB, two rounds of fill workgroups); larger ones keep kTargetBuckets
+// (a 75 MB filter measured slower with 572 tiles of 128 KB than with 1024
+// of 73 KB).
+constexpr uint32_t kSmallBuildBuckets = 256;
+constexpr uint32_t kSmallBuildTileWords = 8192;
+
+// The bucket target of a single build, from its filters' block counts (as
+// sized from the selected count, or as recorded): the same in every kernel
+// of the build.
+__device__ __forceinline__ uint32_t single_target(const FilterSet &fs, uint32_t lg, uint32_t bits_per_key,
+                                                  uint64_t n_sel, bool from_count) {
+  uint64_t all = 0;
+  for (uint32_t i = 0; i < fs.n; i++) all += part_blocks(fs.f[i], lg, bits_per_key, n_sel, from_count);
+  return all <= static_cast<uint64_t>(kSmallBuildBuckets) * (kSmallBuildTileWords >> (lg - 5)) ? kSmallBuildBuckets
+                                                                                              : kTargetBuckets;
+}
 
 // LDS words of the private copies a partitioned build falls back to when
 // its filters turn out small: 64 KB, so that two count workgroups still fit
@@ -76,8 +94,9 @@ __global__ void __launch_bounds__(kWideThreads)
       return;
     }
   }
-  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, true, kTargetBuckets,
-                                 kMinTileWords >> (lg - 5));
+  const uint32_t target = single_target(fs, lg, bits_per_key, n_sel, true);
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, true, target,
+                               kMinTileWords >> (lg - 5));
   if (!geo.ok) {
     for (uint32_t i = 0; i < fs.n; i++) {
       const FilterRef &f = fs.f[i];
@@ -89,7 +108,7 @@ __global__ void __launch_bounds__(kWideThreads)
     return;
   }
   part_count_body<true>(fs, app, lg, bits_per_key, count, n_rows, bitmap, seg_words, entries_cap,
-                        hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, true, kTargetBuckets, whole_grid(),
+                        hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, true, target, whole_grid(),
                         kMinTileWords >> (lg - 5));
 }
 
@@ -137,8 +156,9 @@ __global__ void __launch_bounds__(kWideThreads)
     }
     return;
   }
-  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false, kTargetBuckets,
-                                 kMinTileWords >> (lg - 5));
+  const uint32_t target = single_target(fs, lg, bits_per_key, 0, false);
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false, target,
+                               kMinTileWords >> (lg - 5));
   if (!geo.ok) return;
   const uint32_t per = (n_groups + kWaves - 1) / kWaves;
   const uint32_t g0 = min(wv * per, n_groups), g1 = min(g0 + per, n_groups);
@@ -182,8 +202,9 @@ __global__ void __launch_bounds__(kWideThreads)
   __shared__ uint64_t s_wsum[kWaves];
   const uint32_t lg = block_log2<B>(lg_rt);
   if (build_pruned(fs) || copies_total(fs, lg, copy_words)) return;
-  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false, kTargetBuckets,
-                                 kMinTileWords >> (lg - 5));
+  const uint32_t target = single_target(fs, lg, bits_per_key, 0, false);
+  const PartGeo geo = part_geo(fs, lg, bits_per_key, count, n_rows, entries_cap, false, target,
+                               kMinTileWords >> (lg - 5));
   if (geo.ok) {
     const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
     uint64_t carry = 0;
@@ -216,7 +237,7 @@ __global__ void __launch_bounds__(kWideThreads)
   }
   part_scatter_body<true, K>(fs, app, k, lg, bits_per_key, count, n_rows, bitmap, seg_words, entries_cap,
                              hist + static_cast<uint64_t>(blockIdx.x) * kMaxBuckets, nullptr, entries, status, false,
-                             kTargetBuckets, whole_grid(), lds_bytes, kMinTileWords >> (lg - 5));
+                             target, whole_grid(), lds_bytes, kMinTileWords >> (lg - 5));
 }
 
 template <int B, int K>
@@ -227,7 +248,7 @@ __global__ void __launch_bounds__(kWideThreads)
   const uint32_t lg = block_log2<B>(lg_rt);
   if (build_pruned(fs) || copies_total(fs, lg, copy_words)) return;
   part_fill_body<K>(fs, k, lg, bits_per_key, count, n_rows, entries_cap, starts, entries, blockIdx.x, gridDim.x,
-                    false, kTargetBuckets, kMinTileWords >> (lg - 5));
+                    false, single_target(fs, lg, bits_per_key, 0, false), kMinTileWords >> (lg - 5));
 }
 
 }  // namespace

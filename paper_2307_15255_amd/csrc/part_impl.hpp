@@ -244,16 +244,21 @@ __device__ __forceinline__ void part_fill_body(const FilterSet &fs, uint32_t k, 
       const uint32_t blk = min(entry_block(v, lg), n_blocks - 1);
       insert_lds<K>(tile + blk * W, 1, k, 0, entry_h2(v, lg), lg);
     };
-    uint64_t e = e0 + threadIdx.x;
-    // four entries per thread in flight (a bucket can hold millions)
-    for (; e + 3ull * blockDim.x < e1; e += 4ull * blockDim.x) {
-      uint32_t v[4];
+    // eight entries per thread in flight (a bucket can hold millions); the
+    // last round's loads are clamped to the bucket's last entry rather than
+    // skipped, so that they too are issued together
+    constexpr int kFillBatch = 8;
+    for (uint64_t e = e0 + threadIdx.x; e < e1; e += static_cast<uint64_t>(kFillBatch) * blockDim.x) {
+      uint32_t v[kFillBatch];
 #pragma unroll
-      for (int q = 0; q < 4; q++) v[q] = entries[e + static_cast<uint64_t>(q) * blockDim.x];
+      for (int q = 0; q < kFillBatch; q++) {
+        const uint64_t i = e + static_cast<uint64_t>(q) * blockDim.x;
+        v[q] = entries[i < e1 ? i : e1 - 1];
+      }
 #pragma unroll
-      for (int q = 0; q < 4; q++) insert(v[q]);
+      for (int q = 0; q < kFillBatch; q++)
+        if (e + static_cast<uint64_t>(q) * blockDim.x < e1) insert(v[q]);
     }
-    for (; e < e1; e += blockDim.x) insert(entries[e]);
     __syncthreads();
     uint32_t *out = fs.f[f].words + static_cast<uint64_t>(first) * W;
     for (uint32_t j = threadIdx.x; j < n_blocks * W; j += blockDim.x) out[j] = tile[j];
