@@ -162,23 +162,46 @@ __global__ void __launch_bounds__(kWideThreads)
   if (!geo.ok) return;
   const uint32_t per = (n_groups + kWaves - 1) / kWaves;
   const uint32_t g0 = min(wv * per, n_groups), g1 = min(g0 + per, n_groups);
+  // A wave's first kRegGroups counters stay in registers between the sum
+  // and the rewrite (one round of loads, issued together: the addresses
+  // are clamped into the table, the values of lanes or groups outside it
+  // zeroed); groups beyond that (more than 16 x 16 workgroups) are read
+  // again.
+  constexpr uint32_t kRegGroups = 16;
   for (uint32_t b0 = blockIdx.x * kWave; b0 < geo.buckets; b0 += gridDim.x * kWave) {
     const uint32_t b = b0 + lane;
     const bool in = b < geo.buckets;
+    const uint32_t bc = in ? b : geo.buckets - 1;
+    uint32_t v[kRegGroups];
     uint64_t sum = 0;
-#pragma unroll 8
-    for (uint32_t g = g0; g < g1; g++) sum += in ? hist[static_cast<uint64_t>(g) * kMaxBuckets + b] : 0;
+    if (g1 > g0) {
+#pragma unroll
+      for (uint32_t j = 0; j < kRegGroups; j++) {
+        const uint32_t g = g0 + j;
+        const uint32_t x = hist[(g < g1 ? g : g1 - 1) * kMaxBuckets + bc];  // < 2^32: groups <= 2^18
+        v[j] = in && g < g1 ? x : 0;
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kRegGroups; j++) sum += v[j];
+      for (uint32_t g = g0 + kRegGroups; g < g1; g++) sum += in ? hist[static_cast<uint64_t>(g) * kMaxBuckets + b] : 0;
+    }
     s_part[wv][lane] = sum;
     __syncthreads();
     uint64_t run = 0;
     for (uint32_t w = 0; w < wv; w++) run += s_part[w][lane];
     if (wv == kWaves - 1 && in) totals[b] = run + sum;
-    for (uint32_t g = g0; g < g1; g++) {
-      if (in) {
+    if (in) {
+#pragma unroll
+      for (uint32_t j = 0; j < kRegGroups; j++) {
+        const uint32_t g = g0 + j;
+        if (g < g1) hist[g * kMaxBuckets + b] = static_cast<uint32_t>(run);
+        run += v[j];
+      }
+      for (uint32_t g = g0 + kRegGroups; g < g1; g++) {
         uint32_t *h = hist + static_cast<uint64_t>(g) * kMaxBuckets + b;
-        const uint32_t v = *h;
+        const uint32_t x = *h;
         *h = static_cast<uint32_t>(run);
-        run += v;
+        run += x;
       }
     }
     __syncthreads();
